@@ -1,0 +1,172 @@
+"""Benchmark of the PM kick-drift-kick hot path on one MI355X.
+
+A "step" is one KDK step of the whole path: CIC readout + kick + drift,
+counting sort by tile, LDS-tiled CIC paint, r2c FFT, fused Green/gradient
+x pass, inverse FFTs to three force meshes.  The timed region is one
+``pm_run`` over K steps (it includes the force at the first scale factor and
+the closing half kick) on 512^3 particles / 1024^3 mesh / 1024 Mpc/h, with
+the initial conditions already resident in HBM.
+
+Prints one JSON line.  Extra objects: ``roofline`` (dominant kernel class,
+algorithmic bytes / average event-timed duration vs 8 TB/s) and
+``cpu_baseline`` (the FP64 oracle timed on a bounded sample on this host).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_bytes(w, np3):
+    """Algorithmic HBM bytes per launch of each timed kernel class (float32).
+
+    Mesh field F = N^3 reals = N^2 (N/2) complex, plus the Nyquist plane of
+    N^2 complex values.  Particle state 24 B (x, p), id 4 B, key+rank 8 B.
+    """
+    n = w.n_mesh
+    real = 4.0 * n ** 3
+    spec = 4.0 * n ** 3 + 8.0 * n * n
+    return {
+        "fft_z_r2c": real + spec,                       # 1 field
+        "fft_y_fwd": 2 * spec,                          # 1 field, in place
+        "fft_x_fused": spec + 3 * spec,                 # read 1 spectrum, write 3
+        "fft_y_inv": 3 * 2 * spec,                      # 3 fields
+        "fft_z_c2r": 3 * (spec + real),                 # 3 fields
+        "paint": 12.0 * np3 + real,                     # positions in, mesh out
+        "readout_kdk": 3 * real + np3 * (24 + 4 + 24 + 8),  # 3 meshes + x,p,id in; x,p,key,rank out
+        "scatter": np3 * (8 + 28 + 28),                 # key+rank, state in, state out
+    }
+
+
+def cpu_baseline(seconds_hint=20.0):
+    """The oracle (FP64 NumPy, unmodified) on a bounded sample: the same
+    recipe (B = 2, 1 Mpc/h cells, no-wiggle P(k), 2LPT at a = 0.1) at
+    128^3 particles on a 256^3 mesh, 2 KDK steps; reported in
+    particle-steps/s."""
+    import numpy as np
+    from oracle import lpt, pm
+    from paper_2010_11847_amd import inputs
+    w = inputs.scaled(inputs.LARGE, 256, 128, n_steps=2)
+    x, p = lpt.generate(w)
+    t0 = time.perf_counter()
+    pm.kdk_run(x, p, w.a_list, w.n_mesh, w.n_particles, w.cosmo.omega_m)
+    dt = time.perf_counter() - t0
+    return {"value": w.n_particles * w.n_steps / dt, "unit": "particle-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{w.n_part}^3 particles on {w.n_mesh}^3 mesh, box {w.box_size:g} Mpc/h "
+                      f"(same B=2, 1 Mpc/h cell, no-wiggle P(k)), {w.n_steps} KDK steps incl. first force, "
+                      f"{dt:.1f} s wall, NumPy FFT single-threaded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="pm512_mesh1024_box1024")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-profile", action="store_true", help="skip the event-timed profile pass")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs one GPU only: the PM hot path here is the single-GPU share; "
+              "multi-GPU sharding is not built (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2010_11847_amd import inputs
+    from paper_2010_11847_amd.binding import PMContext
+
+    w = inputs.PRESETS[args.workload]
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    ctx = PMContext(w, device=dev)
+    np3 = w.n_particles
+
+    t0 = time.perf_counter()
+    pos0, mom0 = ctx.pm_init_lpt(w.seed, w.a_list[0])
+    torch.cuda.synchronize()
+    init_s = time.perf_counter() - t0
+    print(f"[bench] init_lpt {init_s * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    pos = torch.empty_like(pos0)
+    mom = torch.empty_like(mom0)
+
+    def run(nsteps):
+        a = inputs.a_linear(w.a_list[0], w.a_list[-1], nsteps)
+        pos.copy_(pos0)
+        mom.copy_(mom0)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        ctx.pm_run(a, pos, mom)
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / 1e3
+
+    for _ in range(max(0, args.warmup)):
+        run(max(1, args.steps))
+        print("[bench] warmup done", file=sys.stderr, flush=True)
+    t = run(args.steps)
+    print(f"[bench] timed {args.steps} steps: {t * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    value = np3 * args.steps / t
+
+    roofline = None
+    kernels = {}
+    if not args.no_profile:
+        ctx.pm_profile(True)
+        run(args.steps)
+        prof = ctx.pm_profile_read()
+        ctx.pm_profile(False)
+        nbytes = kernel_bytes(w, np3)
+        for name, (ms, cnt) in prof.items():
+            avg = ms / cnt
+            ent = {"total_ms": round(ms, 3), "launches": cnt, "avg_ms": round(avg, 4)}
+            if name in nbytes:
+                ent["GBps"] = round(nbytes[name] / (avg / 1e3) / 1e9, 1)
+            kernels[name] = ent
+        dom = max((k for k in kernels if k in nbytes), key=lambda k: kernels[k]["total_ms"])
+        ach = kernels[dom]["GBps"]
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                    "bytes_per_launch": nbytes[dom], "avg_launch_ms": kernels[dom]["avg_ms"]}
+        print(f"[bench] kernels {json.dumps(kernels)}", file=sys.stderr, flush=True)
+
+    base = None
+    if not args.no_cpu:
+        base = cpu_baseline()
+
+    out = {
+        "metric": "particle-steps/s (PM KDK) at 512^3/1024^3",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_part": w.n_part, "n_mesh": w.n_mesh, "box_mpc_h": w.box_size,
+                   "seed": w.seed, "a0": w.a_list[0], "a1": w.a_list[-1], "lpt_order": w.lpt_order,
+                   "pk": "eisenstein_hu_nowiggle", "init_lpt_ms": round(init_s * 1e3, 1)},
+        "roofline": roofline,
+        "cpu_baseline": base,
+        "kernels": kernels,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,215 @@
+/*
+ * pm.h - C ABI of the MI355X particle-mesh (PM) N-body library.
+ *
+ * The library evolves dark-matter particles with the FastPM kick-drift-kick
+ * scheme described in section 2 of Modi, Lanusse & Seljak (arXiv:2010.11847):
+ * cloud-in-cell (CIC) painting of the particles to a periodic mesh, a real
+ * 3D FFT, the finite-difference (FD) Green's function and gradient kernels,
+ * three inverse FFTs to force meshes, CIC readout at the particles, and
+ * growth-factor weighted kick and drift updates.  Initial conditions follow
+ * the Gen-IC algorithm of section 6 (Gaussian field scaled by P(k), then
+ * first- or second-order Lagrangian displacements).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All functions are extern "C" and return an int status: PM_OK (0) or a
+ *    negative PM_E* code.  Nothing throws across the ABI.
+ *  - Pointers named d_* are device pointers (HBM of the GPU the context was
+ *    created on); pointers named h_* are host pointers.  Every array is owned
+ *    by the caller.  The library never allocates device memory: its scratch
+ *    lives in the workspace handed to pm_create.
+ *  - Particle arrays are float32, array-of-structures [n][3] (x, y, z).
+ *    Positions and momenta are in mesh-cell units: the box is [0, n_mesh)^3,
+ *    H0 = 1, a (scale factor) is the time variable.  Momentum is
+ *    p = a^3 E(a) dx/da.  To convert: position in Mpc/h = x * box/n_mesh.
+ *  - Meshes are float32, C order [x][y][z], n_mesh^3 elements.
+ *  - Work is enqueued asynchronously on the context's stream (a hipStream_t
+ *    passed as void*).  Kernel errors raised asynchronously surface as
+ *    PM_EHIP at the next call that synchronises (pm_sync, pm_power, ...).
+ *  - A context is not thread-safe.  Separate contexts on separate streams
+ *    with separate workspaces are independent.
+ *  - Particle lattice: particle index i = (ix*Np + iy)*Np + iz sits at
+ *    q = B*(ix, iy, iz) + lattice_shift with B = n_mesh / n_part.
+ */
+#ifndef PM_H
+#define PM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define PM_OK       0
+#define PM_EINVAL  (-1)   /* invalid argument or configuration */
+#define PM_ENOMEM  (-2)   /* workspace smaller than pm_workspace_bytes() */
+#define PM_EHIP    (-3)   /* HIP runtime error (text in pm_last_error) */
+#define PM_ESTATE  (-4)   /* call not valid in the context's current state */
+
+/* ---- linear power spectrum kinds --------------------------------------- */
+#define PM_PK_POWERLAW     0  /* P(k) = A k^pk_index */
+#define PM_PK_EH_NOWIGGLE  1  /* Eisenstein & Hu (1998) no-wiggle, A k^n_s T0(k)^2 */
+#define PM_PK_TABLE        2  /* caller's table, log-log interpolated */
+
+/* ---- optional long/short force split (Fourier filter S = exp(-k^2 rs^2)) */
+#define PM_SPLIT_NONE   0     /* full force */
+#define PM_SPLIT_LONG   1     /* long-range part  S(k) * F */
+#define PM_SPLIT_SHORT  2     /* short-range part (1 - S(k)) * F */
+
+typedef struct {
+    double omega_m;    /* matter density today; flat, Omega_L = 1 - omega_m */
+    double omega_b;    /* baryons (no-wiggle transfer function only) */
+    double h;          /* H0 / (100 km/s/Mpc) (transfer function only) */
+    double n_s;        /* primordial tilt (no-wiggle only) */
+    double sigma8;     /* rms linear overdensity in 8 Mpc/h spheres at a = 1 */
+    double t_cmb;      /* CMB temperature in K (no-wiggle only) */
+    int    pk_kind;    /* PM_PK_* */
+    double pk_amp;     /* A; 0 = normalise to sigma8 (POWERLAW, EH_NOWIGGLE) */
+    double pk_index;   /* power-law index (POWERLAW) */
+    const double *pk_k, *pk_p;  /* TABLE: host arrays (h/Mpc, (Mpc/h)^3), copied by pm_create */
+    int    pk_n;       /* TABLE: number of points (>= 2, k increasing) */
+} pm_cosmo;
+
+typedef struct {
+    double   box_size;      /* comoving box side in Mpc/h (> 0) */
+    int      n_mesh;        /* mesh cells per side: power of 2 in [8, 1024] */
+    int      n_part;        /* particles per side of the lattice; n_mesh % n_part == 0,
+                               n_part a power of 2 >= 8 */
+    pm_cosmo cosmo;
+    int      lpt_order;     /* 1 (Zel'dovich) or 2 (default in the presets) */
+    int      deconv_order;  /* 0, 1 or 2: force divided by W_CIC(k)^deconv_order */
+    double   split_rs;      /* split radius in mesh cells (used if split_mode != NONE) */
+    int      split_mode;    /* PM_SPLIT_* */
+    double   lattice_shift; /* offset of the particle lattice from mesh nodes, cells, [0, 1) */
+    int64_t  max_particles; /* capacity for pm_paint/pm_force/pm_kdk_step; 0 = n_part^3 */
+} pm_config;
+
+typedef struct pm_ctx pm_ctx;   /* opaque; host memory only */
+
+/* Bytes of device workspace pm_create needs for this configuration, or 0 if
+ * the configuration is invalid.  Deterministic in the configuration. */
+size_t pm_workspace_bytes(const pm_config* cfg);
+
+/* Validate cfg, lay out the workspace and upload the static tables (FFT
+ * twiddles, FD kernel tables, the sqrt(P(k)/V) table of the lattice) with the
+ * given stream.  d_workspace must stay valid until pm_destroy; it must be
+ * 256-byte aligned.  Computes every time-independent quantity on the host in
+ * float64.  Returns PM_EINVAL (bad cfg), PM_ENOMEM (bytes too small) or PM_EHIP. */
+int pm_create(const pm_config* cfg, void* d_workspace, size_t bytes, void* stream,
+              pm_ctx** out);
+
+/* Free the host-side context (never the workspace).  NULL is allowed. */
+int pm_destroy(pm_ctx* ctx);
+
+/* Change the stream used by later calls. */
+int pm_set_stream(pm_ctx* ctx, void* stream);
+
+/* Wait for the context's stream; reports asynchronous kernel errors. */
+int pm_sync(pm_ctx* ctx);
+
+const char* pm_strerror(int status);
+const char* pm_last_error(const pm_ctx* ctx);
+
+/* Growth and time-step factors computed by the library (float64, host):
+ * out[0..5] = D1, f1, D2, f2, E, G_f at scale factor a (D1(1) = 1). */
+int pm_growth(const pm_ctx* ctx, double a, double* h_out6);
+
+/* Gen-IC step 1 (section 6): unit white noise on the n_part^3 lattice from the
+ * counter-based generator (SplitMix64 output of seed*2^40 + site, Box-Muller,
+ * cosine branch).  d_noise: [n_part^3] float32. */
+int pm_noise(pm_ctx* ctx, uint64_t seed, float* d_noise);
+
+/* Gen-IC (section 6): white noise -> linear field delta_L(k) =
+ * DFT(w) sqrt(P(k)/V_cell) -> LPT displacements with the FD kernels of
+ * section 2 on the lattice -> particle positions and momenta at scale factor
+ * a0.  d_noise_in: [n_part^3] noise to use, or NULL to draw it from seed;
+ * d_noise_out: NULL or [n_part^3] receives the noise used.  d_pos, d_mom:
+ * [n_part^3][3] outputs in lattice (particle index) order. */
+int pm_init_lpt(pm_ctx* ctx, uint64_t seed, double a0, const float* d_noise_in,
+                float* d_noise_out, float* d_pos, float* d_mom);
+
+/* CIC paint (section 2): delta(c) = rho(c) * n_mesh^3 / np - 1 with
+ * rho(c) = sum_p prod_d max(0, 1 - |x_pd - c_d|) (periodic).  Implemented as a
+ * counting sort of the particles by tile followed by LDS-tiled accumulation
+ * (no global float atomics).  d_pos: [np][3] in [0, n_mesh); np in
+ * [1, max_particles].  d_delta: [n_mesh^3] output. */
+int pm_paint(pm_ctx* ctx, const float* d_pos, int64_t np, float* d_delta);
+
+/* PM force at the particles (section 2, force equation and FD kernels):
+ * F = 1.5 Omega_m * IDFT[i D(w)/K^2(w) W^-deconv S DFT(delta)] read out with
+ * CIC, where K^2 = sum_d (2 sin(w_d/2))^2 and D(w) = (8 sin w - sin 2w)/6.
+ * d_pos: [np][3]; d_force: [np][3] output, same particle order. */
+int pm_force(pm_ctx* ctx, const float* d_pos, int64_t np, float* d_force);
+
+/* One kick-drift-kick step from a0 to a1 (section 2, drift/kick equations,
+ * FastPM factors): p += F K(a0->ac; a0); x += p D(a0->a1; ac) (wrapped);
+ * F = force(x); p += F K(ac->a1; a1), ac = sqrt(a0 a1).  d_force holds F(x)
+ * at a0 on entry and F at a1 on exit.  All arrays [np][3], np = n_part^3. */
+int pm_kdk_step(pm_ctx* ctx, float* d_pos, float* d_mom, float* d_force,
+                double a0, double a1);
+
+/* Full run: force at a[0], then n_a - 1 KDK steps through the host array
+ * h_a (strictly increasing, > 0).  Kicks between steps are merged.
+ * d_pos, d_mom: [n_part^3][3] in/out, lattice order.  d_ckpt: NULL or
+ * [n_a][2][n_part^3][3] receives (x, p) at every a[i] (the adjoint's
+ * checkpoints).  d_delta_final: NULL or [n_mesh^3] receives the overdensity
+ * painted from the final positions. */
+int pm_run(pm_ctx* ctx, const double* h_a, int n_a, float* d_pos, float* d_mom,
+           float* d_ckpt, float* d_delta_final);
+
+/* Adjoint of pm_init_lpt + pm_run (reverse-mode derivative; the paper
+ * differentiates the simulation with respect to the initial field, section 7).
+ * h_a, n_a: the scale factors of the forward pm_run.  d_ckpt: the
+ * [n_a][2][n_part^3][3] checkpoints it wrote; positions x_i are re-read at
+ * every force evaluation point and the force meshes recomputed (no force
+ * meshes are stored).  d_grad_delta_final: NULL or [n_mesh^3], the cotangent
+ * of the final overdensity.  d_grad_pos, d_grad_mom: [n_part^3][3], on entry
+ * the cotangents of the final positions and momenta (zeros if the loss only
+ * sees the density), on exit those of the initial ones (lattice order).
+ * d_grad_noise: NULL, or [n_part^3] receives the cotangent of the white
+ * noise d_noise ([n_part^3], the noise the forward run started from) through
+ * the LPT initial conditions.  The CIC weights are differentiated piecewise
+ * (one-sided at cell faces).  Uses the workspace only. */
+int pm_run_adjoint(pm_ctx* ctx, const double* h_a, int n_a, const float* d_ckpt, const float* d_noise,
+                   const float* d_grad_delta_final, float* d_grad_pos, float* d_grad_mom,
+                   float* d_grad_noise);
+
+/* Binned power spectrum of a real mesh (section 5.1 two-point statistics):
+ * P(k_j) = (L^3/N^6) sum_w |delta^|^2 / sum_w, mode weight 2 on interior
+ * n_z planes and 1 on n_z = 0 and N/2, bins |n| in [j-1/2, j+1/2),
+ * j = 1..n_bins (n_bins <= n_mesh/2).  Only modes with every |n_d| < n_max
+ * count when n_max > 0.  deconv: divide delta^ by the CIC window.  The mesh
+ * at d_delta is left unchanged.  Synchronises; host outputs of n_bins
+ * entries: h_k (mode-weighted mean k, h/Mpc), h_pk ((Mpc/h)^3), h_nmodes. */
+int pm_power(pm_ctx* ctx, const float* d_delta, int n_bins, int n_max, int deconv,
+             double* h_k, double* h_pk, double* h_nmodes);
+
+/* 3D real FFT of a mesh (the transform of section 3, one pass per axis):
+ * d_spec[kx][ky][kz] = sum_x d_real[x] exp(-2 pi i k.x / n_mesh),
+ * kz = 0..n_mesh/2, complex64 interleaved (re, im), i.e. numpy's rfftn
+ * layout [n][n][n/2+1].  d_real is left unchanged. */
+int pm_rfft(pm_ctx* ctx, const float* d_real, float* d_spec);
+
+/* Inverse of pm_rfft, normalised by 1/n_mesh^3 like numpy's irfftn: the
+ * imaginary parts of the kz = 0 and kz = n/2 planes after the x and y
+ * inverse transforms are ignored. d_spec is left unchanged. */
+int pm_irfft(pm_ctx* ctx, const float* d_spec, float* d_real);
+
+/* Optional per-kernel-class timing with HIP events recorded on the
+ * context's stream around every kernel the library enqueues (measurement
+ * support; adds two event records per launch while enabled).
+ * pm_profile(ctx, 1) clears and starts collecting, pm_profile(ctx, 0) stops. */
+int pm_profile(pm_ctx* ctx, int enable);
+
+/* Synchronises, then fills up to max entries: h_names (32 bytes each,
+ * NUL-terminated class name), h_total_ms (summed event time), h_count
+ * (launches).  Returns the number of classes seen, or a negative status. */
+int pm_profile_read(pm_ctx* ctx, int max, char* h_names, double* h_total_ms, int* h_count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PM_H */

@@ -1,0 +1,230 @@
+"""Thin Python binding of the C ABI (include/pm.h) on torch device memory.
+
+Only argument marshalling lives here: tensors are checked for device, dtype,
+shape and contiguity and their pointers passed to libpm.so together with the
+current HIP stream.  Every step of the computation runs in the library's
+kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from .inputs import Workload
+
+
+class PMError(RuntimeError):
+    pass
+
+
+def make_config(w: Workload, max_particles: int = 0) -> _lib.pm_config:
+    c = w.cosmo
+    cos = _lib.pm_cosmo(c.omega_m, c.omega_b, c.h, c.n_s, c.sigma8, c.t_cmb, c.pk_kind,
+                        c.pk_amp, c.pk_index, None, None, 0)
+    return _lib.pm_config(w.box_size, w.n_mesh, w.n_part, cos, w.lpt_order, w.deconv_order,
+                          w.split_rs, w.split_mode, w.lattice_shift, max_particles)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class PMContext:
+    """A library context with its device workspace, bound to one GPU stream."""
+
+    def __init__(self, workload: Workload, device="cuda", max_particles: int = 0, stream=None):
+        self.lib = _lib.load()
+        self.workload = workload
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self.cfg = make_config(workload, max_particles)
+        nbytes = self.lib.pm_workspace_bytes(C.byref(self.cfg))
+        if nbytes == 0:
+            raise PMError(f"invalid configuration for {workload.name}")
+        self.workspace_bytes = int(nbytes)
+        self.ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ctx = C.c_void_p()
+        rc = self.lib.pm_create(C.byref(self.cfg), C.c_void_p(self._ws_ptr), self.workspace_bytes,
+                                C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
+        self._check(rc, "pm_create", ctx=None)
+        self.ctx = ctx
+        self.np3 = workload.n_part ** 3
+
+    # ---- helpers -------------------------------------------------------------
+    def _check(self, rc, what, ctx="self"):
+        if rc != _lib.PM_OK:
+            msg = self.lib.pm_strerror(rc).decode()
+            if ctx == "self" and getattr(self, "ctx", None):
+                msg += ": " + self.lib.pm_last_error(self.ctx).decode()
+            raise PMError(f"{what} failed ({rc}): {msg}")
+
+    def _dev(self, t: torch.Tensor, shape=None, dtype=torch.float32, name="array"):
+        if not isinstance(t, torch.Tensor) or t.device != self.device or t.dtype != dtype:
+            raise PMError(f"{name} must be a {dtype} tensor on {self.device}")
+        if not t.is_contiguous():
+            raise PMError(f"{name} must be contiguous")
+        if shape is not None and tuple(t.shape) != tuple(shape):
+            raise PMError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+        return t
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.pm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        self.stream = stream
+        self._check(self.lib.pm_set_stream(self.ctx, C.c_void_p(stream.cuda_stream)), "pm_set_stream")
+
+    # ---- entry points (same names as the C ABI) --------------------------------
+    def pm_sync(self):
+        self._check(self.lib.pm_sync(self.ctx), "pm_sync")
+
+    def pm_growth(self, a: float):
+        out = (C.c_double * 6)()
+        self._check(self.lib.pm_growth(self.ctx, a, out), "pm_growth")
+        return dict(zip(("D1", "f1", "D2", "f2", "E", "Gf"), list(out)))
+
+    def pm_noise(self, seed: int, out: Optional[torch.Tensor] = None):
+        n = self.workload.n_part
+        out = torch.empty((n, n, n), dtype=torch.float32, device=self.device) if out is None else out
+        self._dev(out, (n, n, n), name="noise")
+        self._check(self.lib.pm_noise(self.ctx, seed, _ptr(out)), "pm_noise")
+        return out
+
+    def pm_init_lpt(self, seed: int, a0: float, noise: Optional[torch.Tensor] = None,
+                    noise_out: Optional[torch.Tensor] = None, pos=None, mom=None):
+        n = self.workload.n_part
+        pos = torch.empty((self.np3, 3), dtype=torch.float32, device=self.device) if pos is None else pos
+        mom = torch.empty((self.np3, 3), dtype=torch.float32, device=self.device) if mom is None else mom
+        self._dev(pos, (self.np3, 3), name="pos")
+        self._dev(mom, (self.np3, 3), name="mom")
+        if noise is not None:
+            self._dev(noise, (n, n, n), name="noise")
+        if noise_out is not None:
+            self._dev(noise_out, (n, n, n), name="noise_out")
+        self._check(self.lib.pm_init_lpt(self.ctx, seed, a0, _ptr(noise), _ptr(noise_out), _ptr(pos), _ptr(mom)),
+                    "pm_init_lpt")
+        return pos, mom
+
+    def pm_paint(self, pos: torch.Tensor, out: Optional[torch.Tensor] = None):
+        n = self.workload.n_mesh
+        self._dev(pos, name="pos")
+        if pos.ndim != 2 or pos.shape[1] != 3:
+            raise PMError("pos must have shape (np, 3)")
+        out = torch.empty((n, n, n), dtype=torch.float32, device=self.device) if out is None else out
+        self._dev(out, (n, n, n), name="delta")
+        self._check(self.lib.pm_paint(self.ctx, _ptr(pos), pos.shape[0], _ptr(out)), "pm_paint")
+        return out
+
+    def pm_force(self, pos: torch.Tensor, out: Optional[torch.Tensor] = None):
+        self._dev(pos, name="pos")
+        if pos.ndim != 2 or pos.shape[1] != 3:
+            raise PMError("pos must have shape (np, 3)")
+        out = torch.empty_like(pos) if out is None else out
+        self._dev(out, tuple(pos.shape), name="force")
+        self._check(self.lib.pm_force(self.ctx, _ptr(pos), pos.shape[0], _ptr(out)), "pm_force")
+        return out
+
+    def pm_kdk_step(self, pos, mom, force, a0: float, a1: float):
+        for t, nm in ((pos, "pos"), (mom, "mom"), (force, "force")):
+            self._dev(t, (self.np3, 3), name=nm)
+        self._check(self.lib.pm_kdk_step(self.ctx, _ptr(pos), _ptr(mom), _ptr(force), a0, a1), "pm_kdk_step")
+        return pos, mom, force
+
+    def pm_run(self, a_list: Sequence[float], pos, mom, ckpt: Optional[torch.Tensor] = None,
+               delta_final: Optional[torch.Tensor] = None):
+        self._dev(pos, (self.np3, 3), name="pos")
+        self._dev(mom, (self.np3, 3), name="mom")
+        a = np.ascontiguousarray(a_list, dtype=np.float64)
+        if ckpt is not None:
+            self._dev(ckpt, (len(a), 2, self.np3, 3), name="ckpt")
+        if delta_final is not None:
+            n = self.workload.n_mesh
+            self._dev(delta_final, (n, n, n), name="delta_final")
+        ap = a.ctypes.data_as(C.POINTER(C.c_double))
+        self._check(self.lib.pm_run(self.ctx, ap, len(a), _ptr(pos), _ptr(mom), _ptr(ckpt), _ptr(delta_final)),
+                    "pm_run")
+        return pos, mom
+
+    def pm_power(self, delta: torch.Tensor, n_bins: Optional[int] = None, n_max: int = 0, deconv: bool = False):
+        n = self.workload.n_mesh
+        self._dev(delta, (n, n, n), name="delta")
+        nb = n // 2 if n_bins is None else n_bins
+        k = (C.c_double * nb)()
+        p = (C.c_double * nb)()
+        m = (C.c_double * nb)()
+        self._check(self.lib.pm_power(self.ctx, _ptr(delta), nb, n_max, int(deconv), k, p, m), "pm_power")
+        return np.array(k), np.array(p), np.array(m)
+
+    def pm_rfft(self, real: torch.Tensor):
+        n = self.workload.n_mesh
+        self._dev(real, (n, n, n), name="real")
+        spec = torch.empty((n, n, n // 2 + 1), dtype=torch.complex64, device=self.device)
+        self._check(self.lib.pm_rfft(self.ctx, _ptr(real), _ptr(spec)), "pm_rfft")
+        return spec
+
+    def pm_irfft(self, spec: torch.Tensor):
+        n = self.workload.n_mesh
+        self._dev(spec, (n, n, n // 2 + 1), dtype=torch.complex64, name="spec")
+        real = torch.empty((n, n, n), dtype=torch.float32, device=self.device)
+        self._check(self.lib.pm_irfft(self.ctx, _ptr(spec), _ptr(real)), "pm_irfft")
+        return real
+
+    def pm_profile(self, enable: bool):
+        self._check(self.lib.pm_profile(self.ctx, int(enable)), "pm_profile")
+
+    def pm_profile_read(self):
+        """{class name: (total ms, launches)} of the kernels timed since pm_profile(True)."""
+        mx = 64
+        names = C.create_string_buffer(32 * mx)
+        ms = (C.c_double * mx)()
+        cnt = (C.c_int * mx)()
+        k = self.lib.pm_profile_read(self.ctx, mx, names, ms, cnt)
+        if k < 0:
+            self._check(k, "pm_profile_read")
+        out = {}
+        for i in range(min(k, mx)):
+            nm = names.raw[32 * i:32 * (i + 1)].split(b"\0", 1)[0].decode()
+            out[nm] = (ms[i], cnt[i])
+        return out
+
+    def pm_run_adjoint(self, a_list, ckpt, noise=None, grad_delta=None, grad_pos=None, grad_mom=None,
+                       want_noise_grad=True):
+        """Cotangents of (x0, p0) and of the white noise for a loss on the final
+        overdensity (grad_delta) and/or final state (grad_pos/grad_mom)."""
+        a = np.ascontiguousarray(a_list, dtype=np.float64)
+        n = self.workload.n_part
+        self._dev(ckpt, (len(a), 2, self.np3, 3), name="ckpt")
+        gx = torch.zeros((self.np3, 3), dtype=torch.float32, device=self.device) if grad_pos is None else grad_pos
+        gp = torch.zeros((self.np3, 3), dtype=torch.float32, device=self.device) if grad_mom is None else grad_mom
+        self._dev(gx, (self.np3, 3), name="grad_pos")
+        self._dev(gp, (self.np3, 3), name="grad_mom")
+        if grad_delta is not None:
+            m = self.workload.n_mesh
+            self._dev(grad_delta, (m, m, m), name="grad_delta")
+        gn = None
+        if want_noise_grad:
+            if noise is None:
+                raise PMError("the noise gradient needs the forward noise")
+            self._dev(noise, (n, n, n), name="noise")
+            gn = torch.empty((n, n, n), dtype=torch.float32, device=self.device)
+        ap = a.ctypes.data_as(C.POINTER(C.c_double))
+        self._check(self.lib.pm_run_adjoint(self.ctx, ap, len(a), _ptr(ckpt), _ptr(noise), _ptr(grad_delta),
+                                            _ptr(gx), _ptr(gp), _ptr(gn)), "pm_run_adjoint")
+        return gx, gp, gn

@@ -1,0 +1,237 @@
+// Adjoint (reverse-mode) kernels of the PM run for gfx950.
+//
+// The reverse sweep needs, at every force evaluation point x_j, the
+// vector-Jacobian product of F(x) = readout(G paint(x), x) with a force
+// cotangent F_bar = p_bar K (K the sum of the kicks that used F(x_j)):
+//   term A  the readout positions: x_bar += sum_c dW/dx (F_bar . M(c)),
+//           M the three force meshes recomputed from x_j;
+//   term B  the painting positions: R_d = paint(x, F_bar_d) (3 channels),
+//           delta_bar = sum_d G_d^T R_d (G_d^T = -G_d, the FD kernel is odd),
+//           x_bar += sum_c dW/dx (s delta_bar(c)), s = Ng^3 / Np.
+// Both use the tile-sorted particles and LDS tiles like the forward paint and
+// readout; cotangents live in particle-index order and are gathered and
+// scattered through the sorted ids (each particle is owned by one thread).
+#include "particles.h"
+#include "pm_device.h"
+
+namespace pmk {
+namespace {
+
+constexpr int kThreads = 256;
+
+// 3-channel CIC paint with per-particle weights w_d = pbar[id][d] * k.
+__global__ __launch_bounds__(kThreads) void k_paint3w(const float* __restrict__ pos, const uint32_t* __restrict__ id,
+                                                      const uint32_t* __restrict__ off, TileGeom g,
+                                                      const float* __restrict__ pbar, float k, float* __restrict__ o0,
+                                                      float* __restrict__ o1, float* __restrict__ o2) {
+  __shared__ float acc[3][kTileMax * kTileMax * kTileMax];
+  const int T = g.t, nt = g.nt, n = g.n;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tz = tile % nt, ty = (tile / nt) % nt, tx = tile / (nt * nt);
+  const int ox = tx * T, oy = ty * T, oz = tz * T;
+  const int cells = T * T * T;
+  for (int c = threadIdx.x; c < cells; c += kThreads) acc[0][c] = acc[1][c] = acc[2][c] = 0.f;
+  __syncthreads();
+  for (int e = 0; e < 8; ++e) {
+    const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
+    const int sx = (tx - ex + nt) % nt, sy = (ty - ey + nt) % nt, sz = (tz - ez + nt) % nt;
+    const uint32_t src = ((uint32_t)sx * nt + sy) * nt + sz;
+    for (int cls = 0; cls < 8; ++cls) {
+      if ((cls & e) != e) continue;
+      const uint32_t b0 = off[src * 8 + cls], b1 = off[src * 8 + cls + 1];
+      for (uint32_t j = b0 + threadIdx.x; j < b1; j += kThreads) {
+        int ix, iy, iz;
+        float fx, fy, fz;
+        cic_base(pos[3 * (long)j + 0], n, ix, fx);
+        cic_base(pos[3 * (long)j + 1], n, iy, fy);
+        cic_base(pos[3 * (long)j + 2], n, iz, fz);
+        int lx = (ix - ox) & (n - 1), ly = (iy - oy) & (n - 1), lz = (iz - oz) & (n - 1);
+        if (lx > T) lx -= n;
+        if (ly > T) ly -= n;
+        if (lz > T) lz -= n;
+        const long p = (long)id[j];
+        const float m0 = pbar[3 * p + 0] * k, m1 = pbar[3 * p + 1] * k, m2 = pbar[3 * p + 2] * k;
+        const float wx[2] = {1.f - fx, fx}, wy[2] = {1.f - fy, fy}, wz[2] = {1.f - fz, fz};
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          const int cx = lx + a;
+          if (cx < 0 || cx >= T) continue;
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            const int cy = ly + b;
+            if (cy < 0 || cy >= T) continue;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+              const int cz = lz + c;
+              if (cz < 0 || cz >= T) continue;
+              const float w = wx[a] * wy[b] * wz[c];
+              const int li = (cx * T + cy) * T + cz;
+              atomicAdd(&acc[0][li], w * m0);
+              atomicAdd(&acc[1][li], w * m1);
+              atomicAdd(&acc[2][li], w * m2);
+            }
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < cells; c += kThreads) {
+    const int cz = c % T, cy = (c / T) % T, cx = c / (T * T);
+    const long gi = ((long)(ox + cx) * n + (oy + cy)) * n + (oz + cz);
+    o0[gi] = acc[0][c];
+    o1[gi] = acc[1][c];
+    o2[gi] = acc[2][c];
+  }
+}
+
+// x_bar[id] += sum_corners dW/dx * V(c) where
+//   NCH = 3: V(c) = sum_d pbar[id][d] k M_d(c)
+//   NCH = 1: V(c) = k M_0(c)
+template <int NCH>
+__global__ __launch_bounds__(kThreads) void k_readout_grad(const float* __restrict__ pos,
+                                                           const uint32_t* __restrict__ id,
+                                                           const uint32_t* __restrict__ off, TileGeom g,
+                                                           const float* __restrict__ m0, const float* __restrict__ m1,
+                                                           const float* __restrict__ m2, const float* __restrict__ pbar,
+                                                           float k, float* __restrict__ xbar) {
+  using V = typename std::conditional<NCH == 3, float4, float>::type;
+  __shared__ V ft[(kTileMax + 1) * (kTileMax + 1) * (kTileMax + 1)];
+  const int T = g.t, nt = g.nt, n = g.n, T1 = T + 1;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const uint32_t b0 = off[tile * 8], b1 = off[tile * 8 + 8];
+  if (b0 == b1) return;
+  const int tz = tile % nt, ty = (tile / nt) % nt, tx = tile / (nt * nt);
+  const int ox = tx * T, oy = ty * T, oz = tz * T;
+  for (int c = threadIdx.x; c < T1 * T1 * T1; c += kThreads) {
+    const int cz = c % T1, cy = (c / T1) % T1, cx = c / (T1 * T1);
+    const long gi = ((long)((ox + cx) & (n - 1)) * n + ((oy + cy) & (n - 1))) * n + ((oz + cz) & (n - 1));
+    if constexpr (NCH == 3)
+      ft[c] = make_float4(m0[gi], m1[gi], m2[gi], 0.f);
+    else
+      ft[c] = m0[gi];
+  }
+  __syncthreads();
+  for (uint32_t j = b0 + threadIdx.x; j < b1; j += kThreads) {
+    int ix, iy, iz;
+    float fx, fy, fz;
+    cic_base(pos[3 * (long)j + 0], n, ix, fx);
+    cic_base(pos[3 * (long)j + 1], n, iy, fy);
+    cic_base(pos[3 * (long)j + 2], n, iz, fz);
+    const int lx = (ix - ox) & (n - 1), ly = (iy - oy) & (n - 1), lz = (iz - oz) & (n - 1);
+    const long p = (long)id[j];
+    float c0 = k, c1 = 0.f, c2 = 0.f;
+    if constexpr (NCH == 3) {
+      c0 = pbar[3 * p + 0] * k;
+      c1 = pbar[3 * p + 1] * k;
+      c2 = pbar[3 * p + 2] * k;
+    }
+    const float wx[2] = {1.f - fx, fx}, wy[2] = {1.f - fy, fy}, wz[2] = {1.f - fz, fz};
+    float gx = 0.f, gy = 0.f, gz = 0.f;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const V v = ft[((lx + a) * T1 + (ly + b)) * T1 + (lz + c)];
+          float val;
+          if constexpr (NCH == 3)
+            val = c0 * v.x + c1 * v.y + c2 * v.z;
+          else
+            val = c0 * v;
+          const float sa = a ? 1.f : -1.f, sb = b ? 1.f : -1.f, sc = c ? 1.f : -1.f;
+          gx += sa * wy[b] * wz[c] * val;
+          gy += wx[a] * sb * wz[c] * val;
+          gz += wx[a] * wy[b] * sc * val;
+        }
+    xbar[3 * p + 0] += gx;
+    xbar[3 * p + 1] += gy;
+    xbar[3 * p + 2] += gz;
+  }
+}
+
+// y += a x  (n floats)
+__global__ void k_axpy(float* __restrict__ y, const float* __restrict__ x, float a, long n) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) y[i] += a * x[i];
+}
+
+// LPT: s1_bar_d = cx1 xbar_d + cp1 pbar_d, s2_bar_d = cx2 xbar_d + cp2 pbar_d
+// (particle index = lattice site, AoS [np3][3] -> three lattice fields each)
+__global__ void k_lpt_sbar(const float* __restrict__ xbar, const float* __restrict__ pbar, long n3, float cx1,
+                           float cp1, float cx2, float cp2, float* __restrict__ s10, float* __restrict__ s11,
+                           float* __restrict__ s12, float* __restrict__ s20, float* __restrict__ s21,
+                           float* __restrict__ s22) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n3; i += stride) {
+    const float x0 = xbar[3 * i], x1 = xbar[3 * i + 1], x2 = xbar[3 * i + 2];
+    const float p0 = pbar[3 * i], p1 = pbar[3 * i + 1], p2 = pbar[3 * i + 2];
+    s10[i] = cx1 * x0 + cp1 * p0;
+    s11[i] = cx1 * x1 + cp1 * p1;
+    s12[i] = cx1 * x2 + cp1 * p2;
+    s20[i] = cx2 * x0 + cp2 * p0;
+    s21[i] = cx2 * x1 + cp2 * p1;
+    s22[i] = cx2 * x2 + cp2 * p2;
+  }
+}
+
+// phi (xx, yy, zz, xy, xz, yz) -> phi_bar in place, given delta2_bar:
+// phi_bar_ii = d2b (phi_jj + phi_kk), phi_bar_ij = -2 d2b phi_ij
+__global__ void k_lpt_phibar(float* __restrict__ xx, float* __restrict__ yy, float* __restrict__ zz,
+                             float* __restrict__ xy, float* __restrict__ xz, float* __restrict__ yz,
+                             const float* __restrict__ d2b, long n3) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n3; i += stride) {
+    const float a = xx[i], b = yy[i], c = zz[i], d = d2b[i];
+    xx[i] = d * (b + c);
+    yy[i] = d * (a + c);
+    zz[i] = d * (a + b);
+    xy[i] = -2.f * d * xy[i];
+    xz[i] = -2.f * d * xz[i];
+    yz[i] = -2.f * d * yz[i];
+  }
+}
+
+inline int grid_for(long n) {
+  long g = (n + kThreads - 1) / kThreads;
+  if (g < 1) g = 1;
+  return (int)(g > 65536 ? 65536 : g);
+}
+
+}  // namespace
+
+void launch_paint3w(const float* pos, const uint32_t* id, const uint32_t* off, const TileGeom& g, const float* pbar,
+                    float k, float* o0, float* o1, float* o2, hipStream_t s) {
+  hipLaunchKernelGGL(k_paint3w, dim3(g.ntiles), dim3(kThreads), 0, s, pos, id, off, g, pbar, k, o0, o1, o2);
+}
+
+void launch_readout_grad3(const float* pos, const uint32_t* id, const uint32_t* off, const TileGeom& g,
+                          const float* m0, const float* m1, const float* m2, const float* pbar, float k, float* xbar,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_readout_grad<3>, dim3(g.ntiles), dim3(kThreads), 0, s, pos, id, off, g, m0, m1, m2, pbar, k,
+                     xbar);
+}
+
+void launch_readout_grad1(const float* pos, const uint32_t* id, const uint32_t* off, const TileGeom& g,
+                          const float* m0, float k, float* xbar, hipStream_t s) {
+  hipLaunchKernelGGL(k_readout_grad<1>, dim3(g.ntiles), dim3(kThreads), 0, s, pos, id, off, g, m0, m0, m0,
+                     (const float*)nullptr, k, xbar);
+}
+
+void launch_axpy(float* y, const float* x, float a, long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy, dim3(grid_for(n)), dim3(kThreads), 0, s, y, x, a, n);
+}
+
+void launch_lpt_sbar(const float* xbar, const float* pbar, long n3, float cx1, float cp1, float cx2, float cp2,
+                     float* const* s1, float* const* s2, hipStream_t s) {
+  hipLaunchKernelGGL(k_lpt_sbar, dim3(grid_for(n3)), dim3(kThreads), 0, s, xbar, pbar, n3, cx1, cp1, cx2, cp2, s1[0],
+                     s1[1], s1[2], s2[0], s2[1], s2[2]);
+}
+
+void launch_lpt_phibar(float* const* phi6, const float* d2b, long n3, hipStream_t s) {
+  hipLaunchKernelGGL(k_lpt_phibar, dim3(grid_for(n3)), dim3(kThreads), 0, s, phi6[0], phi6[1], phi6[2], phi6[3],
+                     phi6[4], phi6[5], d2b, n3);
+}
+
+}  // namespace pmk

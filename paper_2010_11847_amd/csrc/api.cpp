@@ -1,0 +1,853 @@
+// C-ABI entry points of the PM library (declared in include/pm.h): config
+// validation, workspace layout, host float64 tables and the orchestration of
+// the HIP kernels for painting, force, KDK steps, full runs, initial
+// conditions and power spectra.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "cosmo.h"
+#include "particles.h"
+#include "pm.h"
+#include "pm_internal.h"
+
+using pmk::Field;
+using pmk::FftTables;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
+
+size_t field_bytes(long n) { return align_up((size_t)n * n * n * 4) + align_up((size_t)n * n * 8); }
+
+size_t fft_table_bytes(long n) {
+  return align_up(n * 8) + align_up(n / 2 * 8) + 4 * align_up(n * 4) + 4 * align_up((n / 2 + 1) * 4);
+}
+
+int tile_side(int n) {
+  int t = 16;
+  while (t > 1 && t * 2 > n) t >>= 1;   // at least two tiles per side
+  return t;
+}
+
+// Byte layout of the workspace (offsets from its base).
+struct Layout {
+  size_t tab_mesh = 0, tab_lat = 0, pk_lat = 0;
+  size_t mesh[3] = {0, 0, 0};
+  size_t pos_s[2] = {0, 0}, mom_s[2] = {0, 0}, id_s[2] = {0, 0};
+  size_t key = 0, rank = 0;
+  size_t count = 0, off = 0, bsum = 0;
+  size_t pw_partial = 0, pw_out = 0;
+  size_t lat0 = 0;   // LPT lattice fields alias the mesh + particle region
+  size_t total = 0;
+  long n_keys = 0, cap = 0;
+  int n_bins_max = 0;
+};
+
+int validate(const pm_config* c, std::string* why) {
+  auto bad = [&](const char* m) {
+    if (why) *why = m;
+    return PM_EINVAL;
+  };
+  if (!c) return bad("config is NULL");
+  if (!(c->box_size > 0)) return bad("box_size must be > 0");
+  if (!is_pow2(c->n_mesh) || c->n_mesh < 8 || c->n_mesh > 1024) return bad("n_mesh must be a power of 2 in [8, 1024]");
+  if (!is_pow2(c->n_part) || c->n_part < 8 || c->n_part > c->n_mesh) return bad("n_part must be a power of 2 in [8, n_mesh]");
+  if (c->n_mesh % c->n_part) return bad("n_mesh must be a multiple of n_part");
+  if (!(c->cosmo.omega_m > 0 && c->cosmo.omega_m <= 1)) return bad("omega_m must be in (0, 1]");
+  if (c->cosmo.pk_kind < 0 || c->cosmo.pk_kind > 2) return bad("unknown pk_kind");
+  if (c->cosmo.pk_kind == PM_PK_EH_NOWIGGLE &&
+      !(c->cosmo.h > 0 && c->cosmo.omega_b >= 0 && c->cosmo.omega_b < c->cosmo.omega_m && c->cosmo.t_cmb > 0))
+    return bad("no-wiggle P(k) needs h > 0, 0 <= omega_b < omega_m, t_cmb > 0");
+  if (c->cosmo.pk_kind == PM_PK_TABLE) {
+    if (c->cosmo.pk_n < 2 || !c->cosmo.pk_k || !c->cosmo.pk_p) return bad("table P(k) needs pk_n >= 2 points");
+    for (int i = 0; i < c->cosmo.pk_n; ++i) {
+      if (!(c->cosmo.pk_k[i] > 0) || !(c->cosmo.pk_p[i] >= 0)) return bad("table P(k) needs k > 0, P >= 0");
+      if (i && !(c->cosmo.pk_k[i] > c->cosmo.pk_k[i - 1])) return bad("table k must increase");
+    }
+  }
+  if (c->cosmo.pk_amp == 0 && c->cosmo.pk_kind != PM_PK_TABLE && !(c->cosmo.sigma8 > 0))
+    return bad("sigma8 must be > 0 when pk_amp is 0");
+  if (c->lpt_order != 1 && c->lpt_order != 2) return bad("lpt_order must be 1 or 2");
+  if (c->deconv_order < 0 || c->deconv_order > 2) return bad("deconv_order must be 0, 1 or 2");
+  if (c->split_mode < 0 || c->split_mode > 2) return bad("unknown split_mode");
+  if (c->split_mode != PM_SPLIT_NONE && !(c->split_rs > 0)) return bad("split_rs must be > 0");
+  if (!(c->lattice_shift >= 0 && c->lattice_shift < 1)) return bad("lattice_shift must be in [0, 1)");
+  const long np3 = (long)c->n_part * c->n_part * c->n_part;
+  if (c->max_particles < 0) return bad("max_particles must be >= 0");
+  if (c->max_particles > 0 && c->max_particles < np3) return bad("max_particles must be 0 or >= n_part^3");
+  if ((c->max_particles > 0 ? c->max_particles : np3) > (1L << 31) - 1) return bad("too many particles");
+  return PM_OK;
+}
+
+Layout make_layout(const pm_config* c) {
+  Layout L;
+  const long ng = c->n_mesh, np = c->n_part;
+  const long np3 = np * np * np;
+  L.cap = c->max_particles > 0 ? c->max_particles : np3;
+  const int t = tile_side((int)ng);
+  const long nt = ng / t;
+  L.n_keys = nt * nt * nt * 8;
+  L.n_bins_max = (int)(ng / 2);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += align_up(bytes);
+    return at;
+  };
+  L.tab_mesh = take(fft_table_bytes(ng));
+  L.tab_lat = take(fft_table_bytes(np));
+  L.pk_lat = take((size_t)(3 * (np / 2) * (np / 2) + 1) * 4);
+  L.count = take((size_t)(L.n_keys + 1) * 4);
+  L.off = take((size_t)(L.n_keys + 1) * 4);
+  L.bsum = take((size_t)(pmk::scan_scratch_words(L.n_keys) + 1) * 4);
+  L.pw_partial = take((size_t)pmk::power_partial_doubles(L.n_bins_max) * 8);
+  L.pw_out = take((size_t)3 * L.n_bins_max * 8);
+  const size_t region = o;
+  for (int i = 0; i < 3; ++i) L.mesh[i] = take(field_bytes(ng));
+  for (int i = 0; i < 2; ++i) L.pos_s[i] = take((size_t)L.cap * 12);
+  for (int i = 0; i < 2; ++i) L.mom_s[i] = take((size_t)L.cap * 12);
+  for (int i = 0; i < 2; ++i) L.id_s[i] = take((size_t)L.cap * 4);
+  L.key = take((size_t)L.cap * 4);
+  L.rank = take((size_t)L.cap * 4);
+  // initial conditions (and their adjoint) use up to 13 lattice fields
+  // inside the (then idle) mesh and particle region
+  L.lat0 = region;
+  const size_t lat_end = region + 13 * field_bytes(np);
+  if (lat_end > o) o = lat_end;
+  L.total = o;
+  return L;
+}
+
+void build_fft_tables(long n, double rs, std::vector<char>& host, size_t base_off, FftTables& t, char* dev) {
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += align_up(bytes);
+    return at;
+  };
+  const size_t o_twn = take(n * 8), o_twh = take(n / 2 * 8);
+  const size_t o_d = take(n * 4), o_k = take(n * 4), o_w = take(n * 4), o_s = take(n * 4);
+  const size_t o_dz = take((n / 2 + 1) * 4), o_kz = take((n / 2 + 1) * 4), o_wz = take((n / 2 + 1) * 4),
+               o_sz = take((n / 2 + 1) * 4);
+  char* h = host.data() + base_off;
+  float2* twn = reinterpret_cast<float2*>(h + o_twn);
+  float2* twh = reinterpret_cast<float2*>(h + o_twh);
+  for (long k = 0; k < n; ++k) twn[k] = make_float2((float)std::cos(2 * kPi * k / n), (float)-std::sin(2 * kPi * k / n));
+  for (long k = 0; k < n / 2; ++k)
+    twh[k] = make_float2((float)std::cos(2 * kPi * k / (n / 2)), (float)-std::sin(2 * kPi * k / (n / 2)));
+  auto fill = [&](float* d, float* kk, float* w, float* s, long len, bool signed_freq) {
+    for (long i = 0; i < len; ++i) {
+      const double f = signed_freq ? (i < n / 2 ? (double)i : (double)(i - n)) : (double)i;
+      const double om = 2 * kPi * f / n;
+      d[i] = (float)((8.0 * std::sin(om) - std::sin(2.0 * om)) / 6.0);
+      const double s2 = 2.0 * std::sin(om / 2.0);
+      kk[i] = (float)(s2 * s2);
+      const double sc = om == 0 ? 1.0 : std::sin(om / 2.0) / (om / 2.0);
+      w[i] = (float)(sc * sc);
+      s[i] = (float)std::exp(-om * om * rs * rs);
+    }
+  };
+  fill(reinterpret_cast<float*>(h + o_d), reinterpret_cast<float*>(h + o_k), reinterpret_cast<float*>(h + o_w),
+       reinterpret_cast<float*>(h + o_s), n, true);
+  fill(reinterpret_cast<float*>(h + o_dz), reinterpret_cast<float*>(h + o_kz), reinterpret_cast<float*>(h + o_wz),
+       reinterpret_cast<float*>(h + o_sz), n / 2 + 1, false);
+  char* d = dev + base_off;
+  t.n = (int)n;
+  t.tw_n = reinterpret_cast<float2*>(d + o_twn);
+  t.tw_h = reinterpret_cast<float2*>(d + o_twh);
+  t.dxy = reinterpret_cast<float*>(d + o_d);
+  t.kxy = reinterpret_cast<float*>(d + o_k);
+  t.wxy = reinterpret_cast<float*>(d + o_w);
+  t.sxy = reinterpret_cast<float*>(d + o_s);
+  t.dz = reinterpret_cast<float*>(d + o_dz);
+  t.kz = reinterpret_cast<float*>(d + o_kz);
+  t.wz = reinterpret_cast<float*>(d + o_wz);
+  t.sz = reinterpret_cast<float*>(d + o_sz);
+}
+
+// Kernel classes timed by the optional event profiler.
+enum ProfCls : int {
+  PC_FILL, PC_KEYS, PC_SCAN, PC_SCATTER, PC_PAINT, PC_FFT_R2C_Z, PC_FFT_Y_FWD, PC_FFT_X_FUSED, PC_FFT_Y_INV,
+  PC_FFT_C2R_Z, PC_READOUT, PC_NCLS
+};
+const char* const kProfNames[PC_NCLS] = {"fill",        "keys",        "scan",         "scatter",
+                                         "paint",       "fft_z_r2c",   "fft_y_fwd",    "fft_x_fused",
+                                         "fft_y_inv",   "fft_z_c2r",   "readout_kdk"};
+
+struct Profiler {
+  bool on = false;
+  struct Rec {
+    int cls;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  hipEvent_t get() {
+    if (used == pool.size()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  ~Profiler() {
+    for (auto e : pool) hipEventDestroy(e);
+  }
+};
+
+}  // namespace
+
+struct pm_ctx {
+  pm_config cfg{};
+  hipStream_t stream = nullptr;
+  std::string err;
+  pmk::Cosmo cosmo;
+  std::vector<double> pk_k_copy, pk_p_copy;
+  char* ws = nullptr;
+  Layout L;
+  int ng = 0, npart = 0, ratio = 1;
+  long np3 = 0;
+  pmk::TileGeom tg;
+  FftTables tm, tl;
+  Field mesh[3];
+  float* pos_s[2] = {};
+  float* mom_s[2] = {};
+  uint32_t* id_s[2] = {};
+  uint32_t *key = nullptr, *rank = nullptr, *count = nullptr, *off = nullptr, *bsum = nullptr;
+  double *pw_partial = nullptr, *pw_out = nullptr;
+  float* pk_lat = nullptr;
+  Profiler prof;
+
+  // run f (which enqueues one kernel class) between two events when profiling
+  template <class F>
+  void timed(int cls, F&& f) {
+    if (!prof.on || prof.recs.size() >= 65536) {
+      f();
+      return;
+    }
+    hipEvent_t a = prof.get(), b = prof.get();
+    if (!a || !b) {
+      f();
+      return;
+    }
+    hipEventRecord(a, stream);
+    f();
+    hipEventRecord(b, stream);
+    prof.recs.push_back({cls, a, b});
+  }
+
+  int fail(int code, const std::string& m) {
+    err = m;
+    return code;
+  }
+  int check(const char* where) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(PM_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+    return PM_OK;
+  }
+  Field lat(int i) const {
+    Field f;
+    char* b = ws + L.lat0 + (size_t)i * field_bytes(npart);
+    f.r = reinterpret_cast<float*>(b);
+    f.q = reinterpret_cast<float2*>(b + align_up((size_t)npart * npart * npart * 4));
+    return f;
+  }
+
+  // counting sort of np particles (caller order) into sorted buffer dst
+  void sort(const float* pos, const float* mom, const uint32_t* id, long np, int dst) {
+    timed(PC_FILL, [&] { pmk::launch_fill_u32(count, L.n_keys, 0u, stream); });
+    timed(PC_KEYS, [&] { pmk::launch_keys(pos, np, tg, key, rank, count, stream); });
+    finish_sort(pos, mom, id, np, dst);
+  }
+  // scan + scatter once key/rank/count are known
+  void finish_sort(const float* pos, const float* mom, const uint32_t* id, long np, int dst) {
+    timed(PC_SCAN, [&] { pmk::launch_scan(count, L.n_keys, off, bsum, stream); });
+    pmk::ScatterArgs a;
+    a.np = np;
+    a.pos = pos;
+    a.mom = mom;
+    a.id = id;
+    a.key = key;
+    a.rank = rank;
+    a.off = off;
+    a.pos_out = pos_s[dst];
+    a.mom_out = mom ? mom_s[dst] : nullptr;
+    a.id_out = id_s[dst];
+    timed(PC_SCATTER, [&] { pmk::launch_scatter(a, stream); });
+  }
+  void paint(int cur, long np, float* out) {
+    const double scale = (double)ng * ng * ng / (double)np;
+    timed(PC_PAINT, [&] { pmk::launch_paint(pos_s[cur], off, tg, out, (float)scale, -1.f, stream); });
+  }
+  // force meshes from the overdensity in mesh[0].r (overwritten)
+  void force_meshes() {
+    timed(PC_FFT_R2C_Z, [&] { pmk::fft_z_r2c(tm, &mesh[0], 1, stream); });
+    timed(PC_FFT_Y_FWD, [&] { pmk::fft_y(tm, &mesh[0], 1, -1, stream); });
+    pmk::SpecOp op;
+    op.kind = pmk::OP_FORCE;
+    op.n_out = 3;
+    op.scale = (float)(1.5 * cfg.cosmo.omega_m / ((double)ng * ng * ng));
+    op.deconv = cfg.deconv_order;
+    op.split = cfg.split_mode;
+    for (int i = 0; i < 3; ++i) {
+      op.out_c[i] = mesh[i].c();
+      op.out_q[i] = mesh[i].q;
+    }
+    timed(PC_FFT_X_FUSED, [&] { pmk::fft_x_fused(tm, mesh[0], op, stream); });
+    timed(PC_FFT_Y_INV, [&] { pmk::fft_y(tm, mesh, 3, 1, stream); });
+    timed(PC_FFT_C2R_Z, [&] { pmk::fft_z_c2r(tm, mesh, 3, stream); });
+  }
+  void readout(const pmk::ReadoutArgs& a) {
+    timed(PC_READOUT, [&] { pmk::launch_readout(a, stream); });
+  }
+  pmk::ReadoutArgs readout_args(int cur) {
+    pmk::ReadoutArgs a;
+    a.g = tg;
+    a.pos = pos_s[cur];
+    a.mom = mom_s[cur];
+    a.id = id_s[cur];
+    a.off = off;
+    a.f0 = mesh[0].r;
+    a.f1 = mesh[1].r;
+    a.f2 = mesh[2].r;
+    a.key_out = key;
+    a.rank_out = rank;
+    a.count = count;
+    return a;
+  }
+};
+
+extern "C" {
+
+const char* pm_strerror(int s) {
+  switch (s) {
+    case PM_OK: return "ok";
+    case PM_EINVAL: return "invalid argument";
+    case PM_ENOMEM: return "workspace too small";
+    case PM_EHIP: return "HIP runtime error";
+    case PM_ESTATE: return "invalid state";
+    default: return "unknown status";
+  }
+}
+
+const char* pm_last_error(const pm_ctx* ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+size_t pm_workspace_bytes(const pm_config* cfg) {
+  if (validate(cfg, nullptr) != PM_OK) return 0;
+  return make_layout(cfg).total;
+}
+
+int pm_create(const pm_config* cfg, void* d_workspace, size_t bytes, void* stream, pm_ctx** out) {
+  if (!out) return PM_EINVAL;
+  *out = nullptr;
+  std::string why;
+  if (validate(cfg, &why) != PM_OK) {
+    std::fprintf(stderr, "pm_create: %s\n", why.c_str());
+    return PM_EINVAL;
+  }
+  if (!d_workspace || ((uintptr_t)d_workspace % kAlign)) return PM_EINVAL;
+  const Layout L = make_layout(cfg);
+  if (bytes < L.total) return PM_ENOMEM;
+  pm_ctx* c = new (std::nothrow) pm_ctx;
+  if (!c) return PM_ENOMEM;
+  c->cfg = *cfg;
+  if (cfg->cosmo.pk_kind == PM_PK_TABLE) {   // own a copy of the caller's table
+    c->pk_k_copy.assign(cfg->cosmo.pk_k, cfg->cosmo.pk_k + cfg->cosmo.pk_n);
+    c->pk_p_copy.assign(cfg->cosmo.pk_p, cfg->cosmo.pk_p + cfg->cosmo.pk_n);
+    c->cfg.cosmo.pk_k = c->pk_k_copy.data();
+    c->cfg.cosmo.pk_p = c->pk_p_copy.data();
+  }
+  c->stream = reinterpret_cast<hipStream_t>(stream);
+  c->ws = reinterpret_cast<char*>(d_workspace);
+  c->L = L;
+  c->ng = cfg->n_mesh;
+  c->npart = cfg->n_part;
+  c->ratio = cfg->n_mesh / cfg->n_part;
+  c->np3 = (long)cfg->n_part * cfg->n_part * cfg->n_part;
+  c->cosmo.init(c->cfg.cosmo);
+  const int t = tile_side(c->ng);
+  c->tg.n = c->ng;
+  c->tg.t = t;
+  c->tg.nt = c->ng / t;
+  c->tg.ntiles = c->tg.nt * c->tg.nt * c->tg.nt;
+  char* w = c->ws;
+  for (int i = 0; i < 3; ++i) {
+    c->mesh[i].r = reinterpret_cast<float*>(w + L.mesh[i]);
+    c->mesh[i].q = reinterpret_cast<float2*>(w + L.mesh[i] + align_up((size_t)c->ng * c->ng * c->ng * 4));
+  }
+  for (int i = 0; i < 2; ++i) {
+    c->pos_s[i] = reinterpret_cast<float*>(w + L.pos_s[i]);
+    c->mom_s[i] = reinterpret_cast<float*>(w + L.mom_s[i]);
+    c->id_s[i] = reinterpret_cast<uint32_t*>(w + L.id_s[i]);
+  }
+  c->key = reinterpret_cast<uint32_t*>(w + L.key);
+  c->rank = reinterpret_cast<uint32_t*>(w + L.rank);
+  c->count = reinterpret_cast<uint32_t*>(w + L.count);
+  c->off = reinterpret_cast<uint32_t*>(w + L.off);
+  c->bsum = reinterpret_cast<uint32_t*>(w + L.bsum);
+  c->pw_partial = reinterpret_cast<double*>(w + L.pw_partial);
+  c->pw_out = reinterpret_cast<double*>(w + L.pw_out);
+  c->pk_lat = reinterpret_cast<float*>(w + L.pk_lat);
+
+  // static tables, built on the host in float64 and uploaded once
+  std::vector<char> host(L.mesh[0], 0);
+  const double rs = cfg->split_mode != PM_SPLIT_NONE ? cfg->split_rs : 0.0;
+  build_fft_tables(c->ng, rs, host, L.tab_mesh, c->tm, w);
+  build_fft_tables(c->npart, 0.0, host, L.tab_lat, c->tl, w);
+  {
+    float* pk = reinterpret_cast<float*>(host.data() + L.pk_lat);
+    const long h = c->npart / 2;
+    const double box = cfg->box_size;
+    const double vcell = std::pow(box / c->npart, 3);
+    const double n3 = (double)c->np3;
+    for (long n2 = 0; n2 <= 3 * h * h; ++n2) {
+      const double k = 2 * kPi * std::sqrt((double)n2) / box;
+      pk[n2] = n2 == 0 ? 0.f : (float)(std::sqrt(c->cosmo.pk(k) / vcell) / n3);
+    }
+  }
+  hipError_t e = hipMemcpyAsync(w, host.data(), L.mesh[0], hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    std::fprintf(stderr, "pm_create: %s\n", hipGetErrorString(e));
+    delete c;
+    return PM_EHIP;
+  }
+  *out = c;
+  return PM_OK;
+}
+
+int pm_destroy(pm_ctx* ctx) {
+  delete ctx;
+  return PM_OK;
+}
+
+int pm_set_stream(pm_ctx* ctx, void* stream) {
+  if (!ctx) return PM_EINVAL;
+  ctx->stream = reinterpret_cast<hipStream_t>(stream);
+  return PM_OK;
+}
+
+int pm_sync(pm_ctx* ctx) {
+  if (!ctx) return PM_EINVAL;
+  const hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return ctx->fail(PM_EHIP, std::string("sync: ") + hipGetErrorString(e));
+  return ctx->check("sync");
+}
+
+int pm_growth(const pm_ctx* ctx, double a, double* out6) {
+  if (!ctx || !out6 || !(a > 0)) return PM_EINVAL;
+  ctx->cosmo.growth(a, out6);
+  return PM_OK;
+}
+
+int pm_noise(pm_ctx* ctx, uint64_t seed, float* d_noise) {
+  if (!ctx || !d_noise) return PM_EINVAL;
+  pmk::launch_noise(seed, ctx->np3, d_noise, ctx->stream);
+  return ctx->check("pm_noise");
+}
+
+int pm_init_lpt(pm_ctx* ctx, uint64_t seed, double a0, const float* d_noise_in, float* d_noise_out, float* d_pos,
+                float* d_mom) {
+  if (!ctx || !d_pos || !d_mom || !(a0 > 0)) return PM_EINVAL;
+  pm_ctx& c = *ctx;
+  const long n3 = c.np3;
+  Field f[10];
+  for (int i = 0; i < 10; ++i) f[i] = c.lat(i);
+  if (d_noise_in) {
+    if (hipMemcpyAsync(f[0].r, d_noise_in, n3 * 4, hipMemcpyDeviceToDevice, c.stream) != hipSuccess)
+      return c.check("pm_init_lpt copy");
+  } else {
+    pmk::launch_noise(seed, n3, f[0].r, c.stream);
+  }
+  if (d_noise_out && hipMemcpyAsync(d_noise_out, f[0].r, n3 * 4, hipMemcpyDeviceToDevice, c.stream) != hipSuccess)
+    return c.check("pm_init_lpt copy");
+  const int order = c.cfg.lpt_order;
+  pmk::fft_r2c_zy(c.tl, &f[0], 1, c.stream);
+  pmk::SpecOp op;
+  op.kind = pmk::OP_LPT1;
+  op.n_out = order >= 2 ? 9 : 3;
+  op.pk = c.pk_lat;
+  for (int i = 0; i < op.n_out; ++i) {
+    op.out_c[i] = f[1 + i].c();
+    op.out_q[i] = f[1 + i].q;
+  }
+  pmk::fft_x_fused(c.tl, f[0], op, c.stream);
+  pmk::fft_c2r_yz(c.tl, &f[1], op.n_out, c.stream);
+  if (order >= 2) {
+    float* phi[6] = {f[4].r, f[5].r, f[6].r, f[7].r, f[8].r, f[9].r};
+    pmk::launch_lpt_delta2(phi, n3, f[0].r, c.stream);
+    pmk::fft_r2c_zy(c.tl, &f[0], 1, c.stream);
+    pmk::SpecOp op2;
+    op2.kind = pmk::OP_LPT2;
+    op2.n_out = 3;
+    op2.scale = (float)(1.0 / (double)n3);
+    for (int i = 0; i < 3; ++i) {
+      op2.out_c[i] = f[4 + i].c();
+      op2.out_q[i] = f[4 + i].q;
+    }
+    pmk::fft_x_fused(c.tl, f[0], op2, c.stream);
+    pmk::fft_c2r_yz(c.tl, &f[4], 3, c.stream);
+  }
+  double g[6];
+  c.cosmo.growth(a0, g);
+  const double d1 = g[0], f1 = g[1], d2 = order >= 2 ? g[2] : 0.0, f2 = g[3], e = g[4];
+  const double b = c.ratio;
+  pmk::LptParticleArgs a;
+  a.np = c.npart;
+  a.ratio = c.ratio;
+  a.shift = (float)c.cfg.lattice_shift;
+  a.nmesh = (float)c.ng;
+  a.cx1 = (float)(b * d1);
+  a.cx2 = (float)(b * d2);
+  a.cp1 = (float)(b * a0 * a0 * e * f1 * d1);
+  a.cp2 = (float)(b * a0 * a0 * e * f2 * d2);
+  for (int d = 0; d < 3; ++d) {
+    a.s1[d] = f[1 + d].r;
+    a.s2[d] = f[4 + d].r;
+  }
+  a.has_s2 = order >= 2 ? 1 : 0;
+  a.pos = d_pos;
+  a.mom = d_mom;
+  pmk::launch_lpt_particles(a, c.stream);
+  return c.check("pm_init_lpt");
+}
+
+int pm_paint(pm_ctx* ctx, const float* d_pos, int64_t np, float* d_delta) {
+  if (!ctx || !d_pos || !d_delta || np < 1 || np > ctx->L.cap) return PM_EINVAL;
+  pm_ctx& c = *ctx;
+  c.sort(d_pos, nullptr, nullptr, np, 0);
+  c.paint(0, np, d_delta);
+  return c.check("pm_paint");
+}
+
+int pm_force(pm_ctx* ctx, const float* d_pos, int64_t np, float* d_force) {
+  if (!ctx || !d_pos || !d_force || np < 1 || np > ctx->L.cap) return PM_EINVAL;
+  pm_ctx& c = *ctx;
+  c.sort(d_pos, nullptr, nullptr, np, 0);
+  c.paint(0, np, c.mesh[0].r);
+  c.force_meshes();
+  pmk::ReadoutArgs a = c.readout_args(0);
+  a.mom = nullptr;
+  a.flags = pmk::RO_FORCE_BYID;
+  a.force_out = d_force;
+  c.readout(a);
+  return c.check("pm_force");
+}
+
+int pm_kdk_step(pm_ctx* ctx, float* d_pos, float* d_mom, float* d_force, double a0, double a1) {
+  if (!ctx || !d_pos || !d_mom || !d_force || !(a0 > 0) || !(a1 > a0)) return PM_EINVAL;
+  pm_ctx& c = *ctx;
+  const double ac = std::sqrt(a0 * a1);
+  const double k1 = c.cosmo.kick(a0, ac, a0), dr = c.cosmo.drift(a0, a1, ac), k2 = c.cosmo.kick(ac, a1, a1);
+  pmk::launch_kick_drift(d_pos, d_mom, d_force, c.np3, (float)k1, (float)dr, (float)c.ng, c.stream);
+  c.sort(d_pos, d_mom, nullptr, c.np3, 0);
+  c.paint(0, c.np3, c.mesh[0].r);
+  c.force_meshes();
+  pmk::ReadoutArgs a = c.readout_args(0);
+  a.flags = pmk::RO_KICK | pmk::RO_XP_BYID | pmk::RO_FORCE_BYID;
+  a.kick_a = (float)k2;
+  a.kick_b = 0.f;
+  a.pos_out = d_pos;
+  a.mom_out = d_mom;
+  a.force_out = d_force;
+  c.readout(a);
+  return c.check("pm_kdk_step");
+}
+
+int pm_run(pm_ctx* ctx, const double* h_a, int n_a, float* d_pos, float* d_mom, float* d_ckpt,
+           float* d_delta_final) {
+  if (!ctx || !h_a || n_a < 1 || !d_pos || !d_mom) return PM_EINVAL;
+  pm_ctx& c = *ctx;
+  for (int i = 0; i < n_a; ++i)
+    if (!(h_a[i] > 0) || (i && !(h_a[i] > h_a[i - 1]))) return c.fail(PM_EINVAL, "a must be > 0 and increasing");
+  const int ns = n_a - 1;
+  std::vector<double> k1(ns), dr(ns), k2(ns);
+  for (int i = 0; i < ns; ++i) {
+    const double ai = h_a[i], aj = h_a[i + 1], ac = std::sqrt(ai * aj);
+    k1[i] = c.cosmo.kick(ai, ac, ai);
+    dr[i] = c.cosmo.drift(ai, aj, ac);
+    k2[i] = c.cosmo.kick(ac, aj, aj);
+  }
+  const long np = c.np3;
+  const size_t ck = (size_t)np * 3;
+  int cur = 0;
+  c.sort(d_pos, d_mom, nullptr, np, cur);
+  if (ns == 0 && d_delta_final) c.paint(cur, np, d_delta_final);
+  c.paint(cur, np, c.mesh[0].r);
+  c.force_meshes();
+  for (int i = 0; i < ns; ++i) {
+    c.timed(PC_FILL, [&] { pmk::launch_fill_u32(c.count, c.L.n_keys, 0u, c.stream); });
+    pmk::ReadoutArgs a = c.readout_args(cur);
+    a.flags = pmk::RO_KICK | pmk::RO_DRIFT | pmk::RO_WRITE_SORTED | pmk::RO_KEYS;
+    a.kick_a = i ? (float)k2[i - 1] : 0.f;
+    a.kick_b = (float)k1[i];
+    a.drift = (float)dr[i];
+    if (d_ckpt) {
+      a.flags |= pmk::RO_CKPT;
+      a.ckpt_x = d_ckpt + (2 * (size_t)i) * ck;
+      a.ckpt_p = d_ckpt + (2 * (size_t)i + 1) * ck;
+    }
+    c.readout(a);
+    c.finish_sort(c.pos_s[cur], c.mom_s[cur], c.id_s[cur], np, 1 - cur);
+    cur = 1 - cur;
+    if (i == ns - 1 && d_delta_final) c.paint(cur, np, d_delta_final);
+    c.paint(cur, np, c.mesh[0].r);
+    c.force_meshes();
+  }
+  pmk::ReadoutArgs a = c.readout_args(cur);
+  a.flags = pmk::RO_KICK | pmk::RO_XP_BYID;
+  a.kick_a = ns ? (float)k2[ns - 1] : 0.f;
+  a.kick_b = 0.f;
+  a.pos_out = d_pos;
+  a.mom_out = d_mom;
+  if (d_ckpt) {
+    a.flags |= pmk::RO_CKPT;
+    a.ckpt_x = d_ckpt + (2 * (size_t)ns) * ck;
+    a.ckpt_p = d_ckpt + (2 * (size_t)ns + 1) * ck;
+  }
+  c.readout(a);
+  return c.check("pm_run");
+}
+
+int pm_run_adjoint(pm_ctx* ctx, const double* h_a, int n_a, const float* d_ckpt, const float* d_noise,
+                   const float* d_grad_delta_final, float* d_grad_pos, float* d_grad_mom, float* d_grad_noise) {
+  if (!ctx || !h_a || n_a < 1 || !d_ckpt || !d_grad_pos || !d_grad_mom) return PM_EINVAL;
+  pm_ctx& c = *ctx;
+  if (d_grad_noise && !d_noise) return c.fail(PM_EINVAL, "d_grad_noise needs d_noise");
+  for (int i = 0; i < n_a; ++i)
+    if (!(h_a[i] > 0) || (i && !(h_a[i] > h_a[i - 1]))) return c.fail(PM_EINVAL, "a must be > 0 and increasing");
+  const int ns = n_a - 1;
+  std::vector<double> k1(ns), dr(ns), k2(ns);
+  for (int i = 0; i < ns; ++i) {
+    const double ai = h_a[i], aj = h_a[i + 1], ac = std::sqrt(ai * aj);
+    k1[i] = c.cosmo.kick(ai, ac, ai);
+    dr[i] = c.cosmo.drift(ai, aj, ac);
+    k2[i] = c.cosmo.kick(ac, aj, aj);
+  }
+  const long np = c.np3;
+  const size_t ck = (size_t)np * 3;
+  float* xbar = d_grad_pos;
+  float* pbar = d_grad_mom;
+  auto ckpt_x = [&](int i) { return d_ckpt + 2 * (size_t)i * ck; };
+  const double s = (double)c.ng * c.ng * c.ng / (double)np;
+  // loss on the final overdensity: x_bar += paint^T-gradient of s * delta_bar
+  if (d_grad_delta_final) {
+    c.sort(ckpt_x(ns), nullptr, nullptr, np, 0);
+    pmk::launch_readout_grad1(c.pos_s[0], c.id_s[0], c.off, c.tg, d_grad_delta_final, (float)s, xbar, c.stream);
+  }
+  // reverse sweep over the force evaluation points x_ns ... x_0
+  for (int j = ns; j >= 0; --j) {
+    const double kj = (j < ns ? k1[j] : 0.0) + (j > 0 ? k2[j - 1] : 0.0);
+    if (kj != 0.0) {
+      c.sort(ckpt_x(j), nullptr, nullptr, np, 0);
+      c.paint(0, np, c.mesh[0].r);
+      c.force_meshes();
+      // term A: positions at which the force meshes are read out
+      pmk::launch_readout_grad3(c.pos_s[0], c.id_s[0], c.off, c.tg, c.mesh[0].r, c.mesh[1].r, c.mesh[2].r, pbar,
+                                (float)kj, xbar, c.stream);
+      // term B: positions that paint the density, through G^T
+      pmk::launch_paint3w(c.pos_s[0], c.id_s[0], c.off, c.tg, pbar, (float)kj, c.mesh[0].r, c.mesh[1].r,
+                          c.mesh[2].r, c.stream);
+      pmk::fft_r2c_zy(c.tm, c.mesh, 3, c.stream);
+      pmk::SpecOp op;
+      op.kind = pmk::OP_FORCE_T;
+      op.n_in = 3;
+      op.n_out = 1;
+      op.scale = (float)(1.5 * c.cfg.cosmo.omega_m / (double)np);
+      op.deconv = c.cfg.deconv_order;
+      op.split = c.cfg.split_mode;
+      for (int d = 0; d < 3; ++d) {
+        op.in_c[d] = c.mesh[d].c();
+        op.in_q[d] = c.mesh[d].q;
+      }
+      op.out_c[0] = c.mesh[0].c();
+      op.out_q[0] = c.mesh[0].q;
+      pmk::fft_x_fused(c.tm, c.mesh[0], op, c.stream);
+      pmk::fft_c2r_yz(c.tm, &c.mesh[0], 1, c.stream);
+      pmk::launch_readout_grad1(c.pos_s[0], c.id_s[0], c.off, c.tg, c.mesh[0].r, 1.f, xbar, c.stream);
+    }
+    if (j > 0) pmk::launch_axpy(pbar, xbar, (float)dr[j - 1], (long)ck, c.stream);
+  }
+  if (!d_grad_noise) return c.check("pm_run_adjoint");
+
+  // Gen-IC: noise_bar from (x0_bar, p0_bar)
+  const long n3 = np;
+  const int order = c.cfg.lpt_order;
+  Field f[13];
+  for (int i = 0; i < 13; ++i) f[i] = c.lat(i);
+  if (hipMemcpyAsync(f[0].r, d_noise, n3 * 4, hipMemcpyDeviceToDevice, c.stream) != hipSuccess)
+    return c.check("pm_run_adjoint copy");
+  double g[6];
+  c.cosmo.growth(h_a[0], g);
+  const double a0 = h_a[0], b = c.ratio;
+  const double d1 = g[0], f1 = g[1], d2 = order >= 2 ? g[2] : 0.0, f2 = g[3], e = g[4];
+  float* s1b[3] = {f[7].r, f[8].r, f[9].r};
+  float* s2b[3] = {f[10].r, f[11].r, f[12].r};
+  pmk::launch_lpt_sbar(xbar, pbar, n3, (float)(b * d1), (float)(b * a0 * a0 * e * f1 * d1), (float)(b * d2),
+                       (float)(b * a0 * a0 * e * f2 * d2), s1b, s2b, c.stream);
+  int n_in = 3;
+  if (order >= 2) {
+    // phi_ij of the linear field
+    pmk::fft_r2c_zy(c.tl, &f[0], 1, c.stream);
+    pmk::SpecOp op;
+    op.kind = pmk::OP_LPT_PHI;
+    op.n_out = 6;
+    op.pk = c.pk_lat;
+    for (int i = 0; i < 6; ++i) {
+      op.out_c[i] = f[1 + i].c();
+      op.out_q[i] = f[1 + i].q;
+    }
+    pmk::fft_x_fused(c.tl, f[0], op, c.stream);
+    pmk::fft_c2r_yz(c.tl, &f[1], 6, c.stream);
+    // delta2_bar = sum_d S2_d^T s2_bar_d
+    pmk::fft_r2c_zy(c.tl, &f[10], 3, c.stream);
+    pmk::SpecOp o2;
+    o2.kind = pmk::OP_LPT2_T;
+    o2.n_in = 3;
+    o2.scale = (float)(1.0 / (double)n3);
+    for (int d = 0; d < 3; ++d) {
+      o2.in_c[d] = f[10 + d].c();
+      o2.in_q[d] = f[10 + d].q;
+    }
+    o2.out_c[0] = f[0].c();
+    o2.out_q[0] = f[0].q;
+    pmk::fft_x_fused(c.tl, f[0], o2, c.stream);
+    pmk::fft_c2r_yz(c.tl, &f[0], 1, c.stream);
+    float* phi[6] = {f[1].r, f[2].r, f[3].r, f[4].r, f[5].r, f[6].r};
+    pmk::launch_lpt_phibar(phi, f[0].r, n3, c.stream);
+    pmk::fft_r2c_zy(c.tl, &f[1], 6, c.stream);
+    n_in = 9;
+  }
+  pmk::fft_r2c_zy(c.tl, &f[7], 3, c.stream);
+  pmk::SpecOp o1;
+  o1.kind = pmk::OP_LPT1_T;
+  o1.n_in = n_in;
+  o1.pk = c.pk_lat;
+  for (int d = 0; d < 3; ++d) {
+    o1.in_c[d] = f[7 + d].c();
+    o1.in_q[d] = f[7 + d].q;
+  }
+  for (int i = 0; i < 6 && n_in == 9; ++i) {
+    o1.in_c[3 + i] = f[1 + i].c();
+    o1.in_q[3 + i] = f[1 + i].q;
+  }
+  o1.out_c[0] = f[0].c();
+  o1.out_q[0] = f[0].q;
+  pmk::fft_x_fused(c.tl, f[0], o1, c.stream);
+  pmk::fft_c2r_yz(c.tl, &f[0], 1, c.stream);
+  if (hipMemcpyAsync(d_grad_noise, f[0].r, n3 * 4, hipMemcpyDeviceToDevice, c.stream) != hipSuccess)
+    return c.check("pm_run_adjoint copy");
+  return c.check("pm_run_adjoint");
+}
+
+int pm_power(pm_ctx* ctx, const float* d_delta, int n_bins, int n_max, int deconv, double* h_k, double* h_pk,
+             double* h_nmodes) {
+  if (!ctx || !d_delta || !h_k || !h_pk || !h_nmodes) return PM_EINVAL;
+  pm_ctx& c = *ctx;
+  if (n_bins < 1 || n_bins > c.L.n_bins_max) return c.fail(PM_EINVAL, "n_bins must be in [1, n_mesh/2]");
+  const long n3 = (long)c.ng * c.ng * c.ng;
+  if (hipMemcpyAsync(c.mesh[0].r, d_delta, n3 * 4, hipMemcpyDeviceToDevice, c.stream) != hipSuccess)
+    return c.check("pm_power copy");
+  pmk::fft_r2c_zy(c.tm, &c.mesh[0], 1, c.stream);
+  pmk::fft_x_forward(c.tm, &c.mesh[0], 1, c.stream);
+  pmk::PowerArgs a;
+  a.n = c.ng;
+  a.n_bins = n_bins;
+  a.n_max = n_max;
+  a.deconv = deconv;
+  a.c = c.mesh[0].c();
+  a.q = c.mesh[0].q;
+  a.wxy = c.tm.wxy;
+  a.wz = c.tm.wz;
+  a.partial = c.pw_partial;
+  pmk::launch_power(a, c.pw_out, c.stream);
+  std::vector<double> h(3 * (size_t)n_bins);
+  hipError_t e = hipMemcpyAsync(h.data(), c.pw_out, h.size() * 8, hipMemcpyDeviceToHost, c.stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+  if (e != hipSuccess) return c.fail(PM_EHIP, std::string("pm_power: ") + hipGetErrorString(e));
+  const double box = c.cfg.box_size;
+  const double norm = box * box * box / ((double)n3 * (double)n3);
+  for (int j = 0; j < n_bins; ++j) {
+    const double sw = h[j], sk = h[n_bins + j], sp = h[2 * n_bins + j];
+    h_nmodes[j] = sw;
+    h_k[j] = sw > 0 ? sk / sw * 2 * kPi / box : 0.0;
+    h_pk[j] = sw > 0 ? sp / sw * norm : 0.0;
+  }
+  return c.check("pm_power");
+}
+
+int pm_rfft(pm_ctx* ctx, const float* d_real, float* d_spec) {
+  if (!ctx || !d_real || !d_spec) return PM_EINVAL;
+  pm_ctx& c = *ctx;
+  const long n3 = (long)c.ng * c.ng * c.ng;
+  if (hipMemcpyAsync(c.mesh[0].r, d_real, n3 * 4, hipMemcpyDeviceToDevice, c.stream) != hipSuccess)
+    return c.check("pm_rfft copy");
+  pmk::fft_r2c_zy(c.tm, &c.mesh[0], 1, c.stream);
+  pmk::fft_x_forward(c.tm, &c.mesh[0], 1, c.stream);
+  pmk::launch_spec_to_numpy(c.mesh[0].c(), c.mesh[0].q, reinterpret_cast<float2*>(d_spec), c.ng, 1.f, c.stream);
+  return c.check("pm_rfft");
+}
+
+int pm_irfft(pm_ctx* ctx, const float* d_spec, float* d_real) {
+  if (!ctx || !d_real || !d_spec) return PM_EINVAL;
+  pm_ctx& c = *ctx;
+  const long n3 = (long)c.ng * c.ng * c.ng;
+  pmk::launch_spec_from_numpy(reinterpret_cast<const float2*>(d_spec), c.mesh[0].c(), c.mesh[0].q, c.ng,
+                              (float)(1.0 / (double)n3), c.stream);
+  pmk::fft_x_inverse(c.tm, &c.mesh[0], 1, c.stream);
+  pmk::fft_c2r_yz(c.tm, &c.mesh[0], 1, c.stream);
+  if (hipMemcpyAsync(d_real, c.mesh[0].r, n3 * 4, hipMemcpyDeviceToDevice, c.stream) != hipSuccess)
+    return c.check("pm_irfft copy");
+  return c.check("pm_irfft");
+}
+
+int pm_profile(pm_ctx* ctx, int enable) {
+  if (!ctx) return PM_EINVAL;
+  ctx->prof.on = enable != 0;
+  if (enable) {
+    ctx->prof.recs.clear();
+    ctx->prof.used = 0;
+  }
+  return PM_OK;
+}
+
+int pm_profile_read(pm_ctx* ctx, int max, char* h_names, double* h_total_ms, int* h_count) {
+  if (!ctx || max < 0 || (max > 0 && (!h_names || !h_total_ms || !h_count))) return PM_EINVAL;
+  pm_ctx& c = *ctx;
+  const hipError_t e = hipStreamSynchronize(c.stream);
+  if (e != hipSuccess) return c.fail(PM_EHIP, std::string("pm_profile_read: ") + hipGetErrorString(e));
+  double tot[PC_NCLS] = {};
+  int cnt[PC_NCLS] = {};
+  for (const auto& r : c.prof.recs) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      tot[r.cls] += ms;
+      cnt[r.cls] += 1;
+    }
+  }
+  int k = 0;
+  for (int i = 0; i < PC_NCLS; ++i) {
+    if (!cnt[i]) continue;
+    if (k < max) {
+      std::snprintf(h_names + 32 * k, 32, "%s", kProfNames[i]);
+      h_total_ms[k] = tot[i];
+      h_count[k] = cnt[i];
+    }
+    ++k;
+  }
+  return k;
+}
+
+}  // extern "C"

@@ -1,0 +1,791 @@
+// Hand-written batched 3D real FFT for gfx950 (CDNA4).
+//
+// The PM force of section 2 of the paper takes one forward real-to-complex 3D
+// transform and three inverse transforms per step (section 3), each built
+// from 1D transforms along the three axes.  Here each axis is one pass
+// over HBM.  Inside a pass a 1D transform of length N = R1 * R2 is done as a
+// four-step decomposition:
+//
+//   stage A : R1-point DFTs in registers over elements n = R2*j1 + j2,
+//             twiddle exp(-/+ 2 pi i j2 l1 / N), exchange through LDS;
+//   stage B : R2-point DFTs in registers over j2, output k = l1 + R1*l2.
+//
+// Passes along strided axes (y, x) give each workgroup a tile of M adjacent
+// columns so that every global access is an M*8-byte contiguous segment; the
+// contiguous z axis uses the real<->complex packing of N reals as N/2 complex
+// values.  The Nyquist plane kz = N/2 lives in its own array so that all
+// strided tiles are aligned.  No MFMA: the transform is bandwidth bound.
+//
+// The x pass can be fused with a spectral multiplication and the inverse x
+// transform of each output (the Green's-function/gradient kernel of the
+// force, the LPT kernels), so the spectrum is read once and never written.
+#include "pm_internal.h"
+
+namespace pmk {
+namespace {
+
+constexpr int kThreads = 256;
+
+// ---- complex helpers ------------------------------------------------------
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {   // a * conj(b)
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+// multiply by DIR * i  (DIR = -1: -i, DIR = +1: +i)
+template <int DIR>
+__device__ __forceinline__ float2 cmul_i(float2 a) {
+  return DIR < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
+}
+
+// exp(DIR * 2 pi i idx / 32) applied to a; idx is a compile-time constant
+// after unrolling, so the branches fold.
+template <int DIR>
+__device__ __forceinline__ float2 twiddle32(float2 a, int idx) {
+  constexpr float c32[32] = {
+      1.000000000e+00f, 9.807852804e-01f, 9.238795325e-01f, 8.314696123e-01f,
+      7.071067812e-01f, 5.555702330e-01f, 3.826834324e-01f, 1.950903220e-01f,
+      0.0f, -1.950903220e-01f, -3.826834324e-01f, -5.555702330e-01f,
+      -7.071067812e-01f, -8.314696123e-01f, -9.238795325e-01f, -9.807852804e-01f,
+      -1.000000000e+00f, -9.807852804e-01f, -9.238795325e-01f, -8.314696123e-01f,
+      -7.071067812e-01f, -5.555702330e-01f, -3.826834324e-01f, -1.950903220e-01f,
+      0.0f, 1.950903220e-01f, 3.826834324e-01f, 5.555702330e-01f,
+      7.071067812e-01f, 8.314696123e-01f, 9.238795325e-01f, 9.807852804e-01f};
+  if (idx == 0) return a;
+  if (idx == 8) return cmul_i<DIR>(a);
+  if (idx == 16) return make_float2(-a.x, -a.y);
+  if (idx == 24) return cmul_i<-DIR>(a);
+  const float c = c32[idx & 31];
+  const float s = (DIR < 0 ? -1.f : 1.f) * c32[(idx + 24) & 31];   // sin(2 pi idx/32)
+  return make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
+}
+
+template <int R>
+__host__ __device__ constexpr int bitrev(int i) {
+  int r = 0;
+  for (int b = 1; b < R; b <<= 1) {
+    r = (r << 1) | (i & 1);
+    i >>= 1;
+  }
+  return r;
+}
+
+// In-register DFT of R = 1..32 points (power of two), natural order in and
+// out: radix-2 decimation in frequency followed by a bit-reversal that the
+// compiler resolves into register renaming.
+template <int R, int DIR>
+__device__ __forceinline__ void dft(float2 (&v)[R]) {
+  if constexpr (R > 1) {
+#pragma unroll
+    for (int len = R; len >= 2; len >>= 1) {
+      const int half = len >> 1;
+#pragma unroll
+      for (int s = 0; s < R; s += len) {
+#pragma unroll
+        for (int k = 0; k < half; ++k) {
+          const float2 a = v[s + k], b = v[s + k + half];
+          v[s + k] = cadd(a, b);
+          v[s + k + half] = twiddle32<DIR>(csub(a, b), k * (32 / len));
+        }
+      }
+    }
+    float2 t[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) t[i] = v[bitrev<R>(i)];
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = t[i];
+  }
+}
+
+template <int N> struct Split;
+template <> struct Split<4> { static constexpr int R1 = 4, R2 = 1; };
+template <> struct Split<8> { static constexpr int R1 = 8, R2 = 1; };
+template <> struct Split<16> { static constexpr int R1 = 16, R2 = 1; };
+template <> struct Split<32> { static constexpr int R1 = 32, R2 = 1; };
+template <> struct Split<64> { static constexpr int R1 = 8, R2 = 8; };
+template <> struct Split<128> { static constexpr int R1 = 16, R2 = 8; };
+template <> struct Split<256> { static constexpr int R1 = 16, R2 = 16; };
+template <> struct Split<512> { static constexpr int R1 = 32, R2 = 16; };
+template <> struct Split<1024> { static constexpr int R1 = 32, R2 = 32; };
+
+// Columns per workgroup tile of the strided passes.
+template <int N> struct Cols { static constexpr int M = N >= 1024 ? 8 : 16; };
+
+// twiddle exp(DIR 2 pi i e / N) from the table of exp(-2 pi i k / N)
+template <int DIR>
+__device__ __forceinline__ float2 tw_get(const float2* __restrict__ tw, int e) {
+  const float2 w = tw[e];
+  return DIR < 0 ? w : cconj(w);
+}
+
+// blockIdx -> tile index so that consecutive tiles of one launch land on the
+// same XCD (workgroups are dispatched round-robin over the 8 XCDs, each with
+// its own L2): neighbouring column tiles share cache lines.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7;
+  const int xcd = b & 7, slot = b >> 3;
+  return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+}
+
+// ===========================================================================
+// Strided (column-tile) pass: element (batch b, row n, column c) at
+//   data + b*sb + n*sn + c,  n in [0, N), c in [0, ncols)
+// ===========================================================================
+struct ColGeom {
+  long sb, sn;
+  int ncols, ntc;   // columns, column tiles per batch
+};
+
+template <int N, int M>
+struct ColLds {
+  static constexpr int R1 = Split<N>::R1, R2 = Split<N>::R2;
+  // forward exchange [l1][j2][m] with a padded l1 stride; the inverse
+  // exchange of the fused pass uses [l1'][l1][m] (R2 x R1)
+  static constexpr int SA = R2 * M + M;
+  static constexpr int SB = R1 * M + M;
+  static constexpr int size = (R2 > 1) ? (R1 * SA > R2 * SB ? R1 * SA : R2 * SB) : 1;
+};
+
+// One launch covers the main arrays (tiles [0, nb_main)) and the Nyquist
+// planes (the remaining tiles) of up to three fields (blockIdx.y).
+struct ColPass {
+  float2* main[3];
+  float2* plane[3];
+  ColGeom gm, gp;
+  int nb_main;
+};
+
+template <int N, int M, int DIR>
+__global__ __launch_bounds__(kThreads) void k_fft_cols(ColPass p, const float2* __restrict__ tw) {
+  constexpr int R1 = Split<N>::R1, R2 = Split<N>::R2;
+  constexpr int IA = (M * R2 + kThreads - 1) / kThreads;
+  constexpr int IB = (M * R1 + kThreads - 1) / kThreads;
+  __shared__ float2 lds[ColLds<N, M>::size];
+  int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const bool is_plane = tile >= p.nb_main;
+  if (is_plane) tile -= p.nb_main;
+  const ColGeom& g = is_plane ? p.gp : p.gm;
+  float2* data = is_plane ? p.plane[blockIdx.y] : p.main[blockIdx.y];
+  const int b = tile / g.ntc;
+  const int c0 = (tile - b * g.ntc) * M;
+  float2* base = data + b * g.sb + c0;
+  const int tid = threadIdx.x;
+
+  if constexpr (R2 == 1) {
+#pragma unroll
+    for (int i = 0; i < IA; ++i) {
+      const int it = tid + i * kThreads;
+      const int m = it % M;
+      if (it < M && c0 + m < g.ncols) {
+        float2 v[R1];
+#pragma unroll
+        for (int j = 0; j < R1; ++j) v[j] = base[j * g.sn + m];
+        dft<R1, DIR>(v);
+#pragma unroll
+        for (int j = 0; j < R1; ++j) base[j * g.sn + m] = v[j];
+      }
+    }
+  } else {
+    constexpr int SA = ColLds<N, M>::SA;
+#pragma unroll
+    for (int i = 0; i < IA; ++i) {
+      const int it = tid + i * kThreads;
+      if (it < M * R2) {
+        const int m = it % M, j2 = it / M;
+        const bool ok = c0 + m < g.ncols;
+        float2 v[R1];
+#pragma unroll
+        for (int j1 = 0; j1 < R1; ++j1) v[j1] = ok ? base[(R2 * j1 + j2) * g.sn + m] : make_float2(0.f, 0.f);
+        dft<R1, DIR>(v);
+#pragma unroll
+        for (int l1 = 0; l1 < R1; ++l1) {
+          const float2 w = l1 == 0 ? v[l1] : cmul(v[l1], tw_get<DIR>(tw, j2 * l1));
+          lds[l1 * SA + j2 * M + m] = w;
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < IB; ++i) {
+      const int it = tid + i * kThreads;
+      if (it < M * R1) {
+        const int m = it % M, l1 = it / M;
+        float2 v[R2];
+#pragma unroll
+        for (int j2 = 0; j2 < R2; ++j2) v[j2] = lds[l1 * SA + j2 * M + m];
+        dft<R2, DIR>(v);
+        if (c0 + m < g.ncols) {
+#pragma unroll
+          for (int l2 = 0; l2 < R2; ++l2) base[(l1 + R1 * l2) * g.sn + m] = v[l2];
+        }
+      }
+    }
+  }
+}
+
+// ===========================================================================
+// Contiguous z passes.  Line l of the real mesh holds N floats at r + l*N,
+// i.e. H = N/2 complex values at c + l*H.
+// ===========================================================================
+template <int N>
+struct ZGeom {
+  static constexpr int H = N / 2;
+  static constexpr int R1 = Split<H>::R1, R2 = Split<H>::R2;
+  static constexpr int L0 = 8192 / H;
+  static constexpr int L = L0 < N * N ? L0 : N * N;       // lines per workgroup
+  static constexpr int P = R2 + 1;                          // padded j2 stride
+  static constexpr int XS = (R2 > 1) ? L * R1 * P : 1;      // exchange size
+  static constexpr int ZS = L * (H + 1);                    // natural-order Z
+  static constexpr int size = XS > ZS ? XS : ZS;
+};
+
+// stage A + B of a length-H complex transform of L contiguous lines whose
+// element (line m, index n) is produced by load(m, n); the result
+// Z[m][k] is written into lds at m*(H+1) + k (natural order).
+template <int N, int DIR, class Load>
+__device__ __forceinline__ void zline_transform(float2* lds, const float2* __restrict__ twh, Load load) {
+  using G = ZGeom<N>;
+  constexpr int H = G::H, R1 = G::R1, R2 = G::R2, L = G::L;
+  constexpr int IA = (L * R2 + kThreads - 1) / kThreads;
+  constexpr int IB = (L * R1 + kThreads - 1) / kThreads;
+  const int tid = threadIdx.x;
+  if constexpr (R2 == 1) {
+    float2 v[IA][R1];
+#pragma unroll
+    for (int i = 0; i < IA; ++i) {
+      const int m = tid + i * kThreads;
+      if (m < L) {
+#pragma unroll
+        for (int j = 0; j < R1; ++j) v[i][j] = load(m, j);
+        dft<R1, DIR>(v[i]);
+      }
+    }
+    __syncthreads();   // callers may reuse lds they read before
+#pragma unroll
+    for (int i = 0; i < IA; ++i) {
+      const int m = tid + i * kThreads;
+      if (m < L) {
+#pragma unroll
+        for (int j = 0; j < R1; ++j) lds[m * (H + 1) + j] = v[i][j];
+      }
+    }
+  } else {
+    constexpr int P = G::P;
+#pragma unroll
+    for (int i = 0; i < IA; ++i) {
+      const int it = tid + i * kThreads;
+      if (it < L * R2) {
+        const int j2 = it % R2, m = it / R2;
+        float2 v[R1];
+#pragma unroll
+        for (int j1 = 0; j1 < R1; ++j1) v[j1] = load(m, R2 * j1 + j2);
+        dft<R1, DIR>(v);
+#pragma unroll
+        for (int l1 = 0; l1 < R1; ++l1) {
+          const float2 w = l1 == 0 ? v[l1] : cmul(v[l1], tw_get<DIR>(twh, j2 * l1));
+          lds[(m * R1 + l1) * P + j2] = w;
+        }
+      }
+    }
+    __syncthreads();
+    float2 v[IB][R2];
+#pragma unroll
+    for (int i = 0; i < IB; ++i) {
+      const int it = tid + i * kThreads;
+      if (it < L * R1) {
+        const int l1 = it % R1, m = it / R1;
+#pragma unroll
+        for (int j2 = 0; j2 < R2; ++j2) v[i][j2] = lds[(m * R1 + l1) * P + j2];
+        dft<R2, DIR>(v[i]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < IB; ++i) {
+      const int it = tid + i * kThreads;
+      if (it < L * R1) {
+        const int l1 = it % R1, m = it / R1;
+#pragma unroll
+        for (int l2 = 0; l2 < R2; ++l2) lds[m * (H + 1) + l1 + R1 * l2] = v[i][l2];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Real-to-complex along z: N reals -> X[0..N/2-1] in place + X[N/2] to q.
+template <int N>
+__global__ __launch_bounds__(kThreads) void k_r2c_z(float* __restrict__ r0, float* __restrict__ r1,
+                                                     float* __restrict__ r2, float2* __restrict__ q0,
+                                                     float2* __restrict__ q1, float2* __restrict__ q2,
+                                                     const float2* __restrict__ twh,
+                                                     const float2* __restrict__ twn) {
+  using G = ZGeom<N>;
+  constexpr int H = G::H, L = G::L;
+  __shared__ float2 lds[G::size];
+  float* r = blockIdx.y == 0 ? r0 : (blockIdx.y == 1 ? r1 : r2);
+  float2* q = blockIdx.y == 0 ? q0 : (blockIdx.y == 1 ? q1 : q2);
+  const long line0 = (long)xcd_tile(blockIdx.x, gridDim.x) * L;
+  float2* c = reinterpret_cast<float2*>(r) + line0 * H;
+  zline_transform<N, -1>(lds, twh, [&](int m, int n) { return c[(long)m * H + n]; });
+  // post-processing: X[k] = E + w^k O, X[H-k] = conj(E - w^k O)
+  constexpr int NK = H / 2 + 1;
+  for (int it = threadIdx.x; it < L * NK; it += kThreads) {
+    const int k = it % NK, m = it / NK;
+    const float2 zk = lds[m * (H + 1) + k];
+    const float2 zm = cconj(lds[m * (H + 1) + ((H - k) & (H - 1))]);
+    const float2 e = cscale(cadd(zk, zm), 0.5f);
+    const float2 dif = csub(zk, zm);
+    const float2 o = make_float2(0.5f * dif.y, -0.5f * dif.x);   // (zk - zm) / (2i)
+    const float2 t = cmul(o, twn[k]);
+    float2* out = c + (long)m * H;
+    if (k == 0) {
+      out[0] = make_float2(e.x + t.x, 0.f);
+      q[line0 + m] = make_float2(e.x - t.x, 0.f);
+    } else {
+      out[k] = cadd(e, t);
+      if (k != H - k) out[H - k] = cconj(csub(e, t));
+    }
+  }
+}
+
+// Complex-to-real along z (unnormalised): X[0..N/2] -> N reals in place.
+// The imaginary parts of X[0] and X[N/2] are discarded.
+template <int N>
+__global__ __launch_bounds__(kThreads) void k_c2r_z(float* __restrict__ r0, float* __restrict__ r1,
+                                                     float* __restrict__ r2, const float2* __restrict__ q0,
+                                                     const float2* __restrict__ q1, const float2* __restrict__ q2,
+                                                     const float2* __restrict__ twh,
+                                                     const float2* __restrict__ twn) {
+  using G = ZGeom<N>;
+  constexpr int H = G::H, L = G::L;
+  __shared__ float2 lds[G::size];
+  float* r = blockIdx.y == 0 ? r0 : (blockIdx.y == 1 ? r1 : r2);
+  const float2* q = blockIdx.y == 0 ? q0 : (blockIdx.y == 1 ? q1 : q2);
+  const long line0 = (long)xcd_tile(blockIdx.x, gridDim.x) * L;
+  float2* c = reinterpret_cast<float2*>(r) + line0 * H;
+  auto load = [&](int m, int k) {
+    const float2* line = c + (long)m * H;
+    float2 a, b;
+    if (k == 0) {
+      a = make_float2(line[0].x, 0.f);
+      b = make_float2(q[line0 + m].x, 0.f);
+    } else {
+      a = line[k];
+      b = cconj(line[H - k]);
+    }
+    const float2 e = cadd(a, b);
+    const float2 o = cmulc(csub(a, b), twn[k]);     // (a - b) exp(+2 pi i k / N)
+    return make_float2(e.x - o.y, e.y + o.x);       // e + i o
+  };
+  zline_transform<N, +1>(lds, twh, load);
+  for (int it = threadIdx.x; it < L * H; it += kThreads) {
+    const int j = it % H, m = it / H;
+    c[(long)m * H + j] = lds[m * (H + 1) + j];      // (x[2j], x[2j+1])
+  }
+}
+
+// ===========================================================================
+// Fused x pass: forward x transform, spectral op, inverse x transform(s).
+// Geometry as in k_fft_cols with rows n = kx.  mode 0: the main array
+// (b = ky, c = kz < N/2); mode 1: the Nyquist plane (b = 0, c = ky, kz = N/2).
+// ===========================================================================
+struct FusedArgs {
+  SpecOp op;
+  ColGeom gm, gp;          // main array (mode 0) and Nyquist plane (mode 1)
+  int nb_main;
+  const float2* in_main;   // input spectrum (forward-y transformed)
+  const float2* in_nyq;
+  FftTables t;
+};
+
+template <int N>
+__device__ __forceinline__ int sfreq(int n) { return n < N / 2 ? n : n - N; }
+
+// Spectral multiplier m(k) of fan-out output o, or of fan-in input o (then
+// the multiplier returned is already the conjugate used by the transpose),
+// at mode (kx, ky, kz): kx, ky in [0, N) with numpy's signed-frequency
+// convention, kz in [0, N/2].
+template <int N>
+__device__ __forceinline__ float2 spec_mult(const SpecOp& op, const FftTables& t, int o, int kx, int ky, int kz,
+                                            float2 x) {
+  const float kk = t.kxy[kx] + t.kxy[ky] + t.kz[kz];
+  const float inv = kk > 0.f ? 1.f / kk : 0.f;
+  const float d0 = t.dxy[kx], d1 = t.dxy[ky], d2 = t.dz[kz];
+  auto dsel = [&](int d) { return d == 0 ? d0 : (d == 1 ? d1 : d2); };
+  auto pk = [&]() {
+    const int fx = sfreq<N>(kx), fy = sfreq<N>(ky);
+    return op.pk[fx * fx + fy * fy + kz * kz];
+  };
+  auto phi_pair = [&](int c) {   // xx, yy, zz, xy, xz, yz
+    switch (c) {
+      case 0: return d0 * d0;
+      case 1: return d1 * d1;
+      case 2: return d2 * d2;
+      case 3: return d0 * d1;
+      case 4: return d0 * d2;
+      default: return d1 * d2;
+    }
+  };
+  switch (op.kind) {
+    case OP_IDENTITY:
+      return cscale(x, op.scale);
+    case OP_LINEAR:
+      return cscale(x, pk());
+    case OP_FORCE:
+    case OP_FORCE_T: {
+      float g = op.scale * inv;
+      if (op.deconv) {
+        const float w = t.wxy[kx] * t.wxy[ky] * t.wz[kz];
+        g /= (op.deconv == 1 ? w : w * w);
+      }
+      if (op.split) {
+        const float sv = t.sxy[kx] * t.sxy[ky] * t.sz[kz];
+        g *= (op.split == 1 ? sv : 1.f - sv);
+      }
+      const float2 v = cscale(x, dsel(o) * g);
+      return op.kind == OP_FORCE ? cmul_i<1>(v) : cmul_i<-1>(v);   // i D g, conj = -i D g
+    }
+    case OP_LPT1: {
+      const float2 dl = cscale(x, pk() * inv);
+      if (o < 3) return cmul_i<1>(cscale(dl, dsel(o)));             // s1_d = i D_d delta_L / K^2
+      return cscale(dl, phi_pair(o - 3));                            // phi_ij = D_i D_j delta_L / K^2
+    }
+    case OP_LPT_PHI:
+      return cscale(x, pk() * inv * phi_pair(o));
+    case OP_LPT2:
+      return cmul_i<-1>(cscale(x, dsel(o) * inv * op.scale));       // s2_d = -i D_d delta2 / K^2
+    case OP_LPT2_T:
+      return cmul_i<1>(cscale(x, dsel(o) * inv * op.scale));        // conj(-i D_d s / K^2)
+    case OP_LPT1_T: {
+      const float2 v = cscale(x, pk() * inv);
+      if (o < 3) return cmul_i<-1>(cscale(v, dsel(o)));              // conj(i D_d / K^2)
+      return cscale(v, phi_pair(o - 3));
+    }
+    default:
+      return make_float2(0.f, 0.f);
+  }
+}
+
+template <int N, int M, bool FANIN>
+__global__ __launch_bounds__(kThreads) void k_fft_x_fused(FusedArgs a) {
+  constexpr int R1 = Split<N>::R1, R2 = Split<N>::R2;
+  constexpr int IA = (M * R2 + kThreads - 1) / kThreads;   // stage A and inverse stage B'
+  constexpr int IB = (M * R1 + kThreads - 1) / kThreads;   // stage B and inverse stage A'
+  constexpr int SA = ColLds<N, M>::SA, SB = ColLds<N, M>::SB;
+  __shared__ float2 lds[ColLds<N, M>::size];
+  int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int mode = tile >= a.nb_main ? 1 : 0;
+  if (mode) tile -= a.nb_main;
+  const ColGeom& g = mode ? a.gp : a.gm;
+  const int b = tile / g.ntc;
+  const int c0 = (tile - b * g.ntc) * M;
+  const long off = b * g.sb + c0;
+  const int tid = threadIdx.x;
+  const SpecOp& op = a.op;
+  const FftTables& t = a.t;
+  const int nin = FANIN ? op.n_in : 1;
+  const int nout = FANIN ? 1 : op.n_out;
+  auto src_of = [&](int in) -> const float2* {
+    if (FANIN) return (mode == 0 ? op.in_c[in] : op.in_q[in]) + off;
+    return (mode == 0 ? a.in_main : a.in_nyq) + off;
+  };
+  auto dst_of = [&](int o) -> float2* { return (mode == 0 ? op.out_c[o] : op.out_q[o]) + off; };
+  auto freq = [&](int m, int& ky, int& kz) {
+    if (mode == 0) { ky = b; kz = c0 + m; }
+    else { ky = c0 + m; kz = N / 2; }
+  };
+
+  if constexpr (R2 == 1) {
+    // N <= 32: a whole column fits in one thread's registers
+#pragma unroll
+    for (int i = 0; i < IA; ++i) {
+      const int m = tid + i * kThreads;
+      if (m < M && c0 + m < g.ncols) {
+        int ky, kz;
+        freq(m, ky, kz);
+        float2 X[R1], Y[R1];
+#pragma unroll
+        for (int j = 0; j < R1; ++j) Y[j] = make_float2(0.f, 0.f);
+        for (int in = 0; in < nin; ++in) {
+          const float2* src = src_of(in);
+#pragma unroll
+          for (int j = 0; j < R1; ++j) X[j] = src[j * g.sn + m];
+          dft<R1, -1>(X);
+          if (FANIN) {
+#pragma unroll
+            for (int kx = 0; kx < R1; ++kx) Y[kx] = cadd(Y[kx], spec_mult<N>(op, t, in, kx, ky, kz, X[kx]));
+          }
+        }
+        for (int o = 0; o < nout; ++o) {
+          float2 y[R1];
+#pragma unroll
+          for (int kx = 0; kx < R1; ++kx) y[kx] = FANIN ? Y[kx] : spec_mult<N>(op, t, o, kx, ky, kz, X[kx]);
+          dft<R1, 1>(y);
+          float2* dst = dst_of(o);
+#pragma unroll
+          for (int j = 0; j < R1; ++j) dst[j * g.sn + m] = y[j];
+        }
+      }
+    }
+    return;
+  } else {
+    // X: forward transform of the current input (kx = l1 + R1*l2 of item
+    // (m, l1)); Y: fan-in accumulator
+    float2 X[IB][R2], Y[IB][R2];
+#pragma unroll
+    for (int i = 0; i < IB; ++i)
+#pragma unroll
+      for (int l2 = 0; l2 < R2; ++l2) Y[i][l2] = make_float2(0.f, 0.f);
+    for (int in = 0; in < nin; ++in) {
+      const float2* src = src_of(in);
+#pragma unroll
+      for (int i = 0; i < IA; ++i) {
+        const int it = tid + i * kThreads;
+        if (it < M * R2) {
+          const int m = it % M, j2 = it / M;
+          const bool ok = c0 + m < g.ncols;
+          float2 v[R1];
+#pragma unroll
+          for (int j1 = 0; j1 < R1; ++j1) v[j1] = ok ? src[(R2 * j1 + j2) * g.sn + m] : make_float2(0.f, 0.f);
+          dft<R1, -1>(v);
+#pragma unroll
+          for (int l1 = 0; l1 < R1; ++l1)
+            lds[l1 * SA + j2 * M + m] = l1 == 0 ? v[l1] : cmul(v[l1], tw_get<-1>(t.tw_n, j2 * l1));
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < IB; ++i) {
+        const int it = tid + i * kThreads;
+        if (it < M * R1) {
+          const int m = it % M, l1 = it / M;
+#pragma unroll
+          for (int j2 = 0; j2 < R2; ++j2) X[i][j2] = lds[l1 * SA + j2 * M + m];
+          dft<R2, -1>(X[i]);
+          if (FANIN) {
+            int ky, kz;
+            freq(m, ky, kz);
+            if (c0 + m >= g.ncols) { ky = 0; kz = 0; }
+#pragma unroll
+            for (int l2 = 0; l2 < R2; ++l2)
+              Y[i][l2] = cadd(Y[i][l2], spec_mult<N>(op, t, in, l1 + R1 * l2, ky, kz, X[i][l2]));
+          }
+        }
+      }
+      __syncthreads();
+    }
+    for (int o = 0; o < nout; ++o) {
+      // multiply; inverse stage A' over l2 (R2 points); twiddle; exchange
+#pragma unroll
+      for (int i = 0; i < IB; ++i) {
+        const int it = tid + i * kThreads;
+        if (it < M * R1) {
+          const int m = it % M, l1 = it / M;
+          int ky, kz;
+          freq(m, ky, kz);
+          if (c0 + m >= g.ncols) { ky = 0; kz = 0; }
+          float2 y[R2];
+#pragma unroll
+          for (int l2 = 0; l2 < R2; ++l2)
+            y[l2] = FANIN ? Y[i][l2] : spec_mult<N>(op, t, o, l1 + R1 * l2, ky, kz, X[i][l2]);
+          dft<R2, 1>(y);
+#pragma unroll
+          for (int lp = 0; lp < R2; ++lp)
+            lds[lp * SB + l1 * M + m] = lp == 0 ? y[lp] : cmul(y[lp], tw_get<1>(t.tw_n, l1 * lp));
+        }
+      }
+      __syncthreads();
+      // inverse stage B': item (m, l1') over l1 (R1 points) -> n = l1' + R2*l2'
+      float2* dst = dst_of(o);
+#pragma unroll
+      for (int i = 0; i < IA; ++i) {
+        const int it = tid + i * kThreads;
+        if (it < M * R2) {
+          const int m = it % M, lp = it / M;
+          float2 v[R1];
+#pragma unroll
+          for (int l1 = 0; l1 < R1; ++l1) v[l1] = lds[lp * SB + l1 * M + m];
+          dft<R1, 1>(v);
+          if (c0 + m < g.ncols) {
+#pragma unroll
+            for (int l2p = 0; l2p < R1; ++l2p) dst[(lp + R2 * l2p) * g.sn + m] = v[l2p];
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host-side launch helpers
+// ---------------------------------------------------------------------------
+inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+template <int N, int DIR>
+void launch_cols(float2* const* dm, float2* const* dq, int nf, ColGeom gm, int nbm, ColGeom gp, int nbp,
+                 const float2* tw, hipStream_t s) {
+  constexpr int M = Cols<N>::M;
+  ColPass p;
+  for (int i = 0; i < 3; ++i) {
+    p.main[i] = dm[i < nf ? i : 0];
+    p.plane[i] = dq[i < nf ? i : 0];
+  }
+  gm.ntc = cdiv(gm.ncols, M);
+  gp.ntc = cdiv(gp.ncols, M);
+  p.gm = gm;
+  p.gp = gp;
+  p.nb_main = nbm * gm.ntc;
+  dim3 grid(p.nb_main + nbp * gp.ntc, nf);
+  hipLaunchKernelGGL((k_fft_cols<N, M, DIR>), grid, dim3(kThreads), 0, s, p, tw);
+}
+
+// y pass over the main arrays and the Nyquist planes of nf fields
+template <int N, int DIR>
+void ypass(const FftTables& t, Field* f, int nf, hipStream_t s) {
+  float2* dm[3];
+  float2* dq[3];
+  for (int i = 0; i < nf; ++i) { dm[i] = f[i].c(); dq[i] = f[i].q; }
+  // main: element (b = x, n = y, c = z): sb = N*N/2, sn = N/2, ncols = N/2
+  // Nyquist plane q[x][y]: lines along y are contiguous: (b = x, n = y, c = 0)
+  launch_cols<N, DIR>(dm, dq, nf, ColGeom{(long)N * (N / 2), N / 2, N / 2, 0}, N, ColGeom{(long)N, 1, 1, 0}, N,
+                      t.tw_n, s);
+}
+
+template <int N, int DIR>
+void xpass(const FftTables& t, Field* f, int nf, hipStream_t s) {
+  float2* dm[3];
+  float2* dq[3];
+  for (int i = 0; i < nf; ++i) { dm[i] = f[i].c(); dq[i] = f[i].q; }
+  // main: element (b = y, n = x, c = z): sb = N/2, sn = N*N/2
+  // Nyquist plane: (b = 0, n = x, c = y): sn = N
+  launch_cols<N, DIR>(dm, dq, nf, ColGeom{(long)N / 2, (long)N * (N / 2), N / 2, 0}, N, ColGeom{0, (long)N, N, 0},
+                      1, t.tw_n, s);
+}
+
+template <int N>
+void zr2c(const FftTables& t, Field* f, int nf, hipStream_t s) {
+  using G = ZGeom<N>;
+  dim3 grid((N * N) / G::L, nf);
+  hipLaunchKernelGGL((k_r2c_z<N>), grid, dim3(kThreads), 0, s, f[0].r, nf > 1 ? f[1].r : f[0].r,
+                     nf > 2 ? f[2].r : f[0].r, f[0].q, nf > 1 ? f[1].q : f[0].q, nf > 2 ? f[2].q : f[0].q,
+                     t.tw_h, t.tw_n);
+}
+
+template <int N>
+void zc2r(const FftTables& t, Field* f, int nf, hipStream_t s) {
+  using G = ZGeom<N>;
+  dim3 grid((N * N) / G::L, nf);
+  hipLaunchKernelGGL((k_c2r_z<N>), grid, dim3(kThreads), 0, s, f[0].r, nf > 1 ? f[1].r : f[0].r,
+                     nf > 2 ? f[2].r : f[0].r, f[0].q, nf > 1 ? f[1].q : f[0].q, nf > 2 ? f[2].q : f[0].q,
+                     t.tw_h, t.tw_n);
+}
+
+template <int N>
+void xfused(const FftTables& t, const Field& in, const SpecOp& op, hipStream_t s) {
+  constexpr int M = Cols<N>::M;
+  FusedArgs a;
+  a.op = op;
+  a.t = t;
+  a.in_main = in.c();
+  a.in_nyq = in.q;
+  a.gm = ColGeom{(long)N / 2, (long)N * (N / 2), N / 2, cdiv(N / 2, M)};
+  a.gp = ColGeom{0, (long)N, N, cdiv(N, M)};
+  a.nb_main = N * a.gm.ntc;
+  const dim3 grid(a.nb_main + a.gp.ntc);
+  if (op_fan_in(op.kind))
+    hipLaunchKernelGGL((k_fft_x_fused<N, M, true>), grid, dim3(kThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_fft_x_fused<N, M, false>), grid, dim3(kThreads), 0, s, a);
+}
+
+// chunks of at most 3 fields per launch (blockIdx.y selects the field)
+template <class Fn>
+void by3(Field* f, int nf, Fn fn) {
+  for (int i = 0; i < nf; i += 3) fn(f + i, nf - i < 3 ? nf - i : 3);
+}
+
+}  // namespace
+
+#define PM_FFT_SWITCH(n, CALL)                            \
+  switch (n) {                                            \
+    case 8: CALL(8); break;                               \
+    case 16: CALL(16); break;                             \
+    case 32: CALL(32); break;                             \
+    case 64: CALL(64); break;                             \
+    case 128: CALL(128); break;                           \
+    case 256: CALL(256); break;                           \
+    case 512: CALL(512); break;                           \
+    case 1024: CALL(1024); break;                         \
+    default: break;                                       \
+  }
+
+void fft_r2c_zy(const FftTables& t, Field* f, int nf, hipStream_t s) {
+  by3(f, nf, [&](Field* g, int k) {
+#define CALL(N) zr2c<N>(t, g, k, s); ypass<N, -1>(t, g, k, s)
+    PM_FFT_SWITCH(t.n, CALL)
+#undef CALL
+  });
+}
+
+void fft_z_r2c(const FftTables& t, Field* f, int nf, hipStream_t s) {
+  by3(f, nf, [&](Field* g, int k) {
+#define CALL(N) zr2c<N>(t, g, k, s)
+    PM_FFT_SWITCH(t.n, CALL)
+#undef CALL
+  });
+}
+
+void fft_y(const FftTables& t, Field* f, int nf, int dir, hipStream_t s) {
+  by3(f, nf, [&](Field* g, int k) {
+#define CALL(N) (dir < 0 ? ypass<N, -1>(t, g, k, s) : ypass<N, 1>(t, g, k, s))
+    PM_FFT_SWITCH(t.n, CALL)
+#undef CALL
+  });
+}
+
+void fft_z_c2r(const FftTables& t, Field* f, int nf, hipStream_t s) {
+  by3(f, nf, [&](Field* g, int k) {
+#define CALL(N) zc2r<N>(t, g, k, s)
+    PM_FFT_SWITCH(t.n, CALL)
+#undef CALL
+  });
+}
+
+void fft_x_forward(const FftTables& t, Field* f, int nf, hipStream_t s) {
+  by3(f, nf, [&](Field* g, int k) {
+#define CALL(N) xpass<N, -1>(t, g, k, s)
+    PM_FFT_SWITCH(t.n, CALL)
+#undef CALL
+  });
+}
+
+void fft_x_inverse(const FftTables& t, Field* f, int nf, hipStream_t s) {
+  by3(f, nf, [&](Field* g, int k) {
+#define CALL(N) xpass<N, 1>(t, g, k, s)
+    PM_FFT_SWITCH(t.n, CALL)
+#undef CALL
+  });
+}
+
+void fft_x_fused(const FftTables& t, const Field& in, const SpecOp& op, hipStream_t s) {
+#define CALL(N) xfused<N>(t, in, op, s)
+  PM_FFT_SWITCH(t.n, CALL)
+#undef CALL
+}
+
+void fft_c2r_yz(const FftTables& t, Field* f, int nf, hipStream_t s) {
+  by3(f, nf, [&](Field* g, int k) {
+#define CALL(N) ypass<N, 1>(t, g, k, s); zc2r<N>(t, g, k, s)
+    PM_FFT_SWITCH(t.n, CALL)
+#undef CALL
+  });
+}
+
+}  // namespace pmk

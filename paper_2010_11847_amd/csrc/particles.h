@@ -1,0 +1,120 @@
+// Launchers and argument blocks of the particle-side kernels (particles.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace pmk {
+
+struct TileGeom {
+  int n = 0;        // mesh cells per side
+  int t = 0;        // tile side in cells
+  int nt = 0;       // tiles per side
+  int ntiles = 0;   // nt^3
+};
+
+struct LptParticleArgs {
+  int np = 0;             // particles per side
+  int ratio = 1;          // B = n_mesh / n_part
+  float shift = 0.f;
+  float nmesh = 0.f;
+  float cx1 = 0.f, cx2 = 0.f;   // B D1, B D2
+  float cp1 = 0.f, cp2 = 0.f;   // B a0^2 E f1 D1, B a0^2 E f2 D2
+  const float* s1[3] = {};      // device pointers, passed by value
+  const float* s2[3] = {};      // device pointers; used when has_s2
+  int has_s2 = 0;
+  float* pos = nullptr;
+  float* mom = nullptr;
+};
+
+struct ScatterArgs {
+  long np = 0;
+  const float* pos = nullptr;
+  const float* mom = nullptr;      // may be null
+  const uint32_t* id = nullptr;    // null: identity
+  const uint32_t* key = nullptr;
+  const uint32_t* rank = nullptr;
+  const uint32_t* off = nullptr;
+  float* pos_out = nullptr;
+  float* mom_out = nullptr;
+  uint32_t* id_out = nullptr;
+};
+
+enum ReadoutFlags : int {
+  RO_KICK = 1,           // p += F kick_a; (checkpoint); p += F kick_b
+  RO_DRIFT = 2,          // x += p drift, wrapped
+  RO_WRITE_SORTED = 4,   // write x, p back in sorted order
+  RO_XP_BYID = 8,        // write x, p to pos_out/mom_out at the particle id
+  RO_FORCE_BYID = 16,    // write F to force_out at the particle id
+  RO_KEYS = 32,          // tile key and rank of the new position
+  RO_CKPT = 64,          // write x and p (after kick_a) to ckpt_x/ckpt_p at the id
+};
+
+struct ReadoutArgs {
+  TileGeom g;
+  float* pos = nullptr;            // sorted
+  float* mom = nullptr;            // sorted, may be null
+  const uint32_t* id = nullptr;    // sorted ids
+  const uint32_t* off = nullptr;   // bin offsets
+  const float* f0 = nullptr;
+  const float* f1 = nullptr;
+  const float* f2 = nullptr;
+  float kick_a = 0.f, kick_b = 0.f, drift = 0.f;
+  int flags = 0;
+  float* force_out = nullptr;
+  float* pos_out = nullptr;
+  float* mom_out = nullptr;
+  float* ckpt_x = nullptr;
+  float* ckpt_p = nullptr;
+  uint32_t* key_out = nullptr;
+  uint32_t* rank_out = nullptr;
+  uint32_t* count = nullptr;
+};
+
+struct PowerArgs {
+  int n = 0;
+  int n_bins = 0;
+  int n_max = 0;
+  int deconv = 0;
+  const float2* c = nullptr;
+  const float2* q = nullptr;
+  const float* wxy = nullptr;
+  const float* wz = nullptr;
+  double* partial = nullptr;
+};
+
+void launch_noise(uint64_t seed, long n, float* out, hipStream_t s);
+void launch_lpt_delta2(float* const* phi6, long n, float* out, hipStream_t s);
+void launch_lpt_particles(const LptParticleArgs& a, hipStream_t s);
+void launch_fill_u32(uint32_t* p, long n, uint32_t v, hipStream_t s);
+void launch_keys(const float* pos, long np, const TileGeom& g, uint32_t* key, uint32_t* rank, uint32_t* count,
+                 hipStream_t s);
+long scan_scratch_words(long n);
+void launch_scan(const uint32_t* count, long n, uint32_t* off, uint32_t* bsum, hipStream_t s);
+void launch_scatter(const ScatterArgs& a, hipStream_t s);
+void launch_paint(const float* pos_sorted, const uint32_t* off, const TileGeom& g, float* out, float scale,
+                  float offset, hipStream_t s);
+void launch_readout(const ReadoutArgs& a, hipStream_t s);
+void launch_kick_drift(float* pos, float* mom, const float* f, long np, float kick, float drift, float nmesh,
+                       hipStream_t s);
+void launch_spec_to_numpy(const float2* c, const float2* q, float2* out, int n, float scale, hipStream_t s);
+void launch_spec_from_numpy(const float2* in, float2* c, float2* q, int n, float scale, hipStream_t s);
+void launch_scale(float* p, long n, float v, hipStream_t s);
+// adjoint kernels (adjoint.hip)
+void launch_paint3w(const float* pos, const uint32_t* id, const uint32_t* off, const TileGeom& g, const float* pbar,
+                    float k, float* o0, float* o1, float* o2, hipStream_t s);
+void launch_readout_grad3(const float* pos, const uint32_t* id, const uint32_t* off, const TileGeom& g,
+                          const float* m0, const float* m1, const float* m2, const float* pbar, float k, float* xbar,
+                          hipStream_t s);
+void launch_readout_grad1(const float* pos, const uint32_t* id, const uint32_t* off, const TileGeom& g,
+                          const float* m0, float k, float* xbar, hipStream_t s);
+void launch_axpy(float* y, const float* x, float a, long n, hipStream_t s);
+void launch_lpt_sbar(const float* xbar, const float* pbar, long n3, float cx1, float cp1, float cx2, float cp2,
+                     float* const* s1, float* const* s2, hipStream_t s);
+void launch_lpt_phibar(float* const* phi6, const float* d2b, long n3, hipStream_t s);
+int power_max_bins();
+long power_partial_doubles(int n_bins);
+void launch_power(const PowerArgs& a, double* out3, hipStream_t s);
+
+}  // namespace pmk

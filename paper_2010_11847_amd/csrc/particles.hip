@@ -1,0 +1,523 @@
+// Particle-side kernels of the PM step for gfx950: white noise, LPT particle
+// assembly, counting sort by tile, LDS-tiled CIC paint, LDS-tiled CIC readout
+// fused with the kick and drift updates, and the binned power spectrum.
+//
+// Tiles.  The mesh is cut into T^3-cell tiles.  A particle whose CIC base
+// cell floor(x) lies in tile t gets key 8*t + c, where the class bit c_d is
+// set when floor(x_d) is the last cell of the tile along d, i.e. when the
+// particle also deposits into the next tile along d.  A counting sort by key
+// groups the particles of every tile in 8 contiguous bins.
+//  - Paint: the workgroup of tile t accumulates, in LDS, its own particles
+//    and those particles of the 7 lower neighbour tiles whose class says they
+//    reach into t, keeping only the corners inside t.  Every mesh cell is
+//    written once, by its owner, with no global float atomics.
+//  - Readout: the workgroup of tile t stages the (T+1)^3 force values its
+//    particles touch in LDS and interpolates from there.
+#include "particles.h"
+#include "pm_device.h"
+
+namespace pmk {
+namespace {
+
+constexpr int kThreads = 256;
+
+// ---- white noise ------------------------------------------------------------
+// SplitMix64 output of the counter seed*2^40 + i, Box-Muller (cosine branch).
+__global__ void k_noise(uint64_t seed, long n, float* __restrict__ out) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    uint64_t z = seed * (1ull << 40) + (uint64_t)i + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const double u1 = ((double)(z >> 32) + 1.0) * 2.3283064365386963e-10;
+    const double u2 = (double)(z & 0xFFFFFFFFull) * 2.3283064365386963e-10;
+    out[i] = (float)(sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2));
+  }
+}
+
+// ---- LPT -----------------------------------------------------------------------
+// delta2 = phi_xx phi_yy + phi_xx phi_zz + phi_yy phi_zz - phi_xy^2 - phi_xz^2 - phi_yz^2
+__global__ void k_lpt_delta2(const float* __restrict__ xx, const float* __restrict__ yy,
+                             const float* __restrict__ zz, const float* __restrict__ xy,
+                             const float* __restrict__ xz, const float* __restrict__ yz, long n,
+                             float* __restrict__ out) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const float a = xx[i], b = yy[i], c = zz[i], d = xy[i], e = xz[i], f = yz[i];
+    out[i] = a * b + a * c + b * c - d * d - e * e - f * f;
+  }
+}
+
+// x = B q + shift + B (D1 s1 + D2 s2) (wrapped); p = B a0^2 E (f1 D1 s1 + f2 D2 s2)
+__global__ void k_lpt_particles(LptParticleArgs a) {
+  const long n3 = (long)a.np * a.np * a.np;
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n3; i += stride) {
+    const int q[3] = {(int)(i / ((long)a.np * a.np)), (int)((i / a.np) % a.np), (int)(i % a.np)};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const float s1 = a.s1[d][i];
+      const float s2 = a.has_s2 ? a.s2[d][i] : 0.f;
+      const float dx = a.cx1 * s1 + a.cx2 * s2;
+      const float x = (float)(a.ratio * q[d]) + a.shift + dx;
+      a.pos[3 * i + d] = wrap_pos(x, a.nmesh);
+      a.mom[3 * i + d] = a.cp1 * s1 + a.cp2 * s2;
+    }
+  }
+}
+
+// ---- counting sort -------------------------------------------------------------
+__global__ void k_fill_u32(uint32_t* __restrict__ p, long n, uint32_t v) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_keys(const float* __restrict__ pos, long np, TileGeom g,
+                                                   uint32_t* __restrict__ key, uint32_t* __restrict__ rank,
+                                                   uint32_t* __restrict__ count) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i < np;
+  uint32_t k = 0;
+  if (valid) {
+    int ix, iy, iz;
+    float t;
+    cic_base(pos[3 * i + 0], g.n, ix, t);
+    cic_base(pos[3 * i + 1], g.n, iy, t);
+    cic_base(pos[3 * i + 2], g.n, iz, t);
+    k = tile_key(ix, iy, iz, g);
+  }
+  const uint32_t r = agg_rank(count, k, valid);
+  if (valid) {
+    key[i] = k;
+    rank[i] = r;
+  }
+}
+
+// Exclusive scan of count[0..n) into off[0..n], off[n] = total.
+constexpr int kScanItems = 8;
+constexpr int kScanBlock = kThreads * kScanItems;
+
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t& total) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int o = 1; o < kThreads; o <<= 1) {
+    const uint32_t add = tid >= o ? sh[tid - o] : 0u;
+    __syncthreads();
+    sh[tid] += add;
+    __syncthreads();
+  }
+  total = sh[kThreads - 1];
+  const uint32_t incl = sh[tid];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_local(const uint32_t* __restrict__ cnt, long n,
+                                                         uint32_t* __restrict__ off, uint32_t* __restrict__ bsum) {
+  __shared__ uint32_t sh[kThreads];
+  const long base = (long)blockIdx.x * kScanBlock + (long)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    v[j] = base + j < n ? cnt[base + j] : 0u;
+    s += v[j];
+  }
+  uint32_t total;
+  uint32_t run = block_exclusive_scan(s, sh, total);
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    if (base + j < n) off[base + j] = run;
+    run += v[j];
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_top(uint32_t* __restrict__ bsum, int nb) {
+  __shared__ uint32_t sh[kThreads];
+  uint32_t carry = 0;
+  for (int c0 = 0; c0 < nb; c0 += kThreads) {
+    const int i = c0 + threadIdx.x;
+    const uint32_t v = i < nb ? bsum[i] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan(v, sh, total);
+    if (i < nb) bsum[i] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) bsum[nb] = carry;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_add(uint32_t* __restrict__ off, long n,
+                                                       const uint32_t* __restrict__ bsum, int nb) {
+  const long base = (long)blockIdx.x * kScanBlock;
+  const uint32_t add = bsum[blockIdx.x];
+  for (int j = threadIdx.x; j < kScanBlock; j += kThreads)
+    if (base + j < n) off[base + j] += add;
+  if (blockIdx.x == 0 && threadIdx.x == 0) off[n] = bsum[nb];
+}
+
+__global__ void k_scatter(ScatterArgs a) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < a.np; i += stride) {
+    const uint32_t d = a.off[a.key[i]] + a.rank[i];
+    a.pos_out[3 * (long)d + 0] = a.pos[3 * i + 0];
+    a.pos_out[3 * (long)d + 1] = a.pos[3 * i + 1];
+    a.pos_out[3 * (long)d + 2] = a.pos[3 * i + 2];
+    if (a.mom) {
+      a.mom_out[3 * (long)d + 0] = a.mom[3 * i + 0];
+      a.mom_out[3 * (long)d + 1] = a.mom[3 * i + 1];
+      a.mom_out[3 * (long)d + 2] = a.mom[3 * i + 2];
+    }
+    if (a.id_out) a.id_out[d] = a.id ? a.id[i] : (uint32_t)i;
+  }
+}
+
+// ---- paint ---------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_paint(const float* __restrict__ pos, const uint32_t* __restrict__ off,
+                                                    TileGeom g, float* __restrict__ out, float scale, float offset) {
+  __shared__ float acc[kTileMax * kTileMax * kTileMax];
+  const int T = g.t, nt = g.nt, n = g.n;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tz = tile % nt, ty = (tile / nt) % nt, tx = tile / (nt * nt);
+  const int ox = tx * T, oy = ty * T, oz = tz * T;
+  const int cells = T * T * T;
+  for (int c = threadIdx.x; c < cells; c += kThreads) acc[c] = 0.f;
+  __syncthreads();
+  for (int e = 0; e < 8; ++e) {
+    const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
+    const int sx = (tx - ex + nt) % nt, sy = (ty - ey + nt) % nt, sz = (tz - ez + nt) % nt;
+    const uint32_t src = ((uint32_t)sx * nt + sy) * nt + sz;
+    for (int cls = 0; cls < 8; ++cls) {
+      if ((cls & e) != e) continue;
+      const uint32_t b0 = off[src * 8 + cls], b1 = off[src * 8 + cls + 1];
+      for (uint32_t j = b0 + threadIdx.x; j < b1; j += kThreads) {
+        int ix, iy, iz;
+        float fx, fy, fz;
+        cic_base(pos[3 * (long)j + 0], n, ix, fx);
+        cic_base(pos[3 * (long)j + 1], n, iy, fy);
+        cic_base(pos[3 * (long)j + 2], n, iz, fz);
+        // local base cell in [-1, T-1]
+        int lx = (ix - ox) & (n - 1), ly = (iy - oy) & (n - 1), lz = (iz - oz) & (n - 1);
+        if (lx > T) lx -= n;
+        if (ly > T) ly -= n;
+        if (lz > T) lz -= n;
+        const float wx[2] = {1.f - fx, fx}, wy[2] = {1.f - fy, fy}, wz[2] = {1.f - fz, fz};
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          const int cx = lx + a;
+          if (cx < 0 || cx >= T) continue;
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            const int cy = ly + b;
+            if (cy < 0 || cy >= T) continue;
+            const float wxy = wx[a] * wy[b];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+              const int cz = lz + c;
+              if (cz < 0 || cz >= T) continue;
+              atomicAdd(&acc[(cx * T + cy) * T + cz], wxy * wz[c]);
+            }
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < cells; c += kThreads) {
+    const int cz = c % T, cy = (c / T) % T, cx = c / (T * T);
+    out[((long)(ox + cx) * n + (oy + cy)) * n + (oz + cz)] = acc[c] * scale + offset;
+  }
+}
+
+// ---- readout + kick + drift ---------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
+  __shared__ float4 ft[(kTileMax + 1) * (kTileMax + 1) * (kTileMax + 1)];
+  const TileGeom& g = a.g;
+  const int T = g.t, nt = g.nt, n = g.n, T1 = T + 1;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const uint32_t b0 = a.off[tile * 8], b1 = a.off[tile * 8 + 8];
+  if (b0 == b1) return;   // uniform across the workgroup
+  const int tz = tile % nt, ty = (tile / nt) % nt, tx = tile / (nt * nt);
+  const int ox = tx * T, oy = ty * T, oz = tz * T;
+  for (int c = threadIdx.x; c < T1 * T1 * T1; c += kThreads) {
+    const int cz = c % T1, cy = (c / T1) % T1, cx = c / (T1 * T1);
+    const long gi = ((long)((ox + cx) & (n - 1)) * n + ((oy + cy) & (n - 1))) * n + ((oz + cz) & (n - 1));
+    ft[c] = make_float4(a.f0[gi], a.f1[gi], a.f2[gi], 0.f);
+  }
+  __syncthreads();
+  const float nf = (float)n;
+  for (uint32_t base = b0; base < b1; base += kThreads) {
+    const uint32_t j = base + threadIdx.x;
+    const bool valid = j < b1;
+    uint32_t key = 0;
+    if (valid) {
+      float x[3], p[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) x[d] = a.pos[3 * (long)j + d];
+      if (a.mom) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) p[d] = a.mom[3 * (long)j + d];
+      }
+      int ix, iy, iz;
+      float fx, fy, fz;
+      cic_base(x[0], n, ix, fx);
+      cic_base(x[1], n, iy, fy);
+      cic_base(x[2], n, iz, fz);
+      const int lx = (ix - ox) & (n - 1), ly = (iy - oy) & (n - 1), lz = (iz - oz) & (n - 1);
+      const float wx[2] = {1.f - fx, fx}, wy[2] = {1.f - fy, fy}, wz[2] = {1.f - fz, fz};
+      float F[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+      for (int aa = 0; aa < 2; ++aa)
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+          for (int cc = 0; cc < 2; ++cc) {
+            const float w = wx[aa] * wy[bb] * wz[cc];
+            const float4 v = ft[((lx + aa) * T1 + (ly + bb)) * T1 + (lz + cc)];
+            F[0] += w * v.x;
+            F[1] += w * v.y;
+            F[2] += w * v.z;
+          }
+      const uint32_t id = a.id ? a.id[j] : j;
+      if (a.flags & RO_FORCE_BYID) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) a.force_out[3 * (long)id + d] = F[d];
+      }
+      if (a.flags & RO_KICK) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) p[d] += F[d] * a.kick_a;
+      }
+      if (a.flags & RO_CKPT) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          a.ckpt_x[3 * (long)id + d] = x[d];
+          a.ckpt_p[3 * (long)id + d] = p[d];
+        }
+      }
+      if (a.flags & RO_KICK) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) p[d] += F[d] * a.kick_b;
+      }
+      if (a.flags & RO_DRIFT) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) x[d] = wrap_pos(x[d] + p[d] * a.drift, nf);
+      }
+      if (a.flags & RO_WRITE_SORTED) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          a.pos[3 * (long)j + d] = x[d];
+          if (a.mom) a.mom[3 * (long)j + d] = p[d];
+        }
+      }
+      if (a.flags & RO_XP_BYID) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          a.pos_out[3 * (long)id + d] = x[d];
+          a.mom_out[3 * (long)id + d] = p[d];
+        }
+      }
+      if (a.flags & RO_KEYS) {
+        int jx, jy, jz;
+        float t;
+        cic_base(x[0], n, jx, t);
+        cic_base(x[1], n, jy, t);
+        cic_base(x[2], n, jz, t);
+        key = tile_key(jx, jy, jz, g);
+      }
+    }
+    if (a.flags & RO_KEYS) {
+      const uint32_t r = agg_rank(a.count, key, valid);
+      if (valid) {
+        a.key_out[j] = key;
+        a.rank_out[j] = r;
+      }
+    }
+  }
+}
+
+// elementwise kick + drift with a given per-particle force (first half of a
+// standalone KDK step)
+__global__ void k_kick_drift(float* __restrict__ pos, float* __restrict__ mom, const float* __restrict__ f,
+                             long np, float kick, float drift, float nmesh) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += stride) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const float p = mom[3 * i + d] + f[3 * i + d] * kick;
+      mom[3 * i + d] = p;
+      pos[3 * i + d] = wrap_pos(pos[3 * i + d] + p * drift, nmesh);
+    }
+  }
+}
+
+// ---- power spectrum --------------------------------------------------------------
+constexpr int kPowerBins = 512;
+constexpr int kPowerBlocks = 1024;
+
+__global__ __launch_bounds__(kThreads) void k_power_bins(PowerArgs a) {
+  __shared__ double sw[kPowerBins], sk[kPowerBins], sp[kPowerBins];
+  for (int i = threadIdx.x; i < a.n_bins; i += kThreads) sw[i] = sk[i] = sp[i] = 0.0;
+  __syncthreads();
+  const int n = a.n, h = n / 2;
+  const long nmain = (long)n * n * h;
+  const long ntot = nmain + (long)n * n;
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < ntot; i += stride) {
+    int kx, ky, kz;
+    float2 v;
+    if (i < nmain) {
+      kz = (int)(i % h);
+      ky = (int)((i / h) % n);
+      kx = (int)(i / ((long)h * n));
+      v = a.c[i];
+    } else {
+      const long j = i - nmain;
+      ky = (int)(j % n);
+      kx = (int)(j / n);
+      kz = h;
+      v = a.q[j];
+    }
+    const int fx = kx < h ? kx : kx - n, fy = ky < h ? ky : ky - n;
+    if (a.n_max > 0 && (abs(fx) >= a.n_max || abs(fy) >= a.n_max || kz >= a.n_max)) continue;
+    const int n2 = fx * fx + fy * fy + kz * kz;
+    const double mag = sqrt((double)n2);
+    const int bin = (int)floor(mag + 0.5);
+    if (bin < 1 || bin > a.n_bins) continue;
+    const double w = (kz == 0 || kz == h) ? 1.0 : 2.0;
+    double p = (double)v.x * v.x + (double)v.y * v.y;
+    if (a.deconv) {
+      const double win = (double)a.wxy[kx] * a.wxy[ky] * a.wz[kz];
+      p /= win * win;
+    }
+    atomicAdd(&sw[bin - 1], w);
+    atomicAdd(&sk[bin - 1], w * mag);
+    atomicAdd(&sp[bin - 1], w * p);
+  }
+  __syncthreads();
+  double* out = a.partial + (long)blockIdx.x * 3 * a.n_bins;
+  for (int i = threadIdx.x; i < a.n_bins; i += kThreads) {
+    out[i] = sw[i];
+    out[a.n_bins + i] = sk[i];
+    out[2 * a.n_bins + i] = sp[i];
+  }
+}
+
+__global__ void k_power_reduce(const double* __restrict__ partial, int nblocks, int n_bins, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * n_bins) return;
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) s += partial[(long)b * 3 * n_bins + i];
+  out[i] = s;
+}
+
+// [n][n][n/2] + Nyquist plane  <->  [n][n][n/2+1] (numpy rfftn layout)
+__global__ void k_spec_pack(const float2* __restrict__ c, const float2* __restrict__ q, float2* __restrict__ out,
+                            int n, float scale, int to_numpy) {
+  const int h = n / 2;
+  const long total = (long)n * n * (h + 1);
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const int kz = (int)(i % (h + 1));
+    const long line = i / (h + 1);
+    if (to_numpy) {
+      const float2 v = kz < h ? c[line * h + kz] : q[line];
+      out[i] = make_float2(v.x * scale, v.y * scale);
+    } else {
+      float2* dst = kz < h ? const_cast<float2*>(c) + line * h + kz : const_cast<float2*>(q) + line;
+      const float2 v = out[i];
+      *dst = make_float2(v.x * scale, v.y * scale);
+    }
+  }
+}
+
+__global__ void k_scale(float* __restrict__ p, long n, float s) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] *= s;
+}
+
+inline int grid_for(long n, int per = kThreads, int cap = 65536) {
+  long g = (n + per - 1) / per;
+  if (g < 1) g = 1;
+  return (int)(g > cap ? cap : g);
+}
+
+}  // namespace
+
+void launch_noise(uint64_t seed, long n, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_noise, dim3(grid_for(n)), dim3(kThreads), 0, s, seed, n, out);
+}
+
+void launch_lpt_delta2(float* const* phi6, long n, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_lpt_delta2, dim3(grid_for(n)), dim3(kThreads), 0, s, phi6[0], phi6[1], phi6[2], phi6[3],
+                     phi6[4], phi6[5], n, out);
+}
+
+void launch_lpt_particles(const LptParticleArgs& a, hipStream_t s) {
+  const long n3 = (long)a.np * a.np * a.np;
+  hipLaunchKernelGGL(k_lpt_particles, dim3(grid_for(n3)), dim3(kThreads), 0, s, a);
+}
+
+void launch_fill_u32(uint32_t* p, long n, uint32_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n)), dim3(kThreads), 0, s, p, n, v);
+}
+
+void launch_keys(const float* pos, long np, const TileGeom& g, uint32_t* key, uint32_t* rank, uint32_t* count,
+                 hipStream_t s) {
+  const int grid = (int)((np + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(k_keys, dim3(grid), dim3(kThreads), 0, s, pos, np, g, key, rank, count);
+}
+
+long scan_scratch_words(long n) { return (n + kScanBlock - 1) / kScanBlock + 1; }
+
+void launch_scan(const uint32_t* count, long n, uint32_t* off, uint32_t* bsum, hipStream_t s) {
+  const int nb = (int)((n + kScanBlock - 1) / kScanBlock);
+  hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(kThreads), 0, s, count, n, off, bsum);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kThreads), 0, s, bsum, nb);
+  hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kThreads), 0, s, off, n, bsum, nb);
+}
+
+void launch_scatter(const ScatterArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter, dim3(grid_for(a.np)), dim3(kThreads), 0, s, a);
+}
+
+void launch_paint(const float* pos_sorted, const uint32_t* off, const TileGeom& g, float* out, float scale,
+                  float offset, hipStream_t s) {
+  hipLaunchKernelGGL(k_paint, dim3(g.ntiles), dim3(kThreads), 0, s, pos_sorted, off, g, out, scale, offset);
+}
+
+void launch_readout(const ReadoutArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_readout, dim3(a.g.ntiles), dim3(kThreads), 0, s, a);
+}
+
+void launch_kick_drift(float* pos, float* mom, const float* f, long np, float kick, float drift, float nmesh,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_kick_drift, dim3(grid_for(np)), dim3(kThreads), 0, s, pos, mom, f, np, kick, drift, nmesh);
+}
+
+void launch_spec_to_numpy(const float2* c, const float2* q, float2* out, int n, float scale, hipStream_t s) {
+  const long total = (long)n * n * (n / 2 + 1);
+  hipLaunchKernelGGL(k_spec_pack, dim3(grid_for(total)), dim3(kThreads), 0, s, c, q, out, n, scale, 1);
+}
+
+void launch_spec_from_numpy(const float2* in, float2* c, float2* q, int n, float scale, hipStream_t s) {
+  const long total = (long)n * n * (n / 2 + 1);
+  hipLaunchKernelGGL(k_spec_pack, dim3(grid_for(total)), dim3(kThreads), 0, s, c, q, const_cast<float2*>(in), n,
+                     scale, 0);
+}
+
+void launch_scale(float* p, long n, float v, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale, dim3(grid_for(n)), dim3(kThreads), 0, s, p, n, v);
+}
+
+int power_max_bins() { return kPowerBins; }
+long power_partial_doubles(int n_bins) { return (long)kPowerBlocks * 3 * n_bins; }
+
+void launch_power(const PowerArgs& a, double* out3, hipStream_t s) {
+  hipLaunchKernelGGL(k_power_bins, dim3(kPowerBlocks), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL(k_power_reduce, dim3((3 * a.n_bins + 255) / 256), dim3(256), 0, s, a.partial, kPowerBlocks,
+                     a.n_bins, out3);
+}
+
+}  // namespace pmk
