@@ -20,7 +20,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import cosmology as cosmo_mod
-from .pm import omega_axes, laplace_symbol, gradient_symbol, wrap
+from .pm import omega_axes, laplace_symbol, gradient_symbol, wrap, rfftn, irfftn
 
 
 def linear_field_k(noise, box_size, cosmo, fixed_amplitude=False):
@@ -30,7 +30,7 @@ def linear_field_k(noise, box_size, cosmo, fixed_amplitude=False):
     ``fixed_amplitude`` replaces |w^| by sqrt(N^3) (test mode).
     """
     n = noise.shape[0]
-    wk = np.fft.rfftn(np.asarray(noise, dtype=np.float64))
+    wk = rfftn(np.asarray(noise, dtype=np.float64))
     if fixed_amplitude:
         mag = np.abs(wk)
         wk = np.where(mag > 0, wk / np.where(mag > 0, mag, 1.0), 0.0) * np.sqrt(float(n) ** 3)
@@ -58,17 +58,17 @@ def lpt_displacements(dk, order=2):
     k2 = laplace_symbol(*ws)
     inv = np.where(k2 > 0, 1.0 / np.where(k2 > 0, k2, 1.0), 0.0)
     dsym = [gradient_symbol(w) for w in ws]
-    s1 = np.stack([np.fft.irfftn(1j * d * inv * dk, s=shape, axes=(0, 1, 2)) for d in dsym], -1)
+    s1 = np.stack([irfftn(1j * d * inv * dk, shape) for d in dsym], -1)
     if order < 2:
         return s1, np.zeros_like(s1)
     phi = {}
     for i in range(3):
         for j in range(i, 3):
-            phi[i, j] = np.fft.irfftn(dsym[i] * dsym[j] * inv * dk, s=shape, axes=(0, 1, 2))
+            phi[i, j] = irfftn(dsym[i] * dsym[j] * inv * dk, shape)
     delta2 = (phi[0, 0] * phi[1, 1] + phi[0, 0] * phi[2, 2] + phi[1, 1] * phi[2, 2]
               - phi[0, 1] ** 2 - phi[0, 2] ** 2 - phi[1, 2] ** 2)
-    d2k = np.fft.rfftn(delta2)
-    s2 = np.stack([np.fft.irfftn(-1j * d * inv * d2k, s=shape, axes=(0, 1, 2)) for d in dsym], -1)
+    d2k = rfftn(delta2)
+    s2 = np.stack([irfftn(-1j * d * inv * d2k, shape) for d in dsym], -1)
     return s1, s2
 
 

@@ -10,10 +10,26 @@ omega = 2 pi n / N in (-pi, pi], particle mass 1, delta = rho Ng^3/Np - 1.
 from __future__ import annotations
 
 import math
+import os
 
 import numpy as np
+import scipy.fft as sfft
 
 from . import cosmology as cosmo_mod
+
+# threads of the library DFT: the CPUs this process may run on, or
+# ORACLE_FFT_WORKERS; painting and readout are single-threaded NumPy
+_WORKERS = int(os.environ.get("ORACLE_FFT_WORKERS", "0")) or len(os.sched_getaffinity(0)) or 1
+
+
+def rfftn(a):
+    """3D real DFT (unnormalised), library routine (pocketfft)."""
+    return sfft.rfftn(a, axes=(0, 1, 2), workers=_WORKERS)
+
+
+def irfftn(a, shape, overwrite=False):
+    """Inverse of rfftn, normalised by 1/N^3, library routine (pocketfft)."""
+    return sfft.irfftn(a, s=shape, axes=(0, 1, 2), workers=_WORKERS, overwrite_x=overwrite)
 
 SPLIT_NONE, SPLIT_LONG, SPLIT_SHORT = 0, 1, 2
 
@@ -48,6 +64,22 @@ def cic_window(wx, wy, wz):
     def s(w):
         return np.sinc(w / (2 * np.pi))   # numpy sinc(x) = sin(pi x)/(pi x)
     return (s(wx) * s(wy) * s(wz)) ** 2
+
+
+def green_function(n, omega_m, deconv_order=0, split_rs=0.0, split_mode=SPLIT_NONE):
+    """Real part common to the three force multipliers: 1.5 Om / K^2 W^-n S."""
+    wx, wy, wz = omega_axes(n)
+    k2 = laplace_symbol(wx, wy, wz)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        green = np.where(k2 > 0, 1.5 * omega_m / np.where(k2 > 0, k2, 1.0), 0.0)
+    del k2
+    if deconv_order:
+        green /= cic_window(wx, wy, wz) ** deconv_order
+    if split_mode != SPLIT_NONE:
+        kk = wx ** 2 + wy ** 2 + wz ** 2
+        s = np.exp(-kk * split_rs ** 2)
+        green *= (s if split_mode == SPLIT_LONG else 1.0 - s)
+    return green
 
 
 def force_multipliers(n, omega_m, deconv_order=0, split_rs=0.0, split_mode=SPLIT_NONE):
@@ -96,6 +128,7 @@ def paint(x, n, mass=None):
     m = None if mass is None else np.asarray(mass, dtype=np.float64)
     for idx, w, _, _ in _cic_corners(x, n):
         rho += np.bincount(idx, weights=w if m is None else w * m, minlength=n ** 3)
+        del idx, w
     return rho.reshape(n, n, n)
 
 
@@ -110,25 +143,44 @@ def readout(mesh, x):
 
 
 def density_contrast(x, n_mesh, n_particles):
-    return paint(x, n_mesh) * (n_mesh ** 3 / n_particles) - 1.0
+    delta = paint(x, n_mesh)
+    delta *= n_mesh ** 3 / n_particles
+    delta -= 1.0
+    return delta
 
 
 # ---------------------------------------------------------------------------
 # Force (section 2: paint -> FFT -> grad lap^-1 -> inverse FFTs -> readout)
 # ---------------------------------------------------------------------------
 
+def force_mesh(dk, green, d, n):
+    """Force component d on the mesh: IDFT(i D(w_d) green DFT(delta))."""
+    w = omega_axes(n)[d]
+    spec = green * (1j * gradient_symbol(w))
+    spec *= dk
+    return irfftn(spec, (n, n, n), overwrite=True)
+
+
 def force_meshes(delta, omega_m, **kw):
     """Three real force meshes F_d = IDFT(G_d DFT(delta))."""
     n = delta.shape[0]
-    dk = np.fft.rfftn(delta)
-    return [np.fft.irfftn(g * dk, s=delta.shape, axes=(0, 1, 2)) for g in force_multipliers(n, omega_m, **kw)]
+    dk = rfftn(delta)
+    green = green_function(n, omega_m, **kw)
+    return [force_mesh(dk, green, d, n) for d in range(3)]
 
 
 def force(x, n_mesh, n_particles, omega_m, **kw):
-    """Per-particle PM force at positions x (mesh units)."""
+    """Per-particle PM force at positions x (mesh units); one component at a time."""
     delta = density_contrast(x, n_mesh, n_particles)
-    meshes = force_meshes(delta, omega_m, **kw)
-    return np.stack([readout(m, x) for m in meshes], axis=1)
+    dk = rfftn(delta)
+    del delta
+    green = green_function(n_mesh, omega_m, **kw)
+    out = np.empty((len(x), 3))
+    for d in range(3):
+        mesh = force_mesh(dk, green, d, n_mesh)
+        out[:, d] = readout(mesh, x)
+        del mesh
+    return out
 
 
 # ---------------------------------------------------------------------------
