@@ -60,11 +60,38 @@ def cpu_baseline(seconds_hint=20.0):
     t0 = time.perf_counter()
     pm.kdk_run(x, p, w.a_list, w.n_mesh, w.n_particles, w.cosmo.omega_m)
     dt = time.perf_counter() - t0
-    return {"value": w.n_particles * w.n_steps / dt, "unit": "particle-steps/s", "cores": 1,
+    return {"value": w.n_particles * w.n_steps / dt, "unit": "particle-steps/s", "cores": pm._WORKERS,
             "kind": "oracle",
             "sample": f"{w.n_part}^3 particles on {w.n_mesh}^3 mesh, box {w.box_size:g} Mpc/h "
                       f"(same B=2, 1 Mpc/h cell, no-wiggle P(k)), {w.n_steps} KDK steps incl. first force, "
-                      f"{dt:.1f} s wall, NumPy FFT single-threaded"}
+                      f"{dt:.1f} s wall; DFTs on {pm._WORKERS} threads (scipy.fft), paint/readout 1 thread"}
+
+
+def serving_section(n_requests, rate=20.0, seed=5, budget_gb=64.0, slots=4):
+    """Continuous batching vs one-at-a-time on the same Poisson trace."""
+    from paper_2010_11847_amd import serve
+    trace = serve.poisson_trace(n_requests, rate, seed)
+    warm = serve.poisson_trace(24, 1000.0, seed + 1)
+    ex = serve.GpuExecutor(keep_results=False)
+    budget = int(budget_gb * (1 << 30))
+    serve.serve(warm, ex, budget, slots, realtime=False)          # builds the slot contexts
+    cb = serve.serve(trace, ex, budget, slots, realtime=True).summary()
+    print(f"[bench] serving continuous {cb}", file=sys.stderr, flush=True)
+    fifo = serve.serve_fifo(trace, ex, realtime=True).summary()
+    print(f"[bench] serving fifo {fifo}", file=sys.stderr, flush=True)
+    # saturated: the same requests all arriving at once (maximum throughput)
+    burst = [serve.SimRequest(r.rid, r.n_part, r.n_mesh, r.box_size, r.n_steps, r.seed, r.with_grad, 0.0)
+             for r in trace]
+    cb_sat = serve.serve(burst, ex, budget, slots, realtime=True).summary()
+    print(f"[bench] serving burst continuous {cb_sat}", file=sys.stderr, flush=True)
+    fifo_sat = serve.serve_fifo(burst, ex, realtime=True).summary()
+    print(f"[bench] serving burst fifo {fifo_sat}", file=sys.stderr, flush=True)
+    grad = [r for r in trace if r.with_grad]
+    return {"requests": n_requests, "rate_per_s": rate, "arrival_seed": seed, "hbm_budget_gb": budget_gb,
+            "slots_per_class": slots, "grad_requests": len(grad),
+            "mix": "60% fwd 64^3/64^3, 30% fwd+grad 128^3/128^3, 10% fwd 256^3/512^3, 5-10 steps",
+            "poisson": {"continuous": cb, "fifo": fifo},
+            "burst": {"continuous": cb_sat, "fifo": fifo_sat}}
 
 
 def main():
@@ -75,6 +102,10 @@ def main():
     ap.add_argument("--workload", default="pm512_mesh1024_box1024")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-profile", action="store_true", help="skip the event-timed profile pass")
+    ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
+                    help="only run a plain device-to-device copy of GIB GiB (counter calibration) and exit")
+    ap.add_argument("--serve", type=int, default=200,
+                    help="requests of the serving trace (Poisson 20/s); 0 skips the serving section")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs one GPU only: the PM hot path here is the single-GPU share; "
@@ -85,6 +116,17 @@ def main():
     import torch
     from paper_2010_11847_amd import inputs
     from paper_2010_11847_amd.binding import PMContext
+
+    if args.calibrate_copy > 0:
+        n = int(args.calibrate_copy * (1 << 30)) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes_read": 4 * n, "calibrate_copy_bytes_written": 4 * n,
+                          "launches": 3}))
+        return
 
     w = inputs.PRESETS[args.workload]
     dev = torch.device("cuda", 0)
@@ -141,6 +183,12 @@ def main():
                     "bytes_per_launch": nbytes[dom], "avg_launch_ms": kernels[dom]["avg_ms"]}
         print(f"[bench] kernels {json.dumps(kernels)}", file=sys.stderr, flush=True)
 
+    serving = None
+    if args.serve > 0:
+        del ctx, pos, mom, pos0, mom0
+        torch.cuda.empty_cache()
+        serving = serving_section(args.serve)
+
     base = None
     if not args.no_cpu:
         base = cpu_baseline()
@@ -163,6 +211,7 @@ def main():
                    "pk": "eisenstein_hu_nowiggle", "init_lpt_ms": round(init_s * 1e3, 1)},
         "roofline": roofline,
         "cpu_baseline": base,
+        "serving": serving,
         "kernels": kernels,
     }
     print(json.dumps(out))

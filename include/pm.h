@@ -159,6 +159,20 @@ int pm_kdk_step(pm_ctx* ctx, float* d_pos, float* d_mom, float* d_force,
 int pm_run(pm_ctx* ctx, const double* h_a, int n_a, float* d_pos, float* d_mom,
            float* d_ckpt, float* d_delta_final);
 
+/* Resumable form of pm_run for schedulers that interleave several runs on
+ * one GPU (continuous batching).  pm_run_begin validates and copies the
+ * scale factors, sorts the particles and computes the force at h_a[0];
+ * pm_run_advance enqueues up to max_steps KDK steps and writes the steps
+ * still to go into *h_remaining (may be NULL); pm_run_end, once no step is
+ * left, enqueues the closing half kick, writes d_pos/d_mom (the arrays given
+ * to pm_run_begin, which must stay valid until then) and, if d_delta_final
+ * is not NULL, the final overdensity.  pm_run(...) == begin + advance(all) +
+ * end.  PM_ESTATE if advance/end are called without a run in progress or end
+ * before the last step. */
+int pm_run_begin(pm_ctx* ctx, const double* h_a, int n_a, float* d_pos, float* d_mom, float* d_ckpt);
+int pm_run_advance(pm_ctx* ctx, int max_steps, int* h_remaining);
+int pm_run_end(pm_ctx* ctx, float* d_delta_final);
+
 /* Adjoint of pm_init_lpt + pm_run (reverse-mode derivative; the paper
  * differentiates the simulation with respect to the initial field, section 7).
  * h_a, n_a: the scale factors of the forward pm_run.  d_ckpt: the

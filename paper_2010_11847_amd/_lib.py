@@ -48,6 +48,10 @@ _SIGS = {
     "pm_kdk_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double]),
     "pm_run": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                          C.c_void_p]),
+    "pm_run_begin": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int, C.c_void_p, C.c_void_p,
+                               C.c_void_p]),
+    "pm_run_advance": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
+    "pm_run_end": (C.c_int, [C.c_void_p, C.c_void_p]),
     "pm_run_adjoint": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int, C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pm_rfft": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),

@@ -228,3 +228,28 @@ class PMContext:
         self._check(self.lib.pm_run_adjoint(self.ctx, ap, len(a), _ptr(ckpt), _ptr(noise), _ptr(grad_delta),
                                             _ptr(gx), _ptr(gp), _ptr(gn)), "pm_run_adjoint")
         return gx, gp, gn
+
+    # ---- resumable run (continuous batching) ---------------------------------
+    def pm_run_begin(self, a_list, pos, mom, ckpt: Optional[torch.Tensor] = None):
+        self._dev(pos, (self.np3, 3), name="pos")
+        self._dev(mom, (self.np3, 3), name="mom")
+        a = np.ascontiguousarray(a_list, dtype=np.float64)
+        if ckpt is not None:
+            self._dev(ckpt, (len(a), 2, self.np3, 3), name="ckpt")
+        self._run_refs = (pos, mom, ckpt)   # keep the arrays alive until pm_run_end
+        ap = a.ctypes.data_as(C.POINTER(C.c_double))
+        self._check(self.lib.pm_run_begin(self.ctx, ap, len(a), _ptr(pos), _ptr(mom), _ptr(ckpt)), "pm_run_begin")
+
+    def pm_run_advance(self, max_steps: int = 1) -> int:
+        rem = C.c_int(0)
+        self._check(self.lib.pm_run_advance(self.ctx, max_steps, C.byref(rem)), "pm_run_advance")
+        return rem.value
+
+    def pm_run_end(self, delta_final: Optional[torch.Tensor] = None):
+        if delta_final is not None:
+            n = self.workload.n_mesh
+            self._dev(delta_final, (n, n, n), name="delta_final")
+        self._check(self.lib.pm_run_end(self.ctx, _ptr(delta_final)), "pm_run_end")
+        refs = getattr(self, "_run_refs", None)
+        self._run_refs = None
+        return refs

@@ -24,60 +24,54 @@ __global__ __launch_bounds__(kThreads) void k_paint3w(const float* __restrict__ 
                                                       const uint32_t* __restrict__ off, TileGeom g,
                                                       const float* __restrict__ pbar, float k, float* __restrict__ o0,
                                                       float* __restrict__ o1, float* __restrict__ o2) {
-  __shared__ float acc[3][kTileMax * kTileMax * kTileMax];
-  const int T = g.t, nt = g.nt, n = g.n;
+  __shared__ float acc[3][kTileCells];
+  __shared__ RangeTable rt;
+  const int TX = g.tx, TY = g.ty, TZ = g.tz, n = g.n;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int tz = tile % nt, ty = (tile / nt) % nt, tx = tile / (nt * nt);
-  const int ox = tx * T, oy = ty * T, oz = tz * T;
-  const int cells = T * T * T;
+  const int tz = tile % g.ntz, ty = (tile / g.ntz) % g.nty, tx = tile / (g.ntz * g.nty);
+  const int ox = tx * TX, oy = ty * TY, oz = tz * TZ;
+  const int cells = TX * TY * TZ;
   for (int c = threadIdx.x; c < cells; c += kThreads) acc[0][c] = acc[1][c] = acc[2][c] = 0.f;
-  __syncthreads();
-  for (int e = 0; e < 8; ++e) {
-    const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
-    const int sx = (tx - ex + nt) % nt, sy = (ty - ey + nt) % nt, sz = (tz - ez + nt) % nt;
-    const uint32_t src = ((uint32_t)sx * nt + sy) * nt + sz;
-    for (int cls = 0; cls < 8; ++cls) {
-      if ((cls & e) != e) continue;
-      const uint32_t b0 = off[src * 8 + cls], b1 = off[src * 8 + cls + 1];
-      for (uint32_t j = b0 + threadIdx.x; j < b1; j += kThreads) {
-        int ix, iy, iz;
-        float fx, fy, fz;
-        cic_base(pos[3 * (long)j + 0], n, ix, fx);
-        cic_base(pos[3 * (long)j + 1], n, iy, fy);
-        cic_base(pos[3 * (long)j + 2], n, iz, fz);
-        int lx = (ix - ox) & (n - 1), ly = (iy - oy) & (n - 1), lz = (iz - oz) & (n - 1);
-        if (lx > T) lx -= n;
-        if (ly > T) ly -= n;
-        if (lz > T) lz -= n;
-        const long p = (long)id[j];
-        const float m0 = pbar[3 * p + 0] * k, m1 = pbar[3 * p + 1] * k, m2 = pbar[3 * p + 2] * k;
-        const float wx[2] = {1.f - fx, fx}, wy[2] = {1.f - fy, fy}, wz[2] = {1.f - fz, fz};
+  build_ranges(rt, off, tx, ty, tz, g);
+  const uint32_t total = rt.pre[27];
+  for (uint32_t idx = threadIdx.x; idx < total; idx += kThreads) {
+    const uint32_t j = range_particle(rt, idx);
+    int ix, iy, iz;
+    float fx, fy, fz;
+    cic_base(pos[3 * (long)j + 0], n, ix, fx);
+    cic_base(pos[3 * (long)j + 1], n, iy, fy);
+    cic_base(pos[3 * (long)j + 2], n, iz, fz);
+    int lx = (ix - ox) & (n - 1), ly = (iy - oy) & (n - 1), lz = (iz - oz) & (n - 1);
+    if (lx > TX) lx -= n;
+    if (ly > TY) ly -= n;
+    if (lz > TZ) lz -= n;
+    const long p = (long)id[j];
+    const float m0 = pbar[3 * p + 0] * k, m1 = pbar[3 * p + 1] * k, m2 = pbar[3 * p + 2] * k;
+    const float wx[2] = {1.f - fx, fx}, wy[2] = {1.f - fy, fy}, wz[2] = {1.f - fz, fz};
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          const int cx = lx + a;
-          if (cx < 0 || cx >= T) continue;
+    for (int a = 0; a < 2; ++a) {
+      const int cx = lx + a;
+      if (cx < 0 || cx >= TX) continue;
 #pragma unroll
-          for (int b = 0; b < 2; ++b) {
-            const int cy = ly + b;
-            if (cy < 0 || cy >= T) continue;
+      for (int b = 0; b < 2; ++b) {
+        const int cy = ly + b;
+        if (cy < 0 || cy >= TY) continue;
 #pragma unroll
-            for (int c = 0; c < 2; ++c) {
-              const int cz = lz + c;
-              if (cz < 0 || cz >= T) continue;
-              const float w = wx[a] * wy[b] * wz[c];
-              const int li = (cx * T + cy) * T + cz;
-              atomicAdd(&acc[0][li], w * m0);
-              atomicAdd(&acc[1][li], w * m1);
-              atomicAdd(&acc[2][li], w * m2);
-            }
-          }
+        for (int c = 0; c < 2; ++c) {
+          const int cz = lz + c;
+          if (cz < 0 || cz >= TZ) continue;
+          const float w = wx[a] * wy[b] * wz[c];
+          const int li = (cx * TY + cy) * TZ + cz;
+          atomicAdd(&acc[0][li], w * m0);
+          atomicAdd(&acc[1][li], w * m1);
+          atomicAdd(&acc[2][li], w * m2);
         }
       }
     }
   }
   __syncthreads();
   for (int c = threadIdx.x; c < cells; c += kThreads) {
-    const int cz = c % T, cy = (c / T) % T, cx = c / (T * T);
+    const int cz = c % TZ, cy = (c / TZ) % TY, cx = c / (TZ * TY);
     const long gi = ((long)(ox + cx) * n + (oy + cy)) * n + (oz + cz);
     o0[gi] = acc[0][c];
     o1[gi] = acc[1][c];
@@ -85,70 +79,53 @@ __global__ __launch_bounds__(kThreads) void k_paint3w(const float* __restrict__ 
   }
 }
 
-// x_bar[id] += sum_corners dW/dx * V(c) where
-//   NCH = 3: V(c) = sum_d pbar[id][d] k M_d(c)
-//   NCH = 1: V(c) = k M_0(c)
+// x_bar[id] += sum_corners dW/dx * V(c), one sorted particle per thread:
+//   NCH = 3: V(c) = k pbar[id] . F(c) with F the interleaved force mesh
+//   NCH = 1: V(c) = k M(c) with M a real mesh
 template <int NCH>
 __global__ __launch_bounds__(kThreads) void k_readout_grad(const float* __restrict__ pos,
-                                                           const uint32_t* __restrict__ id,
-                                                           const uint32_t* __restrict__ off, TileGeom g,
-                                                           const float* __restrict__ m0, const float* __restrict__ m1,
-                                                           const float* __restrict__ m2, const float* __restrict__ pbar,
-                                                           float k, float* __restrict__ xbar) {
-  using V = typename std::conditional<NCH == 3, float4, float>::type;
-  __shared__ V ft[(kTileMax + 1) * (kTileMax + 1) * (kTileMax + 1)];
-  const int T = g.t, nt = g.nt, n = g.n, T1 = T + 1;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const uint32_t b0 = off[tile * 8], b1 = off[tile * 8 + 8];
-  if (b0 == b1) return;
-  const int tz = tile % nt, ty = (tile / nt) % nt, tx = tile / (nt * nt);
-  const int ox = tx * T, oy = ty * T, oz = tz * T;
-  for (int c = threadIdx.x; c < T1 * T1 * T1; c += kThreads) {
-    const int cz = c % T1, cy = (c / T1) % T1, cx = c / (T1 * T1);
-    const long gi = ((long)((ox + cx) & (n - 1)) * n + ((oy + cy) & (n - 1))) * n + ((oz + cz) & (n - 1));
-    if constexpr (NCH == 3)
-      ft[c] = make_float4(m0[gi], m1[gi], m2[gi], 0.f);
-    else
-      ft[c] = m0[gi];
+                                                           const uint32_t* __restrict__ id, long np, int n,
+                                                           const float* __restrict__ mesh,
+                                                           const float* __restrict__ pbar, float k,
+                                                           float* __restrict__ xbar) {
+  const long j = (long)xcd_tile(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
+  if (j >= np) return;
+  int ix, iy, iz;
+  float fx, fy, fz;
+  cic_base(pos[3 * j + 0], n, ix, fx);
+  cic_base(pos[3 * j + 1], n, iy, fy);
+  cic_base(pos[3 * j + 2], n, iz, fz);
+  const long p = (long)id[j];
+  float c0 = k, c1 = 0.f, c2 = 0.f;
+  if constexpr (NCH == 3) {
+    c0 = pbar[3 * p + 0] * k;
+    c1 = pbar[3 * p + 1] * k;
+    c2 = pbar[3 * p + 2] * k;
   }
-  __syncthreads();
-  for (uint32_t j = b0 + threadIdx.x; j < b1; j += kThreads) {
-    int ix, iy, iz;
-    float fx, fy, fz;
-    cic_base(pos[3 * (long)j + 0], n, ix, fx);
-    cic_base(pos[3 * (long)j + 1], n, iy, fy);
-    cic_base(pos[3 * (long)j + 2], n, iz, fz);
-    const int lx = (ix - ox) & (n - 1), ly = (iy - oy) & (n - 1), lz = (iz - oz) & (n - 1);
-    const long p = (long)id[j];
-    float c0 = k, c1 = 0.f, c2 = 0.f;
-    if constexpr (NCH == 3) {
-      c0 = pbar[3 * p + 0] * k;
-      c1 = pbar[3 * p + 1] * k;
-      c2 = pbar[3 * p + 2] * k;
-    }
-    const float wx[2] = {1.f - fx, fx}, wy[2] = {1.f - fy, fy}, wz[2] = {1.f - fz, fz};
-    float gx = 0.f, gy = 0.f, gz = 0.f;
+  const int jx = (ix + 1) & (n - 1), jy = (iy + 1) & (n - 1), jz = (iz + 1) & (n - 1);
+  const int xs[2] = {ix, jx}, ys[2] = {iy, jy}, zs[2] = {iz, jz};
+  const float wx[2] = {1.f - fx, fx}, wy[2] = {1.f - fy, fy}, wz[2] = {1.f - fz, fz};
+  float gx = 0.f, gy = 0.f, gz = 0.f;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < 2; ++b)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          const V v = ft[((lx + a) * T1 + (ly + b)) * T1 + (lz + c)];
-          float val;
-          if constexpr (NCH == 3)
-            val = c0 * v.x + c1 * v.y + c2 * v.z;
-          else
-            val = c0 * v;
-          const float sa = a ? 1.f : -1.f, sb = b ? 1.f : -1.f, sc = c ? 1.f : -1.f;
-          gx += sa * wy[b] * wz[c] * val;
-          gy += wx[a] * sb * wz[c] * val;
-          gz += wx[a] * wy[b] * sc * val;
-        }
-    xbar[3 * p + 0] += gx;
-    xbar[3 * p + 1] += gy;
-    xbar[3 * p + 2] += gz;
-  }
+      for (int c = 0; c < 2; ++c) {
+        const long cell = ((long)xs[a] * n + ys[b]) * n + zs[c];
+        float val;
+        if constexpr (NCH == 3)
+          val = c0 * mesh[3 * cell] + c1 * mesh[3 * cell + 1] + c2 * mesh[3 * cell + 2];
+        else
+          val = c0 * mesh[cell];
+        const float sa = a ? 1.f : -1.f, sb = b ? 1.f : -1.f, sc = c ? 1.f : -1.f;
+        gx += sa * wy[b] * wz[c] * val;
+        gy += wx[a] * sb * wz[c] * val;
+        gz += wx[a] * wy[b] * sc * val;
+      }
+  xbar[3 * p + 0] += gx;
+  xbar[3 * p + 1] += gy;
+  xbar[3 * p + 2] += gz;
 }
 
 // y += a x  (n floats)
@@ -206,17 +183,17 @@ void launch_paint3w(const float* pos, const uint32_t* id, const uint32_t* off, c
   hipLaunchKernelGGL(k_paint3w, dim3(g.ntiles), dim3(kThreads), 0, s, pos, id, off, g, pbar, k, o0, o1, o2);
 }
 
-void launch_readout_grad3(const float* pos, const uint32_t* id, const uint32_t* off, const TileGeom& g,
-                          const float* m0, const float* m1, const float* m2, const float* pbar, float k, float* xbar,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(k_readout_grad<3>, dim3(g.ntiles), dim3(kThreads), 0, s, pos, id, off, g, m0, m1, m2, pbar, k,
-                     xbar);
+void launch_readout_grad3(const float* pos, const uint32_t* id, long np, int n, const float* fi, const float* pbar,
+                          float k, float* xbar, hipStream_t s) {
+  const int grid = (int)((np + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(k_readout_grad<3>, dim3(grid), dim3(kThreads), 0, s, pos, id, np, n, fi, pbar, k, xbar);
 }
 
-void launch_readout_grad1(const float* pos, const uint32_t* id, const uint32_t* off, const TileGeom& g,
-                          const float* m0, float k, float* xbar, hipStream_t s) {
-  hipLaunchKernelGGL(k_readout_grad<1>, dim3(g.ntiles), dim3(kThreads), 0, s, pos, id, off, g, m0, m0, m0,
-                     (const float*)nullptr, k, xbar);
+void launch_readout_grad1(const float* pos, const uint32_t* id, long np, int n, const float* m0, float k, float* xbar,
+                          hipStream_t s) {
+  const int grid = (int)((np + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(k_readout_grad<1>, dim3(grid), dim3(kThreads), 0, s, pos, id, np, n, m0, (const float*)nullptr,
+                     k, xbar);
 }
 
 void launch_axpy(float* y, const float* x, float a, long n, hipStream_t s) {

@@ -34,16 +34,25 @@ size_t fft_table_bytes(long n) {
   return align_up(n * 8) + align_up(n / 2 * 8) + 4 * align_up(n * 4) + 4 * align_up((n / 2 + 1) * 4);
 }
 
-int tile_side(int n) {
-  int t = 16;
-  while (t > 1 && t * 2 > n) t >>= 1;   // at least two tiles per side
-  return t;
+// Paint/sort tiles of 16 x 16 x 32 cells (x, y, z; 32 floats = 128-byte
+// rows along the contiguous axis), at least two tiles per side.
+pmk::TileGeom make_tiles(int n) {
+  pmk::TileGeom g;
+  g.n = n;
+  g.tx = g.ty = n / 2 < 16 ? n / 2 : 16;
+  g.tz = n / 2 < 32 ? n / 2 : 32;
+  g.ntx = n / g.tx;
+  g.nty = n / g.ty;
+  g.ntz = n / g.tz;
+  g.ntiles = g.ntx * g.nty * g.ntz;
+  return g;
 }
 
 // Byte layout of the workspace (offsets from its base).
 struct Layout {
   size_t tab_mesh = 0, tab_lat = 0, pk_lat = 0;
   size_t mesh[3] = {0, 0, 0};
+  size_t force_i = 0;
   size_t pos_s[2] = {0, 0}, mom_s[2] = {0, 0}, id_s[2] = {0, 0};
   size_t key = 0, rank = 0;
   size_t count = 0, off = 0, bsum = 0;
@@ -95,9 +104,7 @@ Layout make_layout(const pm_config* c) {
   const long ng = c->n_mesh, np = c->n_part;
   const long np3 = np * np * np;
   L.cap = c->max_particles > 0 ? c->max_particles : np3;
-  const int t = tile_side((int)ng);
-  const long nt = ng / t;
-  L.n_keys = nt * nt * nt * 8;
+  L.n_keys = (long)make_tiles((int)ng).ntiles * 8;
   L.n_bins_max = (int)(ng / 2);
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -115,6 +122,7 @@ Layout make_layout(const pm_config* c) {
   L.pw_out = take((size_t)3 * L.n_bins_max * 8);
   const size_t region = o;
   for (int i = 0; i < 3; ++i) L.mesh[i] = take(field_bytes(ng));
+  L.force_i = take((size_t)ng * ng * ng * 12);
   for (int i = 0; i < 2; ++i) L.pos_s[i] = take((size_t)L.cap * 12);
   for (int i = 0; i < 2; ++i) L.mom_s[i] = take((size_t)L.cap * 12);
   for (int i = 0; i < 2; ++i) L.id_s[i] = take((size_t)L.cap * 4);
@@ -222,6 +230,7 @@ struct pm_ctx {
   pmk::TileGeom tg;
   FftTables tm, tl;
   Field mesh[3];
+  float* force_i = nullptr;   // interleaved force mesh [n^3][3]
   float* pos_s[2] = {};
   float* mom_s[2] = {};
   uint32_t* id_s[2] = {};
@@ -229,6 +238,14 @@ struct pm_ctx {
   double *pw_partial = nullptr, *pw_out = nullptr;
   float* pk_lat = nullptr;
   Profiler prof;
+
+  // state of a resumable run (pm_run_begin / advance / end)
+  struct RunState {
+    bool active = false;
+    int ns = 0, step = 0, cur = 0;
+    std::vector<double> k1, dr, k2;
+    float *pos = nullptr, *mom = nullptr, *ckpt = nullptr;
+  } run;
 
   // run f (which enqueues one kernel class) between two events when profiling
   template <class F>
@@ -307,21 +324,19 @@ struct pm_ctx {
     }
     timed(PC_FFT_X_FUSED, [&] { pmk::fft_x_fused(tm, mesh[0], op, stream); });
     timed(PC_FFT_Y_INV, [&] { pmk::fft_y(tm, mesh, 3, 1, stream); });
-    timed(PC_FFT_C2R_Z, [&] { pmk::fft_z_c2r(tm, mesh, 3, stream); });
+    timed(PC_FFT_C2R_Z, [&] { pmk::fft_z_c2r_interleaved3(tm, mesh, force_i, stream); });
   }
   void readout(const pmk::ReadoutArgs& a) {
     timed(PC_READOUT, [&] { pmk::launch_readout(a, stream); });
   }
-  pmk::ReadoutArgs readout_args(int cur) {
+  pmk::ReadoutArgs readout_args(int cur, long np) {
     pmk::ReadoutArgs a;
     a.g = tg;
+    a.np = np;
     a.pos = pos_s[cur];
     a.mom = mom_s[cur];
     a.id = id_s[cur];
-    a.off = off;
-    a.f0 = mesh[0].r;
-    a.f1 = mesh[1].r;
-    a.f2 = mesh[2].r;
+    a.fi = force_i;
     a.key_out = key;
     a.rank_out = rank;
     a.count = count;
@@ -377,16 +392,13 @@ int pm_create(const pm_config* cfg, void* d_workspace, size_t bytes, void* strea
   c->ratio = cfg->n_mesh / cfg->n_part;
   c->np3 = (long)cfg->n_part * cfg->n_part * cfg->n_part;
   c->cosmo.init(c->cfg.cosmo);
-  const int t = tile_side(c->ng);
-  c->tg.n = c->ng;
-  c->tg.t = t;
-  c->tg.nt = c->ng / t;
-  c->tg.ntiles = c->tg.nt * c->tg.nt * c->tg.nt;
+  c->tg = make_tiles(c->ng);
   char* w = c->ws;
   for (int i = 0; i < 3; ++i) {
     c->mesh[i].r = reinterpret_cast<float*>(w + L.mesh[i]);
     c->mesh[i].q = reinterpret_cast<float2*>(w + L.mesh[i] + align_up((size_t)c->ng * c->ng * c->ng * 4));
   }
+  c->force_i = reinterpret_cast<float*>(w + L.force_i);
   for (int i = 0; i < 2; ++i) {
     c->pos_s[i] = reinterpret_cast<float*>(w + L.pos_s[i]);
     c->mom_s[i] = reinterpret_cast<float*>(w + L.mom_s[i]);
@@ -538,7 +550,7 @@ int pm_force(pm_ctx* ctx, const float* d_pos, int64_t np, float* d_force) {
   c.sort(d_pos, nullptr, nullptr, np, 0);
   c.paint(0, np, c.mesh[0].r);
   c.force_meshes();
-  pmk::ReadoutArgs a = c.readout_args(0);
+  pmk::ReadoutArgs a = c.readout_args(0, np);
   a.mom = nullptr;
   a.flags = pmk::RO_FORCE_BYID;
   a.force_out = d_force;
@@ -555,7 +567,7 @@ int pm_kdk_step(pm_ctx* ctx, float* d_pos, float* d_mom, float* d_force, double 
   c.sort(d_pos, d_mom, nullptr, c.np3, 0);
   c.paint(0, c.np3, c.mesh[0].r);
   c.force_meshes();
-  pmk::ReadoutArgs a = c.readout_args(0);
+  pmk::ReadoutArgs a = c.readout_args(0, c.np3);
   a.flags = pmk::RO_KICK | pmk::RO_XP_BYID | pmk::RO_FORCE_BYID;
   a.kick_a = (float)k2;
   a.kick_b = 0.f;
@@ -566,59 +578,100 @@ int pm_kdk_step(pm_ctx* ctx, float* d_pos, float* d_mom, float* d_force, double 
   return c.check("pm_kdk_step");
 }
 
-int pm_run(pm_ctx* ctx, const double* h_a, int n_a, float* d_pos, float* d_mom, float* d_ckpt,
-           float* d_delta_final) {
+int pm_run_begin(pm_ctx* ctx, const double* h_a, int n_a, float* d_pos, float* d_mom, float* d_ckpt) {
   if (!ctx || !h_a || n_a < 1 || !d_pos || !d_mom) return PM_EINVAL;
   pm_ctx& c = *ctx;
   for (int i = 0; i < n_a; ++i)
     if (!(h_a[i] > 0) || (i && !(h_a[i] > h_a[i - 1]))) return c.fail(PM_EINVAL, "a must be > 0 and increasing");
-  const int ns = n_a - 1;
-  std::vector<double> k1(ns), dr(ns), k2(ns);
-  for (int i = 0; i < ns; ++i) {
+  auto& r = c.run;
+  r = pm_ctx::RunState();
+  r.ns = n_a - 1;
+  r.k1.resize(r.ns);
+  r.dr.resize(r.ns);
+  r.k2.resize(r.ns);
+  for (int i = 0; i < r.ns; ++i) {
     const double ai = h_a[i], aj = h_a[i + 1], ac = std::sqrt(ai * aj);
-    k1[i] = c.cosmo.kick(ai, ac, ai);
-    dr[i] = c.cosmo.drift(ai, aj, ac);
-    k2[i] = c.cosmo.kick(ac, aj, aj);
+    r.k1[i] = c.cosmo.kick(ai, ac, ai);
+    r.dr[i] = c.cosmo.drift(ai, aj, ac);
+    r.k2[i] = c.cosmo.kick(ac, aj, aj);
   }
+  r.pos = d_pos;
+  r.mom = d_mom;
+  r.ckpt = d_ckpt;
+  r.cur = 0;
+  r.step = 0;
+  const long np = c.np3;
+  c.sort(d_pos, d_mom, nullptr, np, r.cur);
+  c.paint(r.cur, np, c.mesh[0].r);
+  c.force_meshes();
+  r.active = true;
+  return c.check("pm_run_begin");
+}
+
+int pm_run_advance(pm_ctx* ctx, int max_steps, int* h_remaining) {
+  if (!ctx || max_steps < 0) return PM_EINVAL;
+  pm_ctx& c = *ctx;
+  auto& r = c.run;
+  if (!r.active) return c.fail(PM_ESTATE, "no run in progress");
   const long np = c.np3;
   const size_t ck = (size_t)np * 3;
-  int cur = 0;
-  c.sort(d_pos, d_mom, nullptr, np, cur);
-  if (ns == 0 && d_delta_final) c.paint(cur, np, d_delta_final);
-  c.paint(cur, np, c.mesh[0].r);
-  c.force_meshes();
-  for (int i = 0; i < ns; ++i) {
+  for (int k = 0; k < max_steps && r.step < r.ns; ++k) {
+    const int i = r.step;
     c.timed(PC_FILL, [&] { pmk::launch_fill_u32(c.count, c.L.n_keys, 0u, c.stream); });
-    pmk::ReadoutArgs a = c.readout_args(cur);
+    pmk::ReadoutArgs a = c.readout_args(r.cur, np);
     a.flags = pmk::RO_KICK | pmk::RO_DRIFT | pmk::RO_WRITE_SORTED | pmk::RO_KEYS;
-    a.kick_a = i ? (float)k2[i - 1] : 0.f;
-    a.kick_b = (float)k1[i];
-    a.drift = (float)dr[i];
-    if (d_ckpt) {
+    a.kick_a = i ? (float)r.k2[i - 1] : 0.f;
+    a.kick_b = (float)r.k1[i];
+    a.drift = (float)r.dr[i];
+    if (r.ckpt) {
       a.flags |= pmk::RO_CKPT;
-      a.ckpt_x = d_ckpt + (2 * (size_t)i) * ck;
-      a.ckpt_p = d_ckpt + (2 * (size_t)i + 1) * ck;
+      a.ckpt_x = r.ckpt + (2 * (size_t)i) * ck;
+      a.ckpt_p = r.ckpt + (2 * (size_t)i + 1) * ck;
     }
     c.readout(a);
-    c.finish_sort(c.pos_s[cur], c.mom_s[cur], c.id_s[cur], np, 1 - cur);
-    cur = 1 - cur;
-    if (i == ns - 1 && d_delta_final) c.paint(cur, np, d_delta_final);
-    c.paint(cur, np, c.mesh[0].r);
+    c.finish_sort(c.pos_s[r.cur], c.mom_s[r.cur], c.id_s[r.cur], np, 1 - r.cur);
+    r.cur = 1 - r.cur;
+    c.paint(r.cur, np, c.mesh[0].r);
     c.force_meshes();
+    ++r.step;
   }
-  pmk::ReadoutArgs a = c.readout_args(cur);
+  if (h_remaining) *h_remaining = r.ns - r.step;
+  return c.check("pm_run_advance");
+}
+
+int pm_run_end(pm_ctx* ctx, float* d_delta_final) {
+  if (!ctx) return PM_EINVAL;
+  pm_ctx& c = *ctx;
+  auto& r = c.run;
+  if (!r.active) return c.fail(PM_ESTATE, "no run in progress");
+  if (r.step != r.ns) return c.fail(PM_ESTATE, "pm_run_end before the last step");
+  const long np = c.np3;
+  const size_t ck = (size_t)np * 3;
+  if (d_delta_final) c.paint(r.cur, np, d_delta_final);
+  pmk::ReadoutArgs a = c.readout_args(r.cur, np);
   a.flags = pmk::RO_KICK | pmk::RO_XP_BYID;
-  a.kick_a = ns ? (float)k2[ns - 1] : 0.f;
+  a.kick_a = r.ns ? (float)r.k2[r.ns - 1] : 0.f;
   a.kick_b = 0.f;
-  a.pos_out = d_pos;
-  a.mom_out = d_mom;
-  if (d_ckpt) {
+  a.pos_out = r.pos;
+  a.mom_out = r.mom;
+  if (r.ckpt) {
     a.flags |= pmk::RO_CKPT;
-    a.ckpt_x = d_ckpt + (2 * (size_t)ns) * ck;
-    a.ckpt_p = d_ckpt + (2 * (size_t)ns + 1) * ck;
+    a.ckpt_x = r.ckpt + (2 * (size_t)r.ns) * ck;
+    a.ckpt_p = r.ckpt + (2 * (size_t)r.ns + 1) * ck;
   }
   c.readout(a);
-  return c.check("pm_run");
+  r.active = false;
+  return c.check("pm_run_end");
+}
+
+int pm_run(pm_ctx* ctx, const double* h_a, int n_a, float* d_pos, float* d_mom, float* d_ckpt,
+           float* d_delta_final) {
+  int st = pm_run_begin(ctx, h_a, n_a, d_pos, d_mom, d_ckpt);
+  if (st != PM_OK) return st;
+  int rem = 0;
+  st = pm_run_advance(ctx, n_a, &rem);
+  if (st != PM_OK) return st;
+  return pm_run_end(ctx, d_delta_final);
 }
 
 int pm_run_adjoint(pm_ctx* ctx, const double* h_a, int n_a, const float* d_ckpt, const float* d_noise,
@@ -645,7 +698,7 @@ int pm_run_adjoint(pm_ctx* ctx, const double* h_a, int n_a, const float* d_ckpt,
   // loss on the final overdensity: x_bar += paint^T-gradient of s * delta_bar
   if (d_grad_delta_final) {
     c.sort(ckpt_x(ns), nullptr, nullptr, np, 0);
-    pmk::launch_readout_grad1(c.pos_s[0], c.id_s[0], c.off, c.tg, d_grad_delta_final, (float)s, xbar, c.stream);
+    pmk::launch_readout_grad1(c.pos_s[0], c.id_s[0], np, c.ng, d_grad_delta_final, (float)s, xbar, c.stream);
   }
   // reverse sweep over the force evaluation points x_ns ... x_0
   for (int j = ns; j >= 0; --j) {
@@ -655,8 +708,7 @@ int pm_run_adjoint(pm_ctx* ctx, const double* h_a, int n_a, const float* d_ckpt,
       c.paint(0, np, c.mesh[0].r);
       c.force_meshes();
       // term A: positions at which the force meshes are read out
-      pmk::launch_readout_grad3(c.pos_s[0], c.id_s[0], c.off, c.tg, c.mesh[0].r, c.mesh[1].r, c.mesh[2].r, pbar,
-                                (float)kj, xbar, c.stream);
+      pmk::launch_readout_grad3(c.pos_s[0], c.id_s[0], np, c.ng, c.force_i, pbar, (float)kj, xbar, c.stream);
       // term B: positions that paint the density, through G^T
       pmk::launch_paint3w(c.pos_s[0], c.id_s[0], c.off, c.tg, pbar, (float)kj, c.mesh[0].r, c.mesh[1].r,
                           c.mesh[2].r, c.stream);
@@ -676,7 +728,7 @@ int pm_run_adjoint(pm_ctx* ctx, const double* h_a, int n_a, const float* d_ckpt,
       op.out_q[0] = c.mesh[0].q;
       pmk::fft_x_fused(c.tm, c.mesh[0], op, c.stream);
       pmk::fft_c2r_yz(c.tm, &c.mesh[0], 1, c.stream);
-      pmk::launch_readout_grad1(c.pos_s[0], c.id_s[0], c.off, c.tg, c.mesh[0].r, 1.f, xbar, c.stream);
+      pmk::launch_readout_grad1(c.pos_s[0], c.id_s[0], np, c.ng, c.mesh[0].r, 1.f, xbar, c.stream);
     }
     if (j > 0) pmk::launch_axpy(pbar, xbar, (float)dr[j - 1], (long)ck, c.stream);
   }

@@ -247,10 +247,10 @@ struct ZGeom {
 // stage A + B of a length-H complex transform of L contiguous lines whose
 // element (line m, index n) is produced by load(m, n); the result
 // Z[m][k] is written into lds at m*(H+1) + k (natural order).
-template <int N, int DIR, class Load>
+template <int N, int L, int DIR, class Load>
 __device__ __forceinline__ void zline_transform(float2* lds, const float2* __restrict__ twh, Load load) {
   using G = ZGeom<N>;
-  constexpr int H = G::H, R1 = G::R1, R2 = G::R2, L = G::L;
+  constexpr int H = G::H, R1 = G::R1, R2 = G::R2;
   constexpr int IA = (L * R2 + kThreads - 1) / kThreads;
   constexpr int IB = (L * R1 + kThreads - 1) / kThreads;
   const int tid = threadIdx.x;
@@ -332,7 +332,7 @@ __global__ __launch_bounds__(kThreads) void k_r2c_z(float* __restrict__ r0, floa
   float2* q = blockIdx.y == 0 ? q0 : (blockIdx.y == 1 ? q1 : q2);
   const long line0 = (long)xcd_tile(blockIdx.x, gridDim.x) * L;
   float2* c = reinterpret_cast<float2*>(r) + line0 * H;
-  zline_transform<N, -1>(lds, twh, [&](int m, int n) { return c[(long)m * H + n]; });
+  zline_transform<N, L, -1>(lds, twh, [&](int m, int n) { return c[(long)m * H + n]; });
   // post-processing: X[k] = E + w^k O, X[H-k] = conj(E - w^k O)
   constexpr int NK = H / 2 + 1;
   for (int it = threadIdx.x; it < L * NK; it += kThreads) {
@@ -383,10 +383,72 @@ __global__ __launch_bounds__(kThreads) void k_c2r_z(float* __restrict__ r0, floa
     const float2 o = cmulc(csub(a, b), twn[k]);     // (a - b) exp(+2 pi i k / N)
     return make_float2(e.x - o.y, e.y + o.x);       // e + i o
   };
-  zline_transform<N, +1>(lds, twh, load);
+  zline_transform<N, L, +1>(lds, twh, load);
   for (int it = threadIdx.x; it < L * H; it += kThreads) {
     const int j = it % H, m = it / H;
     c[(long)m * H + j] = lds[m * (H + 1) + j];      // (x[2j], x[2j+1])
+  }
+}
+
+// Three fields in one workgroup (L3 lines each), written as one interleaved
+// real mesh out[(line*N + z)*3 + field]: the layout the particle readout
+// gathers from (one 12-byte load per CIC corner).
+template <int N>
+struct ZGeom3 {
+  static constexpr int H = N / 2;
+  static constexpr int R1 = Split<H>::R1, R2 = Split<H>::R2;
+  static constexpr int L3 = ZGeom<N>::L / 4 > 0 ? ZGeom<N>::L / 4 : 1;
+  static constexpr int L = 3 * L3;
+  static constexpr int XS = (R2 > 1) ? L * R1 * (R2 + 1) : 1;
+  static constexpr int ZS = L * (H + 1);
+  static constexpr int size = XS > ZS ? XS : ZS;
+};
+
+template <int N>
+__global__ __launch_bounds__(kThreads) void k_c2r_z3i(const float* __restrict__ r0, const float* __restrict__ r1,
+                                                       const float* __restrict__ r2, const float2* __restrict__ q0,
+                                                       const float2* __restrict__ q1, const float2* __restrict__ q2,
+                                                       float* __restrict__ out, const float2* __restrict__ twh,
+                                                       const float2* __restrict__ twn) {
+  using G = ZGeom3<N>;
+  constexpr int H = G::H, L3 = G::L3, L = G::L;
+  __shared__ float2 lds[G::size];
+  const long line0 = (long)xcd_tile(blockIdx.x, gridDim.x) * L3;
+  auto load = [&](int m, int k) {
+    const int f = m / L3;
+    const long line = line0 + (m - f * L3);
+    const float* r = f == 0 ? r0 : (f == 1 ? r1 : r2);
+    const float2* q = f == 0 ? q0 : (f == 1 ? q1 : q2);
+    const float2* ln = reinterpret_cast<const float2*>(r) + line * H;
+    float2 a, b;
+    if (k == 0) {
+      a = make_float2(ln[0].x, 0.f);
+      b = make_float2(q[line].x, 0.f);
+    } else {
+      a = ln[k];
+      b = cconj(ln[H - k]);
+    }
+    const float2 e = cadd(a, b);
+    const float2 o = cmulc(csub(a, b), twn[k]);     // (a - b) exp(+2 pi i k / N)
+    return make_float2(e.x - o.y, e.y + o.x);       // e + i o
+  };
+  zline_transform<N, L, +1>(lds, twh, load);
+  // the L3 output lines are contiguous: 3*N*L3 floats from out + line0*3N;
+  // each thread writes whole float4s of that stream (element e: cell e/3,
+  // field e%3; cell 2j / 2j+1 is the real / imaginary part of z_j)
+  const float* ldsf = reinterpret_cast<const float*>(lds);
+  float4* o4 = reinterpret_cast<float4*>(out + line0 * 3 * N);
+  constexpr int NQ = 3 * N * L3 / 4;
+  for (int q = threadIdx.x; q < NQ; q += kThreads) {
+    float v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = 4 * q + u;
+      const int cell = e / 3, f = e - 3 * (e / 3);
+      const int m = cell / N, z = cell - m * N;
+      v[u] = ldsf[2 * ((f * L3 + m) * (H + 1) + (z >> 1)) + (z & 1)];
+    }
+    o4[q] = make_float4(v[0], v[1], v[2], v[3]);
   }
 }
 
@@ -399,6 +461,10 @@ struct FusedArgs {
   SpecOp op;
   ColGeom gm, gp;          // main array (mode 0) and Nyquist plane (mode 1)
   int nb_main;
+  int pbasis;              // the power of D(w_x) this launch handles (N > 32)
+  int first, last;         // fan-in: first / last basis launch of the op
+  float2* park_main;       // fan-in: x-spectrum partial sum between launches
+  float2* park_nyq;
   const float2* in_main;   // input spectrum (forward-y transformed)
   const float2* in_nyq;
   FftTables t;
@@ -407,36 +473,64 @@ struct FusedArgs {
 template <int N>
 __device__ __forceinline__ int sfreq(int n) { return n < N / 2 ? n : n - N; }
 
-// Spectral multiplier m(k) of fan-out output o, or of fan-in input o (then
-// the multiplier returned is already the conjugate used by the transpose),
-// at mode (kx, ky, kz): kx, ky in [0, N) with numpy's signed-frequency
-// convention, kz in [0, N/2].
+// The spectral multiplier of every op factorises into
+//   c(k) * D(w_x)^p * coef(column),
+// a real common factor c(k) (Green's function, deconvolution, split filter,
+// P(k) scaling), a power p in {0, 1, 2} of the FD gradient symbol along the
+// transform axis x, and a complex coefficient that is constant along x
+// (built from D(w_y), D(w_z) and +-i).  Because that coefficient commutes
+// with the x transform, a fan-out op needs one inverse x transform per
+// distinct power p (force: 2, LPT: 3) and every output is a scaled copy of
+// one of them; a fan-in op (a transpose) combines its inputs of equal power
+// before one forward x transform each.
+struct Term {
+  int p;       // power of D(w_x)
+  int sel;     // 0: 1, 1: D_y, 2: D_z, 3: D_y^2, 4: D_z^2, 5: D_y D_z
+  int phase;   // 0: 1, 1: +i, 2: -i
+};
+
+__host__ __device__ __forceinline__ Term op_term(int kind, int o) {
+  // component order of the LPT outputs: s1 x, y, z, phi xx, yy, zz, xy, xz, yz
+  constexpr int lp[9] = {1, 0, 0, 2, 0, 0, 1, 1, 0};
+  constexpr int ls[9] = {0, 1, 2, 0, 3, 4, 1, 2, 5};
+  switch (kind) {
+    case OP_FORCE: return Term{o == 0 ? 1 : 0, o, 1};
+    case OP_FORCE_T: return Term{o == 0 ? 1 : 0, o, 2};
+    case OP_LPT2: return Term{o == 0 ? 1 : 0, o, 2};
+    case OP_LPT2_T: return Term{o == 0 ? 1 : 0, o, 1};
+    case OP_LPT1: return Term{lp[o], ls[o], o < 3 ? 1 : 0};
+    case OP_LPT1_T: return Term{lp[o], ls[o], o < 3 ? 2 : 0};
+    case OP_LPT_PHI: return Term{lp[o + 3], ls[o + 3], 0};
+    default: return Term{0, 0, 0};   // IDENTITY, LINEAR
+  }
+}
+
+__device__ __forceinline__ float2 coef_of(const Term& tm, float dy, float dz) {
+  float v;
+  switch (tm.sel) {
+    case 0: v = 1.f; break;
+    case 1: v = dy; break;
+    case 2: v = dz; break;
+    case 3: v = dy * dy; break;
+    case 4: v = dz * dz; break;
+    default: v = dy * dz; break;
+  }
+  return tm.phase == 0 ? make_float2(v, 0.f) : (tm.phase == 1 ? make_float2(0.f, v) : make_float2(0.f, -v));
+}
+
 template <int N>
-__device__ __forceinline__ float2 spec_mult(const SpecOp& op, const FftTables& t, int o, int kx, int ky, int kz,
-                                            float2 x) {
+__device__ __forceinline__ float common_factor(const SpecOp& op, const FftTables& t, int kx, int ky, int kz) {
   const float kk = t.kxy[kx] + t.kxy[ky] + t.kz[kz];
   const float inv = kk > 0.f ? 1.f / kk : 0.f;
-  const float d0 = t.dxy[kx], d1 = t.dxy[ky], d2 = t.dz[kz];
-  auto dsel = [&](int d) { return d == 0 ? d0 : (d == 1 ? d1 : d2); };
   auto pk = [&]() {
     const int fx = sfreq<N>(kx), fy = sfreq<N>(ky);
     return op.pk[fx * fx + fy * fy + kz * kz];
   };
-  auto phi_pair = [&](int c) {   // xx, yy, zz, xy, xz, yz
-    switch (c) {
-      case 0: return d0 * d0;
-      case 1: return d1 * d1;
-      case 2: return d2 * d2;
-      case 3: return d0 * d1;
-      case 4: return d0 * d2;
-      default: return d1 * d2;
-    }
-  };
   switch (op.kind) {
     case OP_IDENTITY:
-      return cscale(x, op.scale);
+      return op.scale;
     case OP_LINEAR:
-      return cscale(x, pk());
+      return pk();
     case OP_FORCE:
     case OP_FORCE_T: {
       float g = op.scale * inv;
@@ -448,29 +542,21 @@ __device__ __forceinline__ float2 spec_mult(const SpecOp& op, const FftTables& t
         const float sv = t.sxy[kx] * t.sxy[ky] * t.sz[kz];
         g *= (op.split == 1 ? sv : 1.f - sv);
       }
-      const float2 v = cscale(x, dsel(o) * g);
-      return op.kind == OP_FORCE ? cmul_i<1>(v) : cmul_i<-1>(v);   // i D g, conj = -i D g
+      return g;
     }
-    case OP_LPT1: {
-      const float2 dl = cscale(x, pk() * inv);
-      if (o < 3) return cmul_i<1>(cscale(dl, dsel(o)));             // s1_d = i D_d delta_L / K^2
-      return cscale(dl, phi_pair(o - 3));                            // phi_ij = D_i D_j delta_L / K^2
-    }
+    case OP_LPT1:
     case OP_LPT_PHI:
-      return cscale(x, pk() * inv * phi_pair(o));
+    case OP_LPT1_T:
+      return pk() * inv;
     case OP_LPT2:
-      return cmul_i<-1>(cscale(x, dsel(o) * inv * op.scale));       // s2_d = -i D_d delta2 / K^2
     case OP_LPT2_T:
-      return cmul_i<1>(cscale(x, dsel(o) * inv * op.scale));        // conj(-i D_d s / K^2)
-    case OP_LPT1_T: {
-      const float2 v = cscale(x, pk() * inv);
-      if (o < 3) return cmul_i<-1>(cscale(v, dsel(o)));              // conj(i D_d / K^2)
-      return cscale(v, phi_pair(o - 3));
-    }
+      return op.scale * inv;
     default:
-      return make_float2(0.f, 0.f);
+      return 0.f;
   }
 }
+
+__device__ __forceinline__ float powp(float d, int p) { return p == 0 ? 1.f : (p == 1 ? d : d * d); }
 
 template <int N, int M, bool FANIN>
 __global__ __launch_bounds__(kThreads) void k_fft_x_fused(FusedArgs a) {
@@ -489,16 +575,27 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_fused(FusedArgs a) {
   const int tid = threadIdx.x;
   const SpecOp& op = a.op;
   const FftTables& t = a.t;
-  const int nin = FANIN ? op.n_in : 1;
-  const int nout = FANIN ? 1 : op.n_out;
+  const int kind = op.kind;
+  const int nterm = FANIN ? op.n_in : op.n_out;
+  int pmask = 0;
+  if (FANIN)
+    for (int o = 0; o < nterm; ++o) pmask |= 1 << op_term(kind, o).p;
   auto src_of = [&](int in) -> const float2* {
     if (FANIN) return (mode == 0 ? op.in_c[in] : op.in_q[in]) + off;
     return (mode == 0 ? a.in_main : a.in_nyq) + off;
   };
   auto dst_of = [&](int o) -> float2* { return (mode == 0 ? op.out_c[o] : op.out_q[o]) + off; };
+  // (ky, kz) of column m; masked columns map to the zero mode
   auto freq = [&](int m, int& ky, int& kz) {
-    if (mode == 0) { ky = b; kz = c0 + m; }
+    if (c0 + m >= g.ncols) { ky = 0; kz = 0; }
+    else if (mode == 0) { ky = b; kz = c0 + m; }
     else { ky = c0 + m; kz = N / 2; }
+  };
+  auto col_d = [&](int m, float& dy, float& dz) {
+    int ky, kz;
+    freq(m, ky, kz);
+    dy = t.dxy[ky];
+    dz = t.dz[kz];
   };
 
   if constexpr (R2 == 1) {
@@ -509,41 +606,65 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_fused(FusedArgs a) {
       if (m < M && c0 + m < g.ncols) {
         int ky, kz;
         freq(m, ky, kz);
+        float dy, dz;
+        col_d(m, dy, dz);
         float2 X[R1], Y[R1];
 #pragma unroll
         for (int j = 0; j < R1; ++j) Y[j] = make_float2(0.f, 0.f);
-        for (int in = 0; in < nin; ++in) {
-          const float2* src = src_of(in);
+        if (FANIN) {
+          for (int p = 0; p < 3; ++p) {
+            if (!(pmask >> p & 1)) continue;
+#pragma unroll
+            for (int j = 0; j < R1; ++j) X[j] = make_float2(0.f, 0.f);
+            for (int in = 0; in < nterm; ++in) {
+              const Term tm = op_term(kind, in);
+              if (tm.p != p) continue;
+              const float2 cf = coef_of(tm, dy, dz);
+              const float2* src = src_of(in);
+#pragma unroll
+              for (int j = 0; j < R1; ++j) X[j] = cadd(X[j], cmul(src[j * g.sn + m], cf));
+            }
+            dft<R1, -1>(X);
+#pragma unroll
+            for (int kx = 0; kx < R1; ++kx) Y[kx] = cadd(Y[kx], cscale(X[kx], powp(t.dxy[kx], p)));
+          }
+#pragma unroll
+          for (int kx = 0; kx < R1; ++kx) Y[kx] = cscale(Y[kx], common_factor<N>(op, t, kx, ky, kz));
+          dft<R1, 1>(Y);
+          float2* dst = dst_of(0);
+#pragma unroll
+          for (int j = 0; j < R1; ++j) dst[j * g.sn + m] = Y[j];
+        } else {
+          const float2* src = src_of(0);
 #pragma unroll
           for (int j = 0; j < R1; ++j) X[j] = src[j * g.sn + m];
           dft<R1, -1>(X);
-          if (FANIN) {
 #pragma unroll
-            for (int kx = 0; kx < R1; ++kx) Y[kx] = cadd(Y[kx], spec_mult<N>(op, t, in, kx, ky, kz, X[kx]));
+          for (int kx = 0; kx < R1; ++kx) X[kx] = cscale(X[kx], common_factor<N>(op, t, kx, ky, kz));
+          {
+            const int p = a.pbasis;
+#pragma unroll
+            for (int kx = 0; kx < R1; ++kx) Y[kx] = cscale(X[kx], powp(t.dxy[kx], p));
+            dft<R1, 1>(Y);
+            for (int o = 0; o < nterm; ++o) {
+              const Term tm = op_term(kind, o);
+              if (tm.p != p) continue;
+              const float2 cf = coef_of(tm, dy, dz);
+              float2* dst = dst_of(o);
+#pragma unroll
+              for (int j = 0; j < R1; ++j) dst[j * g.sn + m] = cmul(Y[j], cf);
+            }
           }
-        }
-        for (int o = 0; o < nout; ++o) {
-          float2 y[R1];
-#pragma unroll
-          for (int kx = 0; kx < R1; ++kx) y[kx] = FANIN ? Y[kx] : spec_mult<N>(op, t, o, kx, ky, kz, X[kx]);
-          dft<R1, 1>(y);
-          float2* dst = dst_of(o);
-#pragma unroll
-          for (int j = 0; j < R1; ++j) dst[j * g.sn + m] = y[j];
         }
       }
     }
     return;
   } else {
-    // X: forward transform of the current input (kx = l1 + R1*l2 of item
-    // (m, l1)); Y: fan-in accumulator
-    float2 X[IB][R2], Y[IB][R2];
-#pragma unroll
-    for (int i = 0; i < IB; ++i)
-#pragma unroll
-      for (int l2 = 0; l2 < R2; ++l2) Y[i][l2] = make_float2(0.f, 0.f);
-    for (int in = 0; in < nin; ++in) {
-      const float2* src = src_of(in);
+    // forward x transform of one (combined) input into X[item][l2], kx = l1 + R1*l2;
+    // the multiplied spectrum Y reuses the same registers
+    float2 X[IB][R2];
+    float2 (&Y)[IB][R2] = X;
+    auto forward = [&](int p) {
 #pragma unroll
       for (int i = 0; i < IA; ++i) {
         const int it = tid + i * kThreads;
@@ -551,8 +672,25 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_fused(FusedArgs a) {
           const int m = it % M, j2 = it / M;
           const bool ok = c0 + m < g.ncols;
           float2 v[R1];
+          if (FANIN) {
+            float dy, dz;
+            col_d(m, dy, dz);
 #pragma unroll
-          for (int j1 = 0; j1 < R1; ++j1) v[j1] = ok ? src[(R2 * j1 + j2) * g.sn + m] : make_float2(0.f, 0.f);
+            for (int j1 = 0; j1 < R1; ++j1) v[j1] = make_float2(0.f, 0.f);
+#pragma unroll 1
+            for (int in = 0; in < nterm; ++in) {
+              const Term tm = op_term(kind, in);
+              if (tm.p != p || !ok) continue;
+              const float2 cf = coef_of(tm, dy, dz);
+              const float2* src = src_of(in);
+#pragma unroll
+              for (int j1 = 0; j1 < R1; ++j1) v[j1] = cadd(v[j1], cmul(src[(R2 * j1 + j2) * g.sn + m], cf));
+            }
+          } else {
+            const float2* src = src_of(0);
+#pragma unroll
+            for (int j1 = 0; j1 < R1; ++j1) v[j1] = ok ? src[(R2 * j1 + j2) * g.sn + m] : make_float2(0.f, 0.f);
+          }
           dft<R1, -1>(v);
 #pragma unroll
           for (int l1 = 0; l1 < R1; ++l1)
@@ -568,41 +706,25 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_fused(FusedArgs a) {
 #pragma unroll
           for (int j2 = 0; j2 < R2; ++j2) X[i][j2] = lds[l1 * SA + j2 * M + m];
           dft<R2, -1>(X[i]);
-          if (FANIN) {
-            int ky, kz;
-            freq(m, ky, kz);
-            if (c0 + m >= g.ncols) { ky = 0; kz = 0; }
-#pragma unroll
-            for (int l2 = 0; l2 < R2; ++l2)
-              Y[i][l2] = cadd(Y[i][l2], spec_mult<N>(op, t, in, l1 + R1 * l2, ky, kz, X[i][l2]));
-          }
         }
       }
       __syncthreads();
-    }
-    for (int o = 0; o < nout; ++o) {
-      // multiply; inverse stage A' over l2 (R2 points); twiddle; exchange
+    };
+    // inverse x transform of Y (spectral, item layout) and store with the
+    // coefficients of every output term of power p (fan-in: output 0)
+    auto inverse_store = [&](int p) {
 #pragma unroll
       for (int i = 0; i < IB; ++i) {
         const int it = tid + i * kThreads;
         if (it < M * R1) {
           const int m = it % M, l1 = it / M;
-          int ky, kz;
-          freq(m, ky, kz);
-          if (c0 + m >= g.ncols) { ky = 0; kz = 0; }
-          float2 y[R2];
-#pragma unroll
-          for (int l2 = 0; l2 < R2; ++l2)
-            y[l2] = FANIN ? Y[i][l2] : spec_mult<N>(op, t, o, l1 + R1 * l2, ky, kz, X[i][l2]);
-          dft<R2, 1>(y);
+          dft<R2, 1>(Y[i]);   // in place: Y is rebuilt before the next use
 #pragma unroll
           for (int lp = 0; lp < R2; ++lp)
-            lds[lp * SB + l1 * M + m] = lp == 0 ? y[lp] : cmul(y[lp], tw_get<1>(t.tw_n, l1 * lp));
+            lds[lp * SB + l1 * M + m] = lp == 0 ? Y[i][lp] : cmul(Y[i][lp], tw_get<1>(t.tw_n, l1 * lp));
         }
       }
       __syncthreads();
-      // inverse stage B': item (m, l1') over l1 (R1 points) -> n = l1' + R2*l2'
-      float2* dst = dst_of(o);
 #pragma unroll
       for (int i = 0; i < IA; ++i) {
         const int it = tid + i * kThreads;
@@ -613,12 +735,83 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_fused(FusedArgs a) {
           for (int l1 = 0; l1 < R1; ++l1) v[l1] = lds[lp * SB + l1 * M + m];
           dft<R1, 1>(v);
           if (c0 + m < g.ncols) {
+            if (FANIN) {
+              float2* dst = dst_of(0);
 #pragma unroll
-            for (int l2p = 0; l2p < R1; ++l2p) dst[(lp + R2 * l2p) * g.sn + m] = v[l2p];
+              for (int l2p = 0; l2p < R1; ++l2p) dst[(lp + R2 * l2p) * g.sn + m] = v[l2p];
+            } else {
+              float dy, dz;
+              col_d(m, dy, dz);
+#pragma unroll 1
+              for (int o = 0; o < nterm; ++o) {
+                const Term tm = op_term(kind, o);
+                if (tm.p != p) continue;
+                const float2 cf = coef_of(tm, dy, dz);
+                float2* dst = dst_of(o);
+#pragma unroll
+                for (int l2p = 0; l2p < R1; ++l2p) dst[(lp + R2 * l2p) * g.sn + m] = cmul(v[l2p], cf);
+              }
+            }
           }
         }
       }
       __syncthreads();
+    };
+
+    if (FANIN) {
+      // one launch per basis power p (increasing): the inputs of power p are
+      // combined and forward transformed, scaled by c(k) D(w_x)^p and added
+      // to the partial sum of the earlier bases.  The partial sum is parked
+      // in x-spectral order in this tile's region of an input of the first
+      // basis (read by this tile before it is written); the last launch
+      // inverse transforms the total into output 0.
+      const int p = a.pbasis;
+      forward(p);
+      float2* park = (mode == 0 ? a.park_main : a.park_nyq) + off;
+#pragma unroll
+      for (int i = 0; i < IB; ++i) {
+        const int it = tid + i * kThreads;
+        if (it < M * R1) {
+          const int m = it % M, l1 = it / M;
+          int ky, kz;
+          freq(m, ky, kz);
+#pragma unroll
+          for (int l2 = 0; l2 < R2; ++l2) {
+            const int kx = l1 + R1 * l2;
+            float2 v = cscale(X[i][l2], common_factor<N>(op, t, kx, ky, kz) * powp(t.dxy[kx], p));
+            if (!a.first && c0 + m < g.ncols) v = cadd(v, park[kx * g.sn + m]);
+            Y[i][l2] = v;
+          }
+          if (!a.last && c0 + m < g.ncols) {
+#pragma unroll
+            for (int l2 = 0; l2 < R2; ++l2) park[(l1 + R1 * l2) * g.sn + m] = Y[i][l2];
+          }
+        }
+      }
+      if (a.last) inverse_store(0);
+    } else {
+      // fan-out: this launch handles the outputs of one basis power p: the
+      // input tile is transformed, scaled by c(k) D(w_x)^p and inverse
+      // transformed.  The host launches the bases in increasing p (one
+      // launch each, so that the register arrays of one basis are all that
+      // is live); an output that aliases the input has the highest p of its
+      // op, so the input is intact for every earlier basis.
+      const int p = a.pbasis;
+      forward(0);
+#pragma unroll
+      for (int i = 0; i < IB; ++i) {
+        const int it = tid + i * kThreads;
+        const int m = it % M, l1 = it / M;
+        int ky, kz;
+        freq(m, ky, kz);
+#pragma unroll
+        for (int l2 = 0; l2 < R2; ++l2) {
+          const int kx = l1 + R1 * l2;
+          Y[i][l2] = it < M * R1 ? cscale(X[i][l2], common_factor<N>(op, t, kx, ky, kz) * powp(t.dxy[kx], p))
+                                 : make_float2(0.f, 0.f);
+        }
+      }
+      inverse_store(p);
     }
   }
 }
@@ -688,6 +881,14 @@ void zc2r(const FftTables& t, Field* f, int nf, hipStream_t s) {
 }
 
 template <int N>
+void zc2r3i(const FftTables& t, const Field* f, float* out, hipStream_t s) {
+  using G = ZGeom3<N>;
+  dim3 grid((N * N) / G::L3);
+  hipLaunchKernelGGL((k_c2r_z3i<N>), grid, dim3(kThreads), 0, s, f[0].r, f[1].r, f[2].r, f[0].q, f[1].q, f[2].q,
+                     out, t.tw_h, t.tw_n);
+}
+
+template <int N>
 void xfused(const FftTables& t, const Field& in, const SpecOp& op, hipStream_t s) {
   constexpr int M = Cols<N>::M;
   FusedArgs a;
@@ -699,10 +900,35 @@ void xfused(const FftTables& t, const Field& in, const SpecOp& op, hipStream_t s
   a.gp = ColGeom{0, (long)N, N, cdiv(N, M)};
   a.nb_main = N * a.gm.ntc;
   const dim3 grid(a.nb_main + a.gp.ntc);
-  if (op_fan_in(op.kind))
+  a.pbasis = 0;
+  a.first = a.last = 1;
+  a.park_main = nullptr;
+  a.park_nyq = nullptr;
+  const bool fan_in = op_fan_in(op.kind);
+  const int nterm = fan_in ? op.n_in : op.n_out;
+  int pmask = 0, first_in = -1;
+  for (int o = 0; o < nterm; ++o) pmask |= 1 << op_term(op.kind, o).p;
+  if (fan_in && Split<N>::R2 == 1) {   // whole columns in registers: all bases in one launch
     hipLaunchKernelGGL((k_fft_x_fused<N, M, true>), grid, dim3(kThreads), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_fft_x_fused<N, M, false>), grid, dim3(kThreads), 0, s, a);
+    return;
+  }
+  const int pfirst = __builtin_ctz(pmask), plast = 31 - __builtin_clz(pmask);
+  if (fan_in) {
+    for (int o = 0; o < nterm && first_in < 0; ++o)
+      if (op_term(op.kind, o).p == pfirst) first_in = o;
+    a.park_main = op.in_c[first_in];
+    a.park_nyq = op.in_q[first_in];
+  }
+  for (int p = pfirst; p <= plast; ++p) {
+    if (!(pmask >> p & 1)) continue;
+    a.pbasis = p;
+    a.first = p == pfirst;
+    a.last = p == plast;
+    if (fan_in)
+      hipLaunchKernelGGL((k_fft_x_fused<N, M, true>), grid, dim3(kThreads), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_fft_x_fused<N, M, false>), grid, dim3(kThreads), 0, s, a);
+  }
 }
 
 // chunks of at most 3 fields per launch (blockIdx.y selects the field)
@@ -776,6 +1002,12 @@ void fft_x_inverse(const FftTables& t, Field* f, int nf, hipStream_t s) {
 
 void fft_x_fused(const FftTables& t, const Field& in, const SpecOp& op, hipStream_t s) {
 #define CALL(N) xfused<N>(t, in, op, s)
+  PM_FFT_SWITCH(t.n, CALL)
+#undef CALL
+}
+
+void fft_z_c2r_interleaved3(const FftTables& t, const Field* f, float* out, hipStream_t s) {
+#define CALL(N) zc2r3i<N>(t, f, out, s)
   PM_FFT_SWITCH(t.n, CALL)
 #undef CALL
 }

@@ -7,11 +7,13 @@
 
 namespace pmk {
 
+// Tiles of tx * ty * tz cells (tz is the contiguous axis): ntx * nty * ntz
+// tiles, tile index (ix * nty + iy) * ntz + iz.
 struct TileGeom {
-  int n = 0;        // mesh cells per side
-  int t = 0;        // tile side in cells
-  int nt = 0;       // tiles per side
-  int ntiles = 0;   // nt^3
+  int n = 0;                   // mesh cells per side
+  int tx = 0, ty = 0, tz = 0;  // tile size in cells
+  int ntx = 0, nty = 0, ntz = 0;
+  int ntiles = 0;
 };
 
 struct LptParticleArgs {
@@ -53,13 +55,11 @@ enum ReadoutFlags : int {
 
 struct ReadoutArgs {
   TileGeom g;
+  long np = 0;
   float* pos = nullptr;            // sorted
   float* mom = nullptr;            // sorted, may be null
   const uint32_t* id = nullptr;    // sorted ids
-  const uint32_t* off = nullptr;   // bin offsets
-  const float* f0 = nullptr;
-  const float* f1 = nullptr;
-  const float* f2 = nullptr;
+  const float* fi = nullptr;       // force mesh, interleaved [n^3][3]
   float kick_a = 0.f, kick_b = 0.f, drift = 0.f;
   int flags = 0;
   float* force_out = nullptr;
@@ -104,11 +104,10 @@ void launch_scale(float* p, long n, float v, hipStream_t s);
 // adjoint kernels (adjoint.hip)
 void launch_paint3w(const float* pos, const uint32_t* id, const uint32_t* off, const TileGeom& g, const float* pbar,
                     float k, float* o0, float* o1, float* o2, hipStream_t s);
-void launch_readout_grad3(const float* pos, const uint32_t* id, const uint32_t* off, const TileGeom& g,
-                          const float* m0, const float* m1, const float* m2, const float* pbar, float k, float* xbar,
+void launch_readout_grad3(const float* pos, const uint32_t* id, long np, int n, const float* fi, const float* pbar,
+                          float k, float* xbar, hipStream_t s);
+void launch_readout_grad1(const float* pos, const uint32_t* id, long np, int n, const float* m0, float k, float* xbar,
                           hipStream_t s);
-void launch_readout_grad1(const float* pos, const uint32_t* id, const uint32_t* off, const TileGeom& g,
-                          const float* m0, float k, float* xbar, hipStream_t s);
 void launch_axpy(float* y, const float* x, float a, long n, hipStream_t s);
 void launch_lpt_sbar(const float* xbar, const float* pbar, long n3, float cx1, float cp1, float cx2, float cp2,
                      float* const* s1, float* const* s2, hipStream_t s);

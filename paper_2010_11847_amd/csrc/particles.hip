@@ -177,164 +177,209 @@ __global__ void k_scatter(ScatterArgs a) {
 // ---- paint ---------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void k_paint(const float* __restrict__ pos, const uint32_t* __restrict__ off,
                                                     TileGeom g, float* __restrict__ out, float scale, float offset) {
-  __shared__ float acc[kTileMax * kTileMax * kTileMax];
-  const int T = g.t, nt = g.nt, n = g.n;
+  __shared__ float acc[kTileCells];
+  __shared__ RangeTable rt;
+  const int TX = g.tx, TY = g.ty, TZ = g.tz, n = g.n;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int tz = tile % nt, ty = (tile / nt) % nt, tx = tile / (nt * nt);
-  const int ox = tx * T, oy = ty * T, oz = tz * T;
-  const int cells = T * T * T;
+  const int tz = tile % g.ntz, ty = (tile / g.ntz) % g.nty, tx = tile / (g.ntz * g.nty);
+  const int ox = tx * TX, oy = ty * TY, oz = tz * TZ;
+  const int cells = TX * TY * TZ;
   for (int c = threadIdx.x; c < cells; c += kThreads) acc[c] = 0.f;
-  __syncthreads();
-  for (int e = 0; e < 8; ++e) {
-    const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
-    const int sx = (tx - ex + nt) % nt, sy = (ty - ey + nt) % nt, sz = (tz - ez + nt) % nt;
-    const uint32_t src = ((uint32_t)sx * nt + sy) * nt + sz;
-    for (int cls = 0; cls < 8; ++cls) {
-      if ((cls & e) != e) continue;
-      const uint32_t b0 = off[src * 8 + cls], b1 = off[src * 8 + cls + 1];
-      for (uint32_t j = b0 + threadIdx.x; j < b1; j += kThreads) {
-        int ix, iy, iz;
-        float fx, fy, fz;
-        cic_base(pos[3 * (long)j + 0], n, ix, fx);
-        cic_base(pos[3 * (long)j + 1], n, iy, fy);
-        cic_base(pos[3 * (long)j + 2], n, iz, fz);
-        // local base cell in [-1, T-1]
-        int lx = (ix - ox) & (n - 1), ly = (iy - oy) & (n - 1), lz = (iz - oz) & (n - 1);
-        if (lx > T) lx -= n;
-        if (ly > T) ly -= n;
-        if (lz > T) lz -= n;
-        const float wx[2] = {1.f - fx, fx}, wy[2] = {1.f - fy, fy}, wz[2] = {1.f - fz, fz};
+  build_ranges(rt, off, tx, ty, tz, g);
+  const uint32_t total = rt.pre[27];
+  constexpr int kBatch = 4;   // particles whose loads are in flight together
+  for (uint32_t base = 0; base < total; base += kThreads * kBatch) {
+    float px[kBatch][3];
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          const int cx = lx + a;
-          if (cx < 0 || cx >= T) continue;
+    for (int u = 0; u < kBatch; ++u) {
+      const uint32_t idx = base + threadIdx.x + u * kThreads;
+      if (idx < total) {
+        const uint32_t j = range_particle(rt, idx);
 #pragma unroll
-          for (int b = 0; b < 2; ++b) {
-            const int cy = ly + b;
-            if (cy < 0 || cy >= T) continue;
-            const float wxy = wx[a] * wy[b];
+        for (int d = 0; d < 3; ++d) px[u][d] = pos[3 * (long)j + d];
+      }
+    }
 #pragma unroll
-            for (int c = 0; c < 2; ++c) {
-              const int cz = lz + c;
-              if (cz < 0 || cz >= T) continue;
-              atomicAdd(&acc[(cx * T + cy) * T + cz], wxy * wz[c]);
-            }
-          }
+    for (int u = 0; u < kBatch; ++u) {
+    if (base + threadIdx.x + u * kThreads >= total) continue;
+    int ix, iy, iz;
+    float fx, fy, fz;
+    cic_base(px[u][0], n, ix, fx);
+    cic_base(px[u][1], n, iy, fy);
+    cic_base(px[u][2], n, iz, fz);
+    // local base cell in [-1, T-1] (-1: the particle sits in the lower neighbour)
+    int lx = (ix - ox) & (n - 1), ly = (iy - oy) & (n - 1), lz = (iz - oz) & (n - 1);
+    if (lx > TX) lx -= n;
+    if (ly > TY) ly -= n;
+    if (lz > TZ) lz -= n;
+    const float wx[2] = {1.f - fx, fx}, wy[2] = {1.f - fy, fy}, wz[2] = {1.f - fz, fz};
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int cx = lx + a;
+      if (cx < 0 || cx >= TX) continue;
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int cy = ly + b;
+        if (cy < 0 || cy >= TY) continue;
+        const float wxy = wx[a] * wy[b];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const int cz = lz + c;
+          if (cz < 0 || cz >= TZ) continue;
+          atomicAdd(&acc[(cx * TY + cy) * TZ + cz], wxy * wz[c]);
         }
       }
+    }
     }
   }
   __syncthreads();
   for (int c = threadIdx.x; c < cells; c += kThreads) {
-    const int cz = c % T, cy = (c / T) % T, cx = c / (T * T);
+    const int cz = c % TZ, cy = (c / TZ) % TY, cx = c / (TZ * TY);
     out[((long)(ox + cx) * n + (oy + cy)) * n + (oz + cz)] = acc[c] * scale + offset;
   }
 }
 
 // ---- readout + kick + drift ---------------------------------------------------------
+// Slot of a new key among the 27 neighbour tiles x 8 classes of the
+// reference tile (rx, ry, rz), or -1 when it is further away (or the tile
+// grid is too small for the neighbourhood to be unambiguous).
+__device__ __forceinline__ int key_slot(uint32_t key, int rx, int ry, int rz, const TileGeom& g) {
+  if (g.ntx < 3 || g.nty < 3 || g.ntz < 3) return -1;
+  const uint32_t tile = key >> 3;
+  const int kz = tile % g.ntz, ky = (tile / g.ntz) % g.nty, kx = tile / (g.ntz * g.nty);
+  auto d = [](int a, int b, int nt) {
+    int v = a - b;
+    if (v > nt / 2) v -= nt;
+    if (v < -nt / 2) v += nt;
+    return v;
+  };
+  const int dx = d(kx, rx, g.ntx), dy = d(ky, ry, g.nty), dz = d(kz, rz, g.ntz);
+  if (dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1) return -1;
+  return (((dx + 1) * 3 + (dy + 1)) * 3 + (dz + 1)) * 8 + (int)(key & 7u);
+}
+
+__device__ __forceinline__ uint32_t slot_key(int slot, int rx, int ry, int rz, const TileGeom& g) {
+  const int cls = slot & 7, s = slot >> 3;
+  const int dz = s % 3 - 1, dy = (s / 3) % 3 - 1, dx = s / 9 - 1;
+  const int kx = (rx + dx + g.ntx) % g.ntx, ky = (ry + dy + g.nty) % g.nty, kz = (rz + dz + g.ntz) % g.ntz;
+  return ((((uint32_t)kx * g.nty + ky) * g.ntz + kz) << 3) | (uint32_t)cls;
+}
+
+// One tile-sorted particle per thread: CIC gather of the 8 corners from the
+// interleaved force mesh (one 12-byte load per corner; sorted neighbours
+// share cache lines), kicks, drift, wrap, and the tile key + rank of the new
+// position.  Ranks are counted per workgroup in LDS by slot (27 neighbour
+// tiles x 8 classes of the workgroup's first particle), then one global
+// atomic per used slot reserves the range.
 __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
-  __shared__ float4 ft[(kTileMax + 1) * (kTileMax + 1) * (kTileMax + 1)];
+  __shared__ uint32_t slot_cnt[216];
+  __shared__ uint32_t slot_base[216];
   const TileGeom& g = a.g;
-  const int T = g.t, nt = g.nt, n = g.n, T1 = T + 1;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const uint32_t b0 = a.off[tile * 8], b1 = a.off[tile * 8 + 8];
-  if (b0 == b1) return;   // uniform across the workgroup
-  const int tz = tile % nt, ty = (tile / nt) % nt, tx = tile / (nt * nt);
-  const int ox = tx * T, oy = ty * T, oz = tz * T;
-  for (int c = threadIdx.x; c < T1 * T1 * T1; c += kThreads) {
-    const int cz = c % T1, cy = (c / T1) % T1, cx = c / (T1 * T1);
-    const long gi = ((long)((ox + cx) & (n - 1)) * n + ((oy + cy) & (n - 1))) * n + ((oz + cz) & (n - 1));
-    ft[c] = make_float4(a.f0[gi], a.f1[gi], a.f2[gi], 0.f);
+  const int n = g.n;
+  const long chunk = xcd_tile(blockIdx.x, gridDim.x);
+  const long j0 = chunk * kThreads;
+  const long j = j0 + threadIdx.x;
+  const bool valid = j < a.np;
+  const bool keys = (a.flags & RO_KEYS) != 0;
+  int rx = 0, ry = 0, rz = 0;
+  if (keys) {
+    for (int i = threadIdx.x; i < 216; i += kThreads) slot_cnt[i] = 0u;
+    int ix, iy, iz;
+    float t;
+    cic_base(a.pos[3 * j0 + 0], n, ix, t);
+    cic_base(a.pos[3 * j0 + 1], n, iy, t);
+    cic_base(a.pos[3 * j0 + 2], n, iz, t);
+    rx = ix / g.tx;
+    ry = iy / g.ty;
+    rz = iz / g.tz;
+    __syncthreads();
+  }
+  int slot = -1;
+  if (valid) {
+    const float nf = (float)n;
+    float x[3], p[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) x[d] = a.pos[3 * j + d];
+    if (a.mom) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) p[d] = a.mom[3 * j + d];
+    }
+    int ix, iy, iz;
+    float fx, fy, fz;
+    cic_base(x[0], n, ix, fx);
+    cic_base(x[1], n, iy, fy);
+    cic_base(x[2], n, iz, fz);
+    const int jx = (ix + 1) & (n - 1), jy = (iy + 1) & (n - 1), jz = (iz + 1) & (n - 1);
+    const long rows[4] = {((long)ix * n + iy) * n, ((long)ix * n + jy) * n, ((long)jx * n + iy) * n,
+                          ((long)jx * n + jy) * n};
+    const float wxy[4] = {(1.f - fx) * (1.f - fy), (1.f - fx) * fy, fx * (1.f - fy), fx * fy};
+    float F[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float* c0 = a.fi + 3 * (rows[r] + iz);
+      const float* c1 = a.fi + 3 * (rows[r] + jz);
+      const float w0 = wxy[r] * (1.f - fz), w1 = wxy[r] * fz;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) F[d] += w0 * c0[d] + w1 * c1[d];
+    }
+    const uint32_t id = a.id ? a.id[j] : (uint32_t)j;
+    if (a.flags & RO_FORCE_BYID) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) a.force_out[3 * (long)id + d] = F[d];
+    }
+    if (a.flags & RO_KICK) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) p[d] += F[d] * a.kick_a;
+    }
+    if (a.flags & RO_CKPT) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        a.ckpt_x[3 * (long)id + d] = x[d];
+        a.ckpt_p[3 * (long)id + d] = p[d];
+      }
+    }
+    if (a.flags & RO_KICK) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) p[d] += F[d] * a.kick_b;
+    }
+    if (a.flags & RO_DRIFT) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) x[d] = wrap_pos(x[d] + p[d] * a.drift, nf);
+    }
+    if (a.flags & RO_WRITE_SORTED) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        a.pos[3 * j + d] = x[d];
+        if (a.mom) a.mom[3 * j + d] = p[d];
+      }
+    }
+    if (a.flags & RO_XP_BYID) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        a.pos_out[3 * (long)id + d] = x[d];
+        a.mom_out[3 * (long)id + d] = p[d];
+      }
+    }
+    if (keys) {
+      int kx, ky, kz;
+      float t;
+      cic_base(x[0], n, kx, t);
+      cic_base(x[1], n, ky, t);
+      cic_base(x[2], n, kz, t);
+      const uint32_t key = tile_key(kx, ky, kz, g);
+      slot = key_slot(key, rx, ry, rz, g);
+      a.key_out[j] = key;
+      a.rank_out[j] = slot >= 0 ? atomicAdd(&slot_cnt[slot], 1u) : atomicAdd(&a.count[key], 1u);
+    }
+  }
+  if (!keys) return;
+  __syncthreads();
+  for (int i = threadIdx.x; i < 216; i += kThreads) {
+    const uint32_t c = slot_cnt[i];
+    slot_base[i] = c ? atomicAdd(&a.count[slot_key(i, rx, ry, rz, g)], c) : 0u;
   }
   __syncthreads();
-  const float nf = (float)n;
-  for (uint32_t base = b0; base < b1; base += kThreads) {
-    const uint32_t j = base + threadIdx.x;
-    const bool valid = j < b1;
-    uint32_t key = 0;
-    if (valid) {
-      float x[3], p[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-      for (int d = 0; d < 3; ++d) x[d] = a.pos[3 * (long)j + d];
-      if (a.mom) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) p[d] = a.mom[3 * (long)j + d];
-      }
-      int ix, iy, iz;
-      float fx, fy, fz;
-      cic_base(x[0], n, ix, fx);
-      cic_base(x[1], n, iy, fy);
-      cic_base(x[2], n, iz, fz);
-      const int lx = (ix - ox) & (n - 1), ly = (iy - oy) & (n - 1), lz = (iz - oz) & (n - 1);
-      const float wx[2] = {1.f - fx, fx}, wy[2] = {1.f - fy, fy}, wz[2] = {1.f - fz, fz};
-      float F[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-      for (int aa = 0; aa < 2; ++aa)
-#pragma unroll
-        for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-          for (int cc = 0; cc < 2; ++cc) {
-            const float w = wx[aa] * wy[bb] * wz[cc];
-            const float4 v = ft[((lx + aa) * T1 + (ly + bb)) * T1 + (lz + cc)];
-            F[0] += w * v.x;
-            F[1] += w * v.y;
-            F[2] += w * v.z;
-          }
-      const uint32_t id = a.id ? a.id[j] : j;
-      if (a.flags & RO_FORCE_BYID) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) a.force_out[3 * (long)id + d] = F[d];
-      }
-      if (a.flags & RO_KICK) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) p[d] += F[d] * a.kick_a;
-      }
-      if (a.flags & RO_CKPT) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          a.ckpt_x[3 * (long)id + d] = x[d];
-          a.ckpt_p[3 * (long)id + d] = p[d];
-        }
-      }
-      if (a.flags & RO_KICK) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) p[d] += F[d] * a.kick_b;
-      }
-      if (a.flags & RO_DRIFT) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) x[d] = wrap_pos(x[d] + p[d] * a.drift, nf);
-      }
-      if (a.flags & RO_WRITE_SORTED) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          a.pos[3 * (long)j + d] = x[d];
-          if (a.mom) a.mom[3 * (long)j + d] = p[d];
-        }
-      }
-      if (a.flags & RO_XP_BYID) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          a.pos_out[3 * (long)id + d] = x[d];
-          a.mom_out[3 * (long)id + d] = p[d];
-        }
-      }
-      if (a.flags & RO_KEYS) {
-        int jx, jy, jz;
-        float t;
-        cic_base(x[0], n, jx, t);
-        cic_base(x[1], n, jy, t);
-        cic_base(x[2], n, jz, t);
-        key = tile_key(jx, jy, jz, g);
-      }
-    }
-    if (a.flags & RO_KEYS) {
-      const uint32_t r = agg_rank(a.count, key, valid);
-      if (valid) {
-        a.key_out[j] = key;
-        a.rank_out[j] = r;
-      }
-    }
-  }
+  if (valid && slot >= 0) a.rank_out[j] += slot_base[slot];
 }
 
 // elementwise kick + drift with a given per-particle force (first half of a
@@ -488,7 +533,8 @@ void launch_paint(const float* pos_sorted, const uint32_t* off, const TileGeom& 
 }
 
 void launch_readout(const ReadoutArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_readout, dim3(a.g.ntiles), dim3(kThreads), 0, s, a);
+  const int grid = (int)((a.np + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(k_readout, dim3(grid), dim3(kThreads), 0, s, a);
 }
 
 void launch_kick_drift(float* pos, float* mom, const float* f, long np, float kick, float drift, float nmesh,

@@ -9,7 +9,7 @@
 
 namespace pmk {
 
-constexpr int kTileMax = 16;   // largest tile side (LDS sizing)
+constexpr int kTileCells = 16 * 16 * 32;   // largest tile (LDS sizing)
 
 // blockIdx -> tile so that consecutive tiles of one launch land on the same
 // XCD (workgroups are dispatched round-robin over the 8 XCDs).
@@ -34,10 +34,9 @@ static __device__ __forceinline__ float wrap_pos(float x, float n) {
 }
 
 static __device__ __forceinline__ uint32_t tile_key(int ix, int iy, int iz, const TileGeom& g) {
-  const int t = g.t;
-  const uint32_t tile = ((uint32_t)(ix / t) * g.nt + (uint32_t)(iy / t)) * g.nt + (uint32_t)(iz / t);
-  const uint32_t c = (uint32_t)((ix % t) == t - 1) | ((uint32_t)((iy % t) == t - 1) << 1) |
-                     ((uint32_t)((iz % t) == t - 1) << 2);
+  const uint32_t tile = ((uint32_t)(ix / g.tx) * g.nty + (uint32_t)(iy / g.ty)) * g.ntz + (uint32_t)(iz / g.tz);
+  const uint32_t c = (uint32_t)((ix % g.tx) == g.tx - 1) | ((uint32_t)((iy % g.ty) == g.ty - 1) << 1) |
+                     ((uint32_t)((iz % g.tz) == g.tz - 1) << 2);
   return tile * 8u + c;
 }
 
@@ -60,6 +59,55 @@ static __device__ __forceinline__ uint32_t agg_rank(uint32_t* count, uint32_t ke
     active &= ~mask;
   }
   return mine;
+}
+
+// The 27 particle ranges a paint workgroup gathers: for every lower
+// neighbour offset e in {0,1}^3 of tile (tx, ty, tz) (e = 0: the tile
+// itself), the bins of classes c with (c & e) == e.  Filled cooperatively
+// (one thread per range, loads issued in parallel); rpre holds the inclusive
+// prefix sums of the range lengths, rstart the first particle of each range.
+struct RangeTable {
+  uint32_t start[27];
+  uint32_t pre[28];
+};
+
+static __device__ __forceinline__ void build_ranges(RangeTable& rt, const uint32_t* __restrict__ off, int tx, int ty,
+                                                    int tz, const TileGeom& g) {
+  const int r = threadIdx.x;
+  uint32_t len = 0;
+  if (r < 27) {
+    // enumerate (e, cls) pairs with (cls & e) == e in a fixed order
+    int k = 0, e_sel = 0, c_sel = 0;
+    for (int e = 0; e < 8; ++e)
+      for (int c = 0; c < 8; ++c)
+        if ((c & e) == e) {
+          if (k == r) { e_sel = e; c_sel = c; }
+          ++k;
+        }
+    const int sx = (tx - (e_sel & 1) + g.ntx) % g.ntx, sy = (ty - ((e_sel >> 1) & 1) + g.nty) % g.nty,
+              sz = (tz - ((e_sel >> 2) & 1) + g.ntz) % g.ntz;
+    const uint32_t bin = (((uint32_t)sx * g.nty + sy) * g.ntz + sz) * 8 + c_sel;
+    const uint32_t b0 = off[bin], b1 = off[bin + 1];
+    rt.start[r] = b0;
+    len = b1 - b0;
+    rt.pre[r + 1] = len;
+  }
+  if (r == 0) rt.pre[0] = 0;
+  __syncthreads();
+  if (r == 0) {
+    for (int i = 1; i <= 27; ++i) rt.pre[i] += rt.pre[i - 1];
+  }
+  __syncthreads();
+}
+
+// particle index of flattened position idx < rt.pre[27]
+static __device__ __forceinline__ uint32_t range_particle(const RangeTable& rt, uint32_t idx) {
+  int lo = 0, hi = 27;   // find r with pre[r] <= idx < pre[r+1]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (rt.pre[mid] <= idx) lo = mid; else hi = mid;
+  }
+  return rt.start[lo] + (idx - rt.pre[lo]);
 }
 
 }  // namespace pmk

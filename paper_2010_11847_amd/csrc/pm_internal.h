@@ -43,7 +43,8 @@ struct FftTables {
 // transforms of the fused x pass.
 // Fan-out kinds read one input spectrum and write n_out outputs; fan-in
 // kinds (the transposes, used by the adjoint) read n_in inputs and write the
-// sum of their conjugate-multiplied spectra to one output.
+// sum of their conjugate-multiplied spectra to one output; they overwrite
+// their inputs.
 enum SpecOpKind : int {
   OP_IDENTITY = 0,   // 1 output: X (round trip, scaled)
   OP_FORCE = 1,      // 3 outputs: i D_d g X with g = scale W^-n S / K^2
@@ -70,8 +71,10 @@ struct SpecOp {
   const float* pk = nullptr;  // table indexed by integer |n|^2
   float2* out_c[kMaxOut] = {};
   float2* out_q[kMaxOut] = {};
-  const float2* in_c[kMaxOut] = {};   // fan-in inputs (forward y transformed)
-  const float2* in_q[kMaxOut] = {};
+  // fan-in inputs (forward y transformed); the op consumes them: the first
+  // input of the lowest D(w_x) power holds partial sums between launches
+  float2* in_c[kMaxOut] = {};
+  float2* in_q[kMaxOut] = {};
 };
 
 // ---- FFT launchers (fft.hip) ---------------------------------------------
@@ -86,6 +89,8 @@ void fft_x_fused(const FftTables& t, const Field& in, const SpecOp& op, hipStrea
 void fft_z_r2c(const FftTables& t, Field* f, int nf, hipStream_t s);
 void fft_y(const FftTables& t, Field* f, int nf, int dir, hipStream_t s);
 void fft_z_c2r(const FftTables& t, Field* f, int nf, hipStream_t s);
+// z pass of three fields written as one interleaved real mesh out[(x*N+y)*N+z][3]
+void fft_z_c2r_interleaved3(const FftTables& t, const Field* f, float* out, hipStream_t s);
 // Inverse: y pass then z pass (complex + Nyquist plane -> real), unnormalised.
 void fft_c2r_yz(const FftTables& t, Field* f, int nf, hipStream_t s);
 // Plain inverse x pass (complex, in place).

@@ -1,0 +1,58 @@
+"""Continuous batching on the GPU: every request's result in the mix equals
+its result when served alone (within the run tolerance), for forward and
+forward + gradient requests of different shapes."""
+import numpy as np
+import pytest
+
+from oracle import pm as opm
+from paper_2010_11847_amd import serve
+from tests.gpu_helpers import banner, rel, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def small_trace():
+    mix = []
+    for i in range(10):
+        if i % 3 == 0:
+            mix.append(serve.SimRequest(i, 16, 16, 32.0, 3 + i % 3, 1000 + i, True, 0.0))
+        elif i % 3 == 1:
+            mix.append(serve.SimRequest(i, 16, 32, 32.0, 4 + i % 4, 1000 + i, False, 0.0))
+        else:
+            mix.append(serve.SimRequest(i, 32, 32, 64.0, 5, 1000 + i, False, 0.0))
+    return mix
+
+
+def test_results_same_alone_and_in_mix(gpu):
+    banner("serve mix vs alone")
+    trace = small_trace()
+    ex = serve.GpuExecutor()
+    mixed = {}
+    rep = serve.serve(trace, ex, budget_bytes=8 << 30, slots_per_class=4, realtime=False, results=mixed)
+    s = rep.summary()
+    banner(f"  {s}")
+    assert s["completed"] == len(trace) and rep.max_active > 1
+    for req in trace:
+        alone = {}
+        serve.serve_fifo([req], serve.GpuExecutor(), realtime=False, results=alone)
+        a, m = alone[req.rid], mixed[req.rid]
+        d = opm.min_image(to_np(m["pos"]).astype(np.float64) - to_np(a["pos"]), req.n_mesh)
+        rms = float(np.sqrt((d ** 2).sum(1).mean()))
+        assert rms < 1e-4, (req.rid, rms)
+        assert rel(to_np(m["delta"]), to_np(a["delta"])) < 1e-4
+        if req.with_grad:
+            assert rel(to_np(m["grad_noise"]), to_np(a["grad_noise"])) < 1e-4
+            assert float(m["loss"]) == pytest.approx(float(a["loss"]), rel=1e-5)
+
+
+def test_tiny_budget_and_oversize_rejection(gpu):
+    banner("serve tiny budget")
+    ex = serve.GpuExecutor(keep_results=False)
+    trace = [serve.SimRequest(i, 16, 16, 32.0, 3, 1000 + i, False, 0.0) for i in range(4)]
+    big = serve.SimRequest(99, 64, 128, 128.0, 3, 7, False, 0.0)
+    one = serve.footprint_bytes(trace[0], ex.workspace_bytes(trace[0]))
+    rep = serve.serve(trace + [big], ex, budget_bytes=one, slots_per_class=4, realtime=False)
+    ok = [c for c in rep.completions if c.ok]
+    assert len(ok) == 4 and rep.max_active == 1
+    bad = [c for c in rep.completions if c.rid == 99][0]
+    assert not bad.ok and "exceeds the HBM budget" in bad.error
