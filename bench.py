@@ -47,6 +47,41 @@ def kernel_bytes(w, np3):
     }
 
 
+def kernel_source_hash():
+    """sha256 over the kernel sources (csrc/*.hip, *.h, *.cpp and include/pm.h),
+    the key that ties a committed counter summary to the code it measured."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2010_11847_amd", "csrc")
+    files = sorted(f for f in os.listdir(csrc) if f.endswith((".hip", ".h", ".cpp")))
+    h = hashlib.sha256()
+    paths = [os.path.join(csrc, f) for f in files] + [os.path.join(ROOT, "include", "pm.h")]
+    for f, path in zip(files + ["pm.h"], paths):
+        with open(path, "rb") as fh:
+            h.update(f.encode())
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, kernel_class):
+    """HBM bytes per launch of one kernel class from the committed rocprofv3
+    counter summary profiles/hbm_traffic_<workload>.txt, or None when the
+    summary is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    sha, rows = None, {}
+    with open(path) as fh:
+        for line in fh:
+            parts = line.split()
+            if len(parts) >= 2 and parts[0] == "sources_sha256:":
+                sha = parts[1]
+            elif len(parts) >= 4 and parts[0] == "class":
+                rows[parts[1]] = float(parts[2]) + float(parts[3])
+    if sha != kernel_source_hash() or kernel_class not in rows:
+        return None
+    return rows[kernel_class]
+
+
 def cpu_baseline(seconds_hint=20.0):
     """The oracle (FP64 NumPy, unmodified) on a bounded sample: the same
     recipe (B = 2, 1 Mpc/h cells, no-wiggle P(k), 2LPT at a = 0.1) at
@@ -178,8 +213,9 @@ def main():
             kernels[name] = ent
         dom = max((k for k in kernels if k in nbytes), key=lambda k: kernels[k]["total_ms"])
         ach = kernels[dom]["GBps"]
+        traffic = measured_traffic(w.name, dom)
         roofline = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "bytes_per_launch": nbytes[dom], "avg_launch_ms": kernels[dom]["avg_ms"]}
         print(f"[bench] kernels {json.dumps(kernels)}", file=sys.stderr, flush=True)
 

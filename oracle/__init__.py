@@ -6,7 +6,7 @@ product path (the HIP library and its Python binding) never calls it and
 shares no code with it.
 
 The oracle is deliberately plain and slow: NumPy/SciPy in float64, library
-FFTs (``numpy.fft``) as single steps, no blocking, fusion or reordering beyond
+FFTs (``scipy.fft``) as single steps, no blocking, fusion or reordering beyond
 what the method states.  Each function cites the passage of the paper
 (Modi, Lanusse & Seljak, "FlowPM: Distributed TensorFlow implementation of the
 FastPM cosmological N-body solver", arXiv:2010.11847) that it follows; where

@@ -156,6 +156,11 @@ def eh_nowiggle_transfer(k, cosmo):
 
     k in h/Mpc.  Sound horizon fit s, shape suppression alpha_Gamma, effective
     shape Gamma_eff(k), and T0(q) = L0 / (L0 + C0 q^2).
+
+    Parity unpinned beyond its limits: the tests pin T0 -> 1 as k -> 0, the
+    monotone fall-off and the sigma8 normalisation of the resulting P(k); the
+    fitting formula's intermediate values have no independent source here
+    (the paper names no linear P(k); this spectrum stands in for it).
     """
     k = np.asarray(k, dtype=np.float64)
     om, ob, h = cosmo.omega_m, cosmo.omega_b, cosmo.h

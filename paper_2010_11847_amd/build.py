@@ -30,12 +30,19 @@ def _compile(src: str, build_dir: str) -> str:
     obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
     path = os.path.join(CSRC, src)
     if src.endswith(".hip"):
-        cmd = [HIPCC, *COMMON, *DEVICE, "-c", path, "-o", obj]
+        # the compiler's per-kernel resource report (registers, LDS, scratch)
+        # is kept beside the object; a test rejects kernels that use scratch
+        cmd = [HIPCC, *COMMON, *DEVICE, "-Rpass-analysis=kernel-resource-usage", "-c", path, "-o", obj]
     else:
-        cmd = [HIPCC, *COMMON, "-c", path, "-o", obj]
+        # host code; hipcc still runs a device pass over .cpp files, so name
+        # the one target instead of its default architecture
+        cmd = [HIPCC, *COMMON, f"--offload-arch={ARCH}", "-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    if src.endswith(".hip"):
+        with open(os.path.splitext(obj)[0] + ".usage.txt", "w") as fh:
+            fh.write(r.stderr)
     return obj
 
 

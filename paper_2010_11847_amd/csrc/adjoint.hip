@@ -28,61 +28,87 @@ __global__ __launch_bounds__(kThreads) void k_paint3w(const float* __restrict__ 
   __shared__ RangeTable rt;
   const int TX = g.tx, TY = g.ty, TZ = g.tz, n = g.n;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int tz = tile % g.ntz, ty = (tile / g.ntz) % g.nty, tx = tile / (g.ntz * g.nty);
+  int tx, ty, tz;
+  tile_coords(tile, g, tx, ty, tz);
   const int ox = tx * TX, oy = ty * TY, oz = tz * TZ;
-  const int cells = TX * TY * TZ;
-  for (int c = threadIdx.x; c < cells; c += kThreads) acc[0][c] = acc[1][c] = acc[2][c] = 0.f;
+  for (int c = threadIdx.x; c < tile_cells(g); c += kThreads) acc[0][c] = acc[1][c] = acc[2][c] = 0.f;
   build_ranges(rt, off, tx, ty, tz, g);
   const uint32_t total = rt.pre[27];
-  for (uint32_t idx = threadIdx.x; idx < total; idx += kThreads) {
-    const uint32_t j = range_particle(rt, idx);
-    int ix, iy, iz;
-    float fx, fy, fz;
-    cic_base(pos[3 * (long)j + 0], n, ix, fx);
-    cic_base(pos[3 * (long)j + 1], n, iy, fy);
-    cic_base(pos[3 * (long)j + 2], n, iz, fz);
-    int lx = (ix - ox) & (n - 1), ly = (iy - oy) & (n - 1), lz = (iz - oz) & (n - 1);
-    if (lx > TX) lx -= n;
-    if (ly > TY) ly -= n;
-    if (lz > TZ) lz -= n;
-    const long p = (long)id[j];
-    const float m0 = pbar[3 * p + 0] * k, m1 = pbar[3 * p + 1] * k, m2 = pbar[3 * p + 2] * k;
-    const float wx[2] = {1.f - fx, fx}, wy[2] = {1.f - fy, fy}, wz[2] = {1.f - fz, fz};
+  constexpr int kBatch = 4;   // particles whose loads are in flight together
+  for (uint32_t base = 0; base < total; base += kThreads * kBatch) {
+    // range searches first, then the position/id loads, then the weight
+    // loads; positions past the end are clamped onto the last particle
+    uint32_t jj[kBatch];
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const int cx = lx + a;
-      if (cx < 0 || cx >= TX) continue;
+    for (int u = 0; u < kBatch; ++u) {
+      const uint32_t idx = base + threadIdx.x + u * kThreads;
+      jj[u] = range_particle(rt, idx < total ? idx : total - 1);
+    }
+    float px[kBatch][3], m[kBatch][3];
+    long pid[kBatch];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const int cy = ly + b;
-        if (cy < 0 || cy >= TY) continue;
+    for (int u = 0; u < kBatch; ++u) {
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          const int cz = lz + c;
-          if (cz < 0 || cz >= TZ) continue;
-          const float w = wx[a] * wy[b] * wz[c];
-          const int li = (cx * TY + cy) * TZ + cz;
-          atomicAdd(&acc[0][li], w * m0);
-          atomicAdd(&acc[1][li], w * m1);
-          atomicAdd(&acc[2][li], w * m2);
+      for (int d = 0; d < 3; ++d) px[u][d] = pos[3 * (long)jj[u] + d];
+      pid[u] = (long)id[jj[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) m[u][d] = pbar[3 * pid[u] + d] * k;
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      if (base + threadIdx.x + u * kThreads >= total) continue;
+      int ix, iy, iz;
+      float fx, fy, fz;
+      cic_base(px[u][0], n, ix, fx);
+      cic_base(px[u][1], n, iy, fy);
+      cic_base(px[u][2], n, iz, fz);
+      int lx = (ix - ox) & (n - 1), ly = (iy - oy) & (n - 1), lz = (iz - oz) & (n - 1);
+      if (lx > TX) lx -= n;
+      if (ly > TY) ly -= n;
+      if (lz > TZ) lz -= n;
+      const float wx[2] = {1.f - fx, fx}, wy[2] = {1.f - fy, fy}, wz[2] = {1.f - fz, fz};
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int cx = lx + a;
+        if (cx < 0 || cx >= TX) continue;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const int cy = ly + b;
+          if (cy < 0 || cy >= TY) continue;
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const int cz = lz + c;
+            if (cz < 0 || cz >= TZ) continue;
+            const float w = wx[a] * wy[b] * wz[c];
+            const int li = tile_li(cx, cy, cz, g);
+            atomicAdd(&acc[0][li], w * m[u][0]);
+            atomicAdd(&acc[1][li], w * m[u][1]);
+            atomicAdd(&acc[2][li], w * m[u][2]);
+          }
         }
       }
     }
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < cells; c += kThreads) {
-    const int cz = c % TZ, cy = (c / TZ) % TY, cx = c / (TZ * TY);
-    const long gi = ((long)(ox + cx) * n + (oy + cy)) * n + (oz + cz);
-    o0[gi] = acc[0][c];
-    o1[gi] = acc[1][c];
-    o2[gi] = acc[2][c];
+  for (int c = threadIdx.x; c < store_walk_len(g); c += kThreads) {
+    int cx, cy, cz;
+    store_walk(c, g, cx, cy, cz);
+    if (cx >= TX) continue;
+    const long gi = blk_real(ox + cx, oy + cy, oz + cz, n);
+    const int li = tile_li(cx, cy, cz, g);
+    o0[gi] = acc[0][li];
+    o1[gi] = acc[1][li];
+    o2[gi] = acc[2][li];
   }
 }
 
 // x_bar[id] += sum_corners dW/dx * V(c), one sorted particle per thread:
 //   NCH = 3: V(c) = k pbar[id] . F(c) with F the interleaved force mesh
-//   NCH = 1: V(c) = k M(c) with M a real mesh
-template <int NCH>
+//            (x-blocked cells of 3 floats)
+//   NCH = 1: V(c) = k M(c) with M a real mesh, x-blocked (STD: [x][y][z])
+template <int NCH, bool STD>
 __global__ __launch_bounds__(kThreads) void k_readout_grad(const float* __restrict__ pos,
                                                            const uint32_t* __restrict__ id, long np, int n,
                                                            const float* __restrict__ mesh,
@@ -112,7 +138,7 @@ __global__ __launch_bounds__(kThreads) void k_readout_grad(const float* __restri
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
-        const long cell = ((long)xs[a] * n + ys[b]) * n + zs[c];
+        const long cell = STD ? ((long)xs[a] * n + ys[b]) * n + zs[c] : blk_real(xs[a], ys[b], zs[c], n);
         float val;
         if constexpr (NCH == 3)
           val = c0 * mesh[3 * cell] + c1 * mesh[3 * cell + 1] + c2 * mesh[3 * cell + 2];
@@ -136,20 +162,24 @@ __global__ void k_axpy(float* __restrict__ y, const float* __restrict__ x, float
 
 // LPT: s1_bar_d = cx1 xbar_d + cp1 pbar_d, s2_bar_d = cx2 xbar_d + cp2 pbar_d
 // (particle index = lattice site, AoS [np3][3] -> three lattice fields each)
-__global__ void k_lpt_sbar(const float* __restrict__ xbar, const float* __restrict__ pbar, long n3, float cx1,
-                           float cp1, float cx2, float cp2, float* __restrict__ s10, float* __restrict__ s11,
-                           float* __restrict__ s12, float* __restrict__ s20, float* __restrict__ s21,
-                           float* __restrict__ s22) {
+// (the fields are x-blocked: element e holds lattice site blk_real_xyz(e))
+__global__ void k_lpt_sbar(const float* __restrict__ xbar, const float* __restrict__ pbar, long n3, int ln,
+                           float cx1, float cp1, float cx2, float cp2, float* __restrict__ s10,
+                           float* __restrict__ s11, float* __restrict__ s12, float* __restrict__ s20,
+                           float* __restrict__ s21, float* __restrict__ s22) {
   const long stride = (long)gridDim.x * blockDim.x;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n3; i += stride) {
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n3; e += stride) {
+    int x, y, z;
+    blk_real_xyz(e, ln, x, y, z);
+    const long i = ((((long)x << ln) + y) << ln) + z;
     const float x0 = xbar[3 * i], x1 = xbar[3 * i + 1], x2 = xbar[3 * i + 2];
     const float p0 = pbar[3 * i], p1 = pbar[3 * i + 1], p2 = pbar[3 * i + 2];
-    s10[i] = cx1 * x0 + cp1 * p0;
-    s11[i] = cx1 * x1 + cp1 * p1;
-    s12[i] = cx1 * x2 + cp1 * p2;
-    s20[i] = cx2 * x0 + cp2 * p0;
-    s21[i] = cx2 * x1 + cp2 * p1;
-    s22[i] = cx2 * x2 + cp2 * p2;
+    s10[e] = cx1 * x0 + cp1 * p0;
+    s11[e] = cx1 * x1 + cp1 * p1;
+    s12[e] = cx1 * x2 + cp1 * p2;
+    s20[e] = cx2 * x0 + cp2 * p0;
+    s21[e] = cx2 * x1 + cp2 * p1;
+    s22[e] = cx2 * x2 + cp2 * p2;
   }
 }
 
@@ -186,14 +216,19 @@ void launch_paint3w(const float* pos, const uint32_t* id, const uint32_t* off, c
 void launch_readout_grad3(const float* pos, const uint32_t* id, long np, int n, const float* fi, const float* pbar,
                           float k, float* xbar, hipStream_t s) {
   const int grid = (int)((np + kThreads - 1) / kThreads);
-  hipLaunchKernelGGL(k_readout_grad<3>, dim3(grid), dim3(kThreads), 0, s, pos, id, np, n, fi, pbar, k, xbar);
+  hipLaunchKernelGGL((k_readout_grad<3, false>), dim3(grid), dim3(kThreads), 0, s, pos, id, np, n, fi, pbar, k,
+                     xbar);
 }
 
 void launch_readout_grad1(const float* pos, const uint32_t* id, long np, int n, const float* m0, float k, float* xbar,
-                          hipStream_t s) {
+                          bool std_layout, hipStream_t s) {
   const int grid = (int)((np + kThreads - 1) / kThreads);
-  hipLaunchKernelGGL(k_readout_grad<1>, dim3(grid), dim3(kThreads), 0, s, pos, id, np, n, m0, (const float*)nullptr,
-                     k, xbar);
+  if (std_layout)
+    hipLaunchKernelGGL((k_readout_grad<1, true>), dim3(grid), dim3(kThreads), 0, s, pos, id, np, n, m0,
+                       (const float*)nullptr, k, xbar);
+  else
+    hipLaunchKernelGGL((k_readout_grad<1, false>), dim3(grid), dim3(kThreads), 0, s, pos, id, np, n, m0,
+                       (const float*)nullptr, k, xbar);
 }
 
 void launch_axpy(float* y, const float* x, float a, long n, hipStream_t s) {
@@ -202,8 +237,10 @@ void launch_axpy(float* y, const float* x, float a, long n, hipStream_t s) {
 
 void launch_lpt_sbar(const float* xbar, const float* pbar, long n3, float cx1, float cp1, float cx2, float cp2,
                      float* const* s1, float* const* s2, hipStream_t s) {
-  hipLaunchKernelGGL(k_lpt_sbar, dim3(grid_for(n3)), dim3(kThreads), 0, s, xbar, pbar, n3, cx1, cp1, cx2, cp2, s1[0],
-                     s1[1], s1[2], s2[0], s2[1], s2[2]);
+  int ln = 0;
+  while ((1L << (3 * (ln + 1))) <= n3) ++ln;   // n3 = n^3, n a power of two
+  hipLaunchKernelGGL(k_lpt_sbar, dim3(grid_for(n3)), dim3(kThreads), 0, s, xbar, pbar, n3, ln, cx1, cp1, cx2, cp2,
+                     s1[0], s1[1], s1[2], s2[0], s2[1], s2[2]);
 }
 
 void launch_lpt_phibar(float* const* phi6, const float* d2b, long n3, hipStream_t s) {

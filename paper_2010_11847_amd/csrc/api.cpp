@@ -45,6 +45,12 @@ pmk::TileGeom make_tiles(int n) {
   g.nty = n / g.ty;
   g.ntz = n / g.tz;
   g.ntiles = g.ntx * g.nty * g.ntz;
+  g.lx = __builtin_ctz(g.tx);
+  g.ly = __builtin_ctz(g.ty);
+  g.lz = __builtin_ctz(g.tz);
+  g.lnx = __builtin_ctz(g.ntx);
+  g.lny = __builtin_ctz(g.nty);
+  g.lnz = __builtin_ctz(g.ntz);
   return g;
 }
 
@@ -304,9 +310,11 @@ struct pm_ctx {
     a.id_out = id_s[dst];
     timed(PC_SCATTER, [&] { pmk::launch_scatter(a, stream); });
   }
-  void paint(int cur, long np, float* out) {
+  // overdensity of the sorted particles; std_layout: caller-visible [x][y][z]
+  // mesh instead of the internal x-blocked one
+  void paint(int cur, long np, float* out, bool std_layout = false) {
     const double scale = (double)ng * ng * ng / (double)np;
-    timed(PC_PAINT, [&] { pmk::launch_paint(pos_s[cur], off, tg, out, (float)scale, -1.f, stream); });
+    timed(PC_PAINT, [&] { pmk::launch_paint(pos_s[cur], off, tg, out, (float)scale, -1.f, std_layout, stream); });
   }
   // force meshes from the overdensity in mesh[0].r (overwritten)
   void force_meshes() {
@@ -398,6 +406,13 @@ int pm_create(const pm_config* cfg, void* d_workspace, size_t bytes, void* strea
     c->mesh[i].r = reinterpret_cast<float*>(w + L.mesh[i]);
     c->mesh[i].q = reinterpret_cast<float2*>(w + L.mesh[i] + align_up((size_t)c->ng * c->ng * c->ng * 4));
   }
+  // the interleaved c2r addresses the three meshes by one stride
+  if (c->mesh[2].r - c->mesh[1].r != c->mesh[1].r - c->mesh[0].r ||
+      c->mesh[2].q - c->mesh[1].q != c->mesh[1].q - c->mesh[0].q) {
+    std::fprintf(stderr, "pm_create: mesh fields are not equally spaced\n");
+    delete c;
+    return PM_EINVAL;
+  }
   c->force_i = reinterpret_cast<float*>(w + L.force_i);
   for (int i = 0; i < 2; ++i) {
     c->pos_s[i] = reinterpret_cast<float*>(w + L.pos_s[i]);
@@ -466,7 +481,7 @@ int pm_growth(const pm_ctx* ctx, double a, double* out6) {
 
 int pm_noise(pm_ctx* ctx, uint64_t seed, float* d_noise) {
   if (!ctx || !d_noise) return PM_EINVAL;
-  pmk::launch_noise(seed, ctx->np3, d_noise, ctx->stream);
+  pmk::launch_noise(seed, ctx->npart, d_noise, false, ctx->stream);
   return ctx->check("pm_noise");
 }
 
@@ -477,14 +492,12 @@ int pm_init_lpt(pm_ctx* ctx, uint64_t seed, double a0, const float* d_noise_in, 
   const long n3 = c.np3;
   Field f[10];
   for (int i = 0; i < 10; ++i) f[i] = c.lat(i);
-  if (d_noise_in) {
-    if (hipMemcpyAsync(f[0].r, d_noise_in, n3 * 4, hipMemcpyDeviceToDevice, c.stream) != hipSuccess)
-      return c.check("pm_init_lpt copy");
-  } else {
-    pmk::launch_noise(seed, n3, f[0].r, c.stream);
-  }
-  if (d_noise_out && hipMemcpyAsync(d_noise_out, f[0].r, n3 * 4, hipMemcpyDeviceToDevice, c.stream) != hipSuccess)
-    return c.check("pm_init_lpt copy");
+  // the lattice fields are x-blocked; the caller's noise is [x][y][z]
+  if (d_noise_in)
+    pmk::launch_relayout(d_noise_in, f[0].r, c.npart, true, c.stream);
+  else
+    pmk::launch_noise(seed, c.npart, f[0].r, true, c.stream);
+  if (d_noise_out) pmk::launch_relayout(f[0].r, d_noise_out, c.npart, false, c.stream);
   const int order = c.cfg.lpt_order;
   pmk::fft_r2c_zy(c.tl, &f[0], 1, c.stream);
   pmk::SpecOp op;
@@ -540,7 +553,7 @@ int pm_paint(pm_ctx* ctx, const float* d_pos, int64_t np, float* d_delta) {
   if (!ctx || !d_pos || !d_delta || np < 1 || np > ctx->L.cap) return PM_EINVAL;
   pm_ctx& c = *ctx;
   c.sort(d_pos, nullptr, nullptr, np, 0);
-  c.paint(0, np, d_delta);
+  c.paint(0, np, d_delta, true);
   return c.check("pm_paint");
 }
 
@@ -647,7 +660,7 @@ int pm_run_end(pm_ctx* ctx, float* d_delta_final) {
   if (r.step != r.ns) return c.fail(PM_ESTATE, "pm_run_end before the last step");
   const long np = c.np3;
   const size_t ck = (size_t)np * 3;
-  if (d_delta_final) c.paint(r.cur, np, d_delta_final);
+  if (d_delta_final) c.paint(r.cur, np, d_delta_final, true);
   pmk::ReadoutArgs a = c.readout_args(r.cur, np);
   a.flags = pmk::RO_KICK | pmk::RO_XP_BYID;
   a.kick_a = r.ns ? (float)r.k2[r.ns - 1] : 0.f;
@@ -698,7 +711,8 @@ int pm_run_adjoint(pm_ctx* ctx, const double* h_a, int n_a, const float* d_ckpt,
   // loss on the final overdensity: x_bar += paint^T-gradient of s * delta_bar
   if (d_grad_delta_final) {
     c.sort(ckpt_x(ns), nullptr, nullptr, np, 0);
-    pmk::launch_readout_grad1(c.pos_s[0], c.id_s[0], np, c.ng, d_grad_delta_final, (float)s, xbar, c.stream);
+    pmk::launch_readout_grad1(c.pos_s[0], c.id_s[0], np, c.ng, d_grad_delta_final, (float)s, xbar, true,
+                              c.stream);
   }
   // reverse sweep over the force evaluation points x_ns ... x_0
   for (int j = ns; j >= 0; --j) {
@@ -728,7 +742,7 @@ int pm_run_adjoint(pm_ctx* ctx, const double* h_a, int n_a, const float* d_ckpt,
       op.out_q[0] = c.mesh[0].q;
       pmk::fft_x_fused(c.tm, c.mesh[0], op, c.stream);
       pmk::fft_c2r_yz(c.tm, &c.mesh[0], 1, c.stream);
-      pmk::launch_readout_grad1(c.pos_s[0], c.id_s[0], np, c.ng, c.mesh[0].r, 1.f, xbar, c.stream);
+      pmk::launch_readout_grad1(c.pos_s[0], c.id_s[0], np, c.ng, c.mesh[0].r, 1.f, xbar, false, c.stream);
     }
     if (j > 0) pmk::launch_axpy(pbar, xbar, (float)dr[j - 1], (long)ck, c.stream);
   }
@@ -739,8 +753,7 @@ int pm_run_adjoint(pm_ctx* ctx, const double* h_a, int n_a, const float* d_ckpt,
   const int order = c.cfg.lpt_order;
   Field f[13];
   for (int i = 0; i < 13; ++i) f[i] = c.lat(i);
-  if (hipMemcpyAsync(f[0].r, d_noise, n3 * 4, hipMemcpyDeviceToDevice, c.stream) != hipSuccess)
-    return c.check("pm_run_adjoint copy");
+  pmk::launch_relayout(d_noise, f[0].r, c.npart, true, c.stream);
   double g[6];
   c.cosmo.growth(h_a[0], g);
   const double a0 = h_a[0], b = c.ratio;
@@ -799,8 +812,7 @@ int pm_run_adjoint(pm_ctx* ctx, const double* h_a, int n_a, const float* d_ckpt,
   o1.out_q[0] = f[0].q;
   pmk::fft_x_fused(c.tl, f[0], o1, c.stream);
   pmk::fft_c2r_yz(c.tl, &f[0], 1, c.stream);
-  if (hipMemcpyAsync(d_grad_noise, f[0].r, n3 * 4, hipMemcpyDeviceToDevice, c.stream) != hipSuccess)
-    return c.check("pm_run_adjoint copy");
+  pmk::launch_relayout(f[0].r, d_grad_noise, c.npart, false, c.stream);
   return c.check("pm_run_adjoint");
 }
 
@@ -809,9 +821,7 @@ int pm_power(pm_ctx* ctx, const float* d_delta, int n_bins, int n_max, int decon
   if (!ctx || !d_delta || !h_k || !h_pk || !h_nmodes) return PM_EINVAL;
   pm_ctx& c = *ctx;
   if (n_bins < 1 || n_bins > c.L.n_bins_max) return c.fail(PM_EINVAL, "n_bins must be in [1, n_mesh/2]");
-  const long n3 = (long)c.ng * c.ng * c.ng;
-  if (hipMemcpyAsync(c.mesh[0].r, d_delta, n3 * 4, hipMemcpyDeviceToDevice, c.stream) != hipSuccess)
-    return c.check("pm_power copy");
+  pmk::launch_relayout(d_delta, c.mesh[0].r, c.ng, true, c.stream);
   pmk::fft_r2c_zy(c.tm, &c.mesh[0], 1, c.stream);
   pmk::fft_x_forward(c.tm, &c.mesh[0], 1, c.stream);
   pmk::PowerArgs a;
@@ -830,7 +840,8 @@ int pm_power(pm_ctx* ctx, const float* d_delta, int n_bins, int n_max, int decon
   if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
   if (e != hipSuccess) return c.fail(PM_EHIP, std::string("pm_power: ") + hipGetErrorString(e));
   const double box = c.cfg.box_size;
-  const double norm = box * box * box / ((double)n3 * (double)n3);
+  const double n3 = (double)c.ng * c.ng * c.ng;
+  const double norm = box * box * box / (n3 * n3);
   for (int j = 0; j < n_bins; ++j) {
     const double sw = h[j], sk = h[n_bins + j], sp = h[2 * n_bins + j];
     h_nmodes[j] = sw;
@@ -843,9 +854,7 @@ int pm_power(pm_ctx* ctx, const float* d_delta, int n_bins, int n_max, int decon
 int pm_rfft(pm_ctx* ctx, const float* d_real, float* d_spec) {
   if (!ctx || !d_real || !d_spec) return PM_EINVAL;
   pm_ctx& c = *ctx;
-  const long n3 = (long)c.ng * c.ng * c.ng;
-  if (hipMemcpyAsync(c.mesh[0].r, d_real, n3 * 4, hipMemcpyDeviceToDevice, c.stream) != hipSuccess)
-    return c.check("pm_rfft copy");
+  pmk::launch_relayout(d_real, c.mesh[0].r, c.ng, true, c.stream);
   pmk::fft_r2c_zy(c.tm, &c.mesh[0], 1, c.stream);
   pmk::fft_x_forward(c.tm, &c.mesh[0], 1, c.stream);
   pmk::launch_spec_to_numpy(c.mesh[0].c(), c.mesh[0].q, reinterpret_cast<float2*>(d_spec), c.ng, 1.f, c.stream);
@@ -860,8 +869,7 @@ int pm_irfft(pm_ctx* ctx, const float* d_spec, float* d_real) {
                               (float)(1.0 / (double)n3), c.stream);
   pmk::fft_x_inverse(c.tm, &c.mesh[0], 1, c.stream);
   pmk::fft_c2r_yz(c.tm, &c.mesh[0], 1, c.stream);
-  if (hipMemcpyAsync(d_real, c.mesh[0].r, n3 * 4, hipMemcpyDeviceToDevice, c.stream) != hipSuccess)
-    return c.check("pm_irfft copy");
+  pmk::launch_relayout(c.mesh[0].r, d_real, c.ng, false, c.stream);
   return c.check("pm_irfft");
 }
 

@@ -10,15 +10,19 @@
 //             twiddle exp(-/+ 2 pi i j2 l1 / N), exchange through LDS;
 //   stage B : R2-point DFTs in registers over j2, output k = l1 + R1*l2.
 //
-// Passes along strided axes (y, x) give each workgroup a tile of M adjacent
-// columns so that every global access is an M*8-byte contiguous segment; the
-// contiguous z axis uses the real<->complex packing of N reals as N/2 complex
-// values.  The Nyquist plane kz = N/2 lives in its own array so that all
-// strided tiles are aligned.  No MFMA: the transform is bandwidth bound.
+// Meshes use the x-blocked layout of layout.h.  The z passes take whole
+// (x/8, y) rows, contiguous regions staged through LDS with 16-byte accesses,
+// and use the real<->complex packing of N reals as N/2 complex values.  The
+// strided passes (y, x) give each workgroup a tile of M adjacent columns; in
+// the x pass eight consecutive rows share one run of memory, so a tile reads
+// 512-byte runs from N/8 places instead of 64-byte runs from N places.  The
+// Nyquist plane kz = N/2 lives in its own array so that all strided tiles
+// are aligned.  No MFMA: the transform is bandwidth bound.
 //
 // The x pass can be fused with a spectral multiplication and the inverse x
 // transform of each output (the Green's-function/gradient kernel of the
-// force, the LPT kernels), so the spectrum is read once and never written.
+// force, the LPT kernels), so the spectrum is read once per basis power of
+// the gradient symbol and the product spectra are never written.
 #include "pm_internal.h"
 
 namespace pmk {
@@ -134,12 +138,20 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 
 // ===========================================================================
 // Strided (column-tile) pass: element (batch b, row n, column c) at
-//   data + b*sb + n*sn + c,  n in [0, N), c in [0, ncols)
+//   data + b*sb + row(n) + c*CS,  n in [0, N), c in [0, ncols)
+// with row(n) = n*sn for the y pass (CS = 1) and, for the x pass over the
+// x-blocked layout, row(n) = (n/8)*sn + n%8 (CS = 8): eight rows share one
+// 64-byte run per column.
 // ===========================================================================
 struct ColGeom {
   long sb, sn;
   int ncols, ntc;   // columns, column tiles per batch
 };
+
+template <bool BLK>
+__device__ __forceinline__ long row_off(int n, long sn) {
+  return BLK ? (long)(n >> 3) * sn + (n & 7) : (long)n * sn;
+}
 
 template <int N, int M>
 struct ColLds {
@@ -160,9 +172,10 @@ struct ColPass {
   int nb_main;
 };
 
-template <int N, int M, int DIR>
+template <int N, int M, int DIR, bool BLK>
 __global__ __launch_bounds__(kThreads) void k_fft_cols(ColPass p, const float2* __restrict__ tw) {
   constexpr int R1 = Split<N>::R1, R2 = Split<N>::R2;
+  constexpr int CS = BLK ? 8 : 1;
   constexpr int IA = (M * R2 + kThreads - 1) / kThreads;
   constexpr int IB = (M * R1 + kThreads - 1) / kThreads;
   __shared__ float2 lds[ColLds<N, M>::size];
@@ -173,7 +186,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(ColPass p, const float2* 
   float2* data = is_plane ? p.plane[blockIdx.y] : p.main[blockIdx.y];
   const int b = tile / g.ntc;
   const int c0 = (tile - b * g.ntc) * M;
-  float2* base = data + b * g.sb + c0;
+  float2* base = data + b * g.sb + (long)c0 * CS;
   const int tid = threadIdx.x;
 
   if constexpr (R2 == 1) {
@@ -184,10 +197,10 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(ColPass p, const float2* 
       if (it < M && c0 + m < g.ncols) {
         float2 v[R1];
 #pragma unroll
-        for (int j = 0; j < R1; ++j) v[j] = base[j * g.sn + m];
+        for (int j = 0; j < R1; ++j) v[j] = base[row_off<BLK>(j, g.sn) + m * CS];
         dft<R1, DIR>(v);
 #pragma unroll
-        for (int j = 0; j < R1; ++j) base[j * g.sn + m] = v[j];
+        for (int j = 0; j < R1; ++j) base[row_off<BLK>(j, g.sn) + m * CS] = v[j];
       }
     }
   } else {
@@ -200,7 +213,8 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(ColPass p, const float2* 
         const bool ok = c0 + m < g.ncols;
         float2 v[R1];
 #pragma unroll
-        for (int j1 = 0; j1 < R1; ++j1) v[j1] = ok ? base[(R2 * j1 + j2) * g.sn + m] : make_float2(0.f, 0.f);
+        for (int j1 = 0; j1 < R1; ++j1)
+          v[j1] = ok ? base[row_off<BLK>(R2 * j1 + j2, g.sn) + m * CS] : make_float2(0.f, 0.f);
         dft<R1, DIR>(v);
 #pragma unroll
         for (int l1 = 0; l1 < R1; ++l1) {
@@ -221,7 +235,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(ColPass p, const float2* 
         dft<R2, DIR>(v);
         if (c0 + m < g.ncols) {
 #pragma unroll
-          for (int l2 = 0; l2 < R2; ++l2) base[(l1 + R1 * l2) * g.sn + m] = v[l2];
+          for (int l2 = 0; l2 < R2; ++l2) base[row_off<BLK>(l1 + R1 * l2, g.sn) + m * CS] = v[l2];
         }
       }
     }
@@ -229,32 +243,64 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(ColPass p, const float2* 
 }
 
 // ===========================================================================
-// Contiguous z passes.  Line l of the real mesh holds N floats at r + l*N,
-// i.e. H = N/2 complex values at c + l*H.
+// Contiguous z passes over the x-blocked layout.  A workgroup takes L lines
+// l0 .. l0+L-1 (L a multiple of 8): L/8 whole (x/8, y) rows, one contiguous
+// region of L*N floats = L*N/2 complex values, which holds the block's real
+// input and, after the pass, its spectrum (in place).  Line m of the block
+// (xi = m % 8, row rr = m / 8) has its real z at region float
+// rr*8N + z*8 + xi; the packed complex value j = (x[2j], x[2j+1]) is the
+// float pair (rr*8N + 16j + xi, +8); spectrum kz is region complex
+// rr*4N + kz*8 + xi.  The region is staged through LDS with 16-byte loads
+// and stores, so global traffic is fully coalesced.
 // ===========================================================================
-template <int N>
-struct ZGeom {
+// Geometry of a workgroup of LINES lines of length N (H = N/2 complex).
+template <int N, int LINES>
+struct ZGeomL {
+  static constexpr int NN = N;
   static constexpr int H = N / 2;
   static constexpr int R1 = Split<H>::R1, R2 = Split<H>::R2;
-  static constexpr int L0 = 8192 / H;
-  static constexpr int L = L0 < N * N ? L0 : N * N;       // lines per workgroup
-  static constexpr int P = R2 + 1;                          // padded j2 stride
-  static constexpr int XS = (R2 > 1) ? L * R1 * P : 1;      // exchange size
-  static constexpr int ZS = L * (H + 1);                    // natural-order Z
-  static constexpr int size = XS > ZS ? XS : ZS;
+  static constexpr int L = LINES;
+  static constexpr int LP = L + 1;                          // padded line stride of the exchange
+  static constexpr int ZP = H + 1;                          // padded natural-order Z
+  static constexpr int XS = (R2 > 1) ? H * LP : 1;          // exchange [l1][j2][m]
+  static constexpr int ZS = L * ZP;                         // natural-order Z[m][k]
+  static constexpr int RS = L * H;                          // staged region (complex)
+  static constexpr int size = (XS > ZS ? XS : ZS) > RS ? (XS > ZS ? XS : ZS) : RS;
+  static_assert(L % 8 == 0, "whole (x/8, y) rows per workgroup");
 };
 
-// stage A + B of a length-H complex transform of L contiguous lines whose
-// element (line m, index n) is produced by load(m, n); the result
-// Z[m][k] is written into lds at m*(H+1) + k (natural order).
-template <int N, int L, int DIR, class Load>
+// the in-place passes take 8192 / H lines (64 KB of data) per workgroup
+template <int N>
+using ZGeom = ZGeomL<N, (8192 / (N / 2) < N * N ? 8192 / (N / 2) : N * N)>;
+
+// copy N16 16-byte words from global memory to LDS (whole workgroup): every
+// load of a thread is issued before its first LDS store, so the loads are in
+// flight together instead of one round trip per word
+template <int N16>
+__device__ __forceinline__ void copy16(float4* __restrict__ dst, const float4* __restrict__ src) {
+  if constexpr (N16 % kThreads == 0) {
+    constexpr int K = N16 / kThreads;
+    float4 t[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) t[k] = src[threadIdx.x + k * kThreads];
+#pragma unroll
+    for (int k = 0; k < K; ++k) dst[threadIdx.x + k * kThreads] = t[k];
+  } else {   // small meshes: fewer words than threads
+    for (int i = threadIdx.x; i < N16; i += kThreads) dst[i] = src[i];
+  }
+}
+
+// Length-H complex transform of the L lines of a workgroup.  load(m, n)
+// returns element n of line m (it may read the staged region in lds: every
+// load happens before the first write to lds).  On return Z[m][k] is in lds
+// at m*ZP + k (natural order).  Items map with the line m fastest so that
+// LDS accesses of a wave spread over the banks.
+template <class G, int DIR, class Load>
 __device__ __forceinline__ void zline_transform(float2* lds, const float2* __restrict__ twh, Load load) {
-  using G = ZGeom<N>;
-  constexpr int H = G::H, R1 = G::R1, R2 = G::R2;
-  constexpr int IA = (L * R2 + kThreads - 1) / kThreads;
-  constexpr int IB = (L * R1 + kThreads - 1) / kThreads;
+  constexpr int H = G::H, R1 = G::R1, R2 = G::R2, L = G::L, LP = G::LP, ZP = G::ZP;
   const int tid = threadIdx.x;
   if constexpr (R2 == 1) {
+    constexpr int IA = (L + kThreads - 1) / kThreads;
     float2 v[IA][R1];
 #pragma unroll
     for (int i = 0; i < IA; ++i) {
@@ -262,63 +308,71 @@ __device__ __forceinline__ void zline_transform(float2* lds, const float2* __res
       if (m < L) {
 #pragma unroll
         for (int j = 0; j < R1; ++j) v[i][j] = load(m, j);
-        dft<R1, DIR>(v[i]);
       }
     }
-    __syncthreads();   // callers may reuse lds they read before
+    __syncthreads();
 #pragma unroll
     for (int i = 0; i < IA; ++i) {
       const int m = tid + i * kThreads;
       if (m < L) {
+        dft<R1, DIR>(v[i]);
 #pragma unroll
-        for (int j = 0; j < R1; ++j) lds[m * (H + 1) + j] = v[i][j];
+        for (int j = 0; j < R1; ++j) lds[m * ZP + j] = v[i][j];
       }
     }
   } else {
-    constexpr int P = G::P;
+    constexpr int IA = (L * R2 + kThreads - 1) / kThreads;
+    constexpr int IB = (L * R1 + kThreads - 1) / kThreads;
+    float2 v[IA][R1];
 #pragma unroll
     for (int i = 0; i < IA; ++i) {
       const int it = tid + i * kThreads;
       if (it < L * R2) {
-        const int j2 = it % R2, m = it / R2;
-        float2 v[R1];
+        const int m = it % L, j2 = it / L;
 #pragma unroll
-        for (int j1 = 0; j1 < R1; ++j1) v[j1] = load(m, R2 * j1 + j2);
-        dft<R1, DIR>(v);
-#pragma unroll
-        for (int l1 = 0; l1 < R1; ++l1) {
-          const float2 w = l1 == 0 ? v[l1] : cmul(v[l1], tw_get<DIR>(twh, j2 * l1));
-          lds[(m * R1 + l1) * P + j2] = w;
-        }
-      }
-    }
-    __syncthreads();
-    float2 v[IB][R2];
-#pragma unroll
-    for (int i = 0; i < IB; ++i) {
-      const int it = tid + i * kThreads;
-      if (it < L * R1) {
-        const int l1 = it % R1, m = it / R1;
-#pragma unroll
-        for (int j2 = 0; j2 < R2; ++j2) v[i][j2] = lds[(m * R1 + l1) * P + j2];
-        dft<R2, DIR>(v[i]);
+        for (int j1 = 0; j1 < R1; ++j1) v[i][j1] = load(m, R2 * j1 + j2);
       }
     }
     __syncthreads();
 #pragma unroll
+    for (int i = 0; i < IA; ++i) {
+      const int it = tid + i * kThreads;
+      if (it < L * R2) {
+        const int m = it % L, j2 = it / L;
+        dft<R1, DIR>(v[i]);
+#pragma unroll
+        for (int l1 = 0; l1 < R1; ++l1)
+          lds[(l1 * R2 + j2) * LP + m] = l1 == 0 ? v[i][l1] : cmul(v[i][l1], tw_get<DIR>(twh, j2 * l1));
+      }
+    }
+    __syncthreads();
+    float2 w[IB][R2];
+#pragma unroll
     for (int i = 0; i < IB; ++i) {
       const int it = tid + i * kThreads;
       if (it < L * R1) {
-        const int l1 = it % R1, m = it / R1;
+        const int m = it % L, l1 = it / L;
 #pragma unroll
-        for (int l2 = 0; l2 < R2; ++l2) lds[m * (H + 1) + l1 + R1 * l2] = v[i][l2];
+        for (int j2 = 0; j2 < R2; ++j2) w[i][j2] = lds[(l1 * R2 + j2) * LP + m];
+        dft<R2, DIR>(w[i]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < IB; ++i) {
+      const int it = tid + i * kThreads;
+      if (it < L * R1) {
+        const int m = it % L, l1 = it / L;
+#pragma unroll
+        for (int l2 = 0; l2 < R2; ++l2) lds[m * ZP + l1 + R1 * l2] = w[i][l2];
       }
     }
   }
   __syncthreads();
 }
 
-// Real-to-complex along z: N reals -> X[0..N/2-1] in place + X[N/2] to q.
+// Real-to-complex along z, in place: the N reals of each line become
+// X[0..N/2-1] (region) and X[N/2] (Nyquist plane, q[l]).
 template <int N>
 __global__ __launch_bounds__(kThreads) void k_r2c_z(float* __restrict__ r0, float* __restrict__ r1,
                                                      float* __restrict__ r2, float2* __restrict__ q0,
@@ -326,35 +380,41 @@ __global__ __launch_bounds__(kThreads) void k_r2c_z(float* __restrict__ r0, floa
                                                      const float2* __restrict__ twh,
                                                      const float2* __restrict__ twn) {
   using G = ZGeom<N>;
-  constexpr int H = G::H, L = G::L;
+  constexpr int H = G::H, L = G::L, ZP = G::ZP;
   __shared__ float2 lds[G::size];
   float* r = blockIdx.y == 0 ? r0 : (blockIdx.y == 1 ? r1 : r2);
   float2* q = blockIdx.y == 0 ? q0 : (blockIdx.y == 1 ? q1 : q2);
-  const long line0 = (long)xcd_tile(blockIdx.x, gridDim.x) * L;
-  float2* c = reinterpret_cast<float2*>(r) + line0 * H;
-  zline_transform<N, L, -1>(lds, twh, [&](int m, int n) { return c[(long)m * H + n]; });
-  // post-processing: X[k] = E + w^k O, X[H-k] = conj(E - w^k O)
+  const long l0 = (long)xcd_tile(blockIdx.x, gridDim.x) * L;
+  float2* reg = reinterpret_cast<float2*>(r) + l0 * H;   // region: L*H complex = L*N floats
+  copy16<L * H / 2>(reinterpret_cast<float4*>(lds), reinterpret_cast<const float4*>(reg));
+  __syncthreads();
+  const float* lf = reinterpret_cast<const float*>(lds);
+  zline_transform<G, -1>(lds, twh, [&](int m, int n) {
+    const int o = (m >> 3) * 8 * N + 16 * n + (m & 7);
+    return make_float2(lf[o], lf[o + 8]);
+  });
+  // post-processing: X[k] = E + w^k O, X[H-k] = conj(E - w^k O); line m fastest
   constexpr int NK = H / 2 + 1;
   for (int it = threadIdx.x; it < L * NK; it += kThreads) {
-    const int k = it % NK, m = it / NK;
-    const float2 zk = lds[m * (H + 1) + k];
-    const float2 zm = cconj(lds[m * (H + 1) + ((H - k) & (H - 1))]);
+    const int m = it % L, k = it / L;
+    const float2 zk = lds[m * ZP + k];
+    const float2 zm = cconj(lds[m * ZP + ((H - k) & (H - 1))]);
     const float2 e = cscale(cadd(zk, zm), 0.5f);
     const float2 dif = csub(zk, zm);
     const float2 o = make_float2(0.5f * dif.y, -0.5f * dif.x);   // (zk - zm) / (2i)
     const float2 t = cmul(o, twn[k]);
-    float2* out = c + (long)m * H;
+    float2* out = reg + (m >> 3) * 4 * N + (m & 7);
     if (k == 0) {
       out[0] = make_float2(e.x + t.x, 0.f);
-      q[line0 + m] = make_float2(e.x - t.x, 0.f);
+      q[l0 + m] = make_float2(e.x - t.x, 0.f);
     } else {
-      out[k] = cadd(e, t);
-      if (k != H - k) out[H - k] = cconj(csub(e, t));
+      out[8 * k] = cadd(e, t);
+      if (k != H - k) out[8 * (H - k)] = cconj(csub(e, t));
     }
   }
 }
 
-// Complex-to-real along z (unnormalised): X[0..N/2] -> N reals in place.
+// Complex-to-real along z (unnormalised), in place: X[0..N/2] -> N reals.
 // The imaginary parts of X[0] and X[N/2] are discarded.
 template <int N>
 __global__ __launch_bounds__(kThreads) void k_c2r_z(float* __restrict__ r0, float* __restrict__ r1,
@@ -363,92 +423,90 @@ __global__ __launch_bounds__(kThreads) void k_c2r_z(float* __restrict__ r0, floa
                                                      const float2* __restrict__ twh,
                                                      const float2* __restrict__ twn) {
   using G = ZGeom<N>;
-  constexpr int H = G::H, L = G::L;
+  constexpr int H = G::H, L = G::L, ZP = G::ZP;
   __shared__ float2 lds[G::size];
   float* r = blockIdx.y == 0 ? r0 : (blockIdx.y == 1 ? r1 : r2);
   const float2* q = blockIdx.y == 0 ? q0 : (blockIdx.y == 1 ? q1 : q2);
-  const long line0 = (long)xcd_tile(blockIdx.x, gridDim.x) * L;
-  float2* c = reinterpret_cast<float2*>(r) + line0 * H;
-  auto load = [&](int m, int k) {
-    const float2* line = c + (long)m * H;
+  const long l0 = (long)xcd_tile(blockIdx.x, gridDim.x) * L;
+  float2* reg = reinterpret_cast<float2*>(r) + l0 * H;
+  copy16<L * H / 2>(reinterpret_cast<float4*>(lds), reinterpret_cast<const float4*>(reg));
+  __syncthreads();
+  zline_transform<G, +1>(lds, twh, [&](int m, int k) {
+    const float2* line = lds + (m >> 3) * 4 * N + (m & 7);
     float2 a, b;
     if (k == 0) {
       a = make_float2(line[0].x, 0.f);
-      b = make_float2(q[line0 + m].x, 0.f);
+      b = make_float2(q[l0 + m].x, 0.f);
     } else {
-      a = line[k];
-      b = cconj(line[H - k]);
+      a = line[8 * k];
+      b = cconj(line[8 * (H - k)]);
     }
     const float2 e = cadd(a, b);
     const float2 o = cmulc(csub(a, b), twn[k]);     // (a - b) exp(+2 pi i k / N)
     return make_float2(e.x - o.y, e.y + o.x);       // e + i o
-  };
-  zline_transform<N, L, +1>(lds, twh, load);
-  for (int it = threadIdx.x; it < L * H; it += kThreads) {
-    const int j = it % H, m = it / H;
-    c[(long)m * H + j] = lds[m * (H + 1) + j];      // (x[2j], x[2j+1])
+  });
+  // region float e = rr*8N + z*8 + xi holds component z&1 of Z[rr*8 + xi][z/2]
+  const float* lf = reinterpret_cast<const float*>(lds);
+  float4* o4 = reinterpret_cast<float4*>(reg);
+  for (int i = threadIdx.x; i < L * N / 4; i += kThreads) {
+    const int e = 4 * i;
+    const int xi = e & 7, z = (e >> 3) & (N - 1), rr = e / (8 * N);
+    const int zo = 2 * (z >> 1) + (z & 1);
+    const float* zl = lf + 2 * ((rr * 8 + xi) * ZP) + zo;
+    o4[i] = make_float4(zl[0], zl[2 * ZP], zl[4 * ZP], zl[6 * ZP]);
   }
 }
 
-// Three fields in one workgroup (L3 lines each), written as one interleaved
-// real mesh out[(line*N + z)*3 + field]: the layout the particle readout
-// gathers from (one 12-byte load per CIC corner).
+// Complex-to-real along z of three fields (the force components) written as
+// one interleaved real mesh in the x-blocked order
+//   out[x/8][y][z][x%8][3],  element ((l/8 * N + z) * 8 + x%8) * 3 + field,
+// the layout the particle readout gathers from: the 3 components of a cell
+// are one 12-byte load, and x, x+1 of one block are adjacent.  A workgroup
+// transforms one field of one (x/8, y) row (8 lines) through LDS and stores
+// its component; the three workgroups of a row have consecutive tile indices,
+// which the XCD-aware mapping places on one XCD, so their stores into each
+// 192-byte run of the output merge in that XCD's L2.
 template <int N>
-struct ZGeom3 {
-  static constexpr int H = N / 2;
-  static constexpr int R1 = Split<H>::R1, R2 = Split<H>::R2;
-  static constexpr int L3 = ZGeom<N>::L / 4 > 0 ? ZGeom<N>::L / 4 : 1;
-  static constexpr int L = 3 * L3;
-  static constexpr int XS = (R2 > 1) ? L * R1 * (R2 + 1) : 1;
-  static constexpr int ZS = L * (H + 1);
-  static constexpr int size = XS > ZS ? XS : ZS;
-};
+using Z3Geom = ZGeomL<N, 8>;
 
 template <int N>
-__global__ __launch_bounds__(kThreads) void k_c2r_z3i(const float* __restrict__ r0, const float* __restrict__ r1,
-                                                       const float* __restrict__ r2, const float2* __restrict__ q0,
-                                                       const float2* __restrict__ q1, const float2* __restrict__ q2,
-                                                       float* __restrict__ out, const float2* __restrict__ twh,
-                                                       const float2* __restrict__ twn) {
-  using G = ZGeom3<N>;
-  constexpr int H = G::H, L3 = G::L3, L = G::L;
+__global__ __launch_bounds__(kThreads) void k_c2r_z3(const float* __restrict__ r0, long fstride,
+                                                      const float2* __restrict__ q0, long qstride,
+                                                      float* __restrict__ out, const float2* __restrict__ twh,
+                                                      const float2* __restrict__ twn) {
+  using G = Z3Geom<N>;
+  constexpr int H = G::H, L = G::L, ZP = G::ZP;
   __shared__ float2 lds[G::size];
-  const long line0 = (long)xcd_tile(blockIdx.x, gridDim.x) * L3;
-  auto load = [&](int m, int k) {
-    const int f = m / L3;
-    const long line = line0 + (m - f * L3);
-    const float* r = f == 0 ? r0 : (f == 1 ? r1 : r2);
-    const float2* q = f == 0 ? q0 : (f == 1 ? q1 : q2);
-    const float2* ln = reinterpret_cast<const float2*>(r) + line * H;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int row = tile / 3, f = tile - 3 * row;
+  const long l0 = (long)row * L;
+  // field f by stride arithmetic (a choice among pointer arguments can
+  // compile to a lookup table in private memory)
+  const float2* reg = reinterpret_cast<const float2*>(r0 + f * fstride) + l0 * H;
+  const float2* q = q0 + f * qstride;
+  copy16<L * H / 2>(reinterpret_cast<float4*>(lds), reinterpret_cast<const float4*>(reg));
+  __syncthreads();
+  zline_transform<G, +1>(lds, twh, [&](int m, int k) {
+    const float2* line = lds + m;   // one row: line m is xi = m
     float2 a, b;
     if (k == 0) {
-      a = make_float2(ln[0].x, 0.f);
-      b = make_float2(q[line].x, 0.f);
+      a = make_float2(line[0].x, 0.f);
+      b = make_float2(q[l0 + m].x, 0.f);
     } else {
-      a = ln[k];
-      b = cconj(ln[H - k]);
+      a = line[8 * k];
+      b = cconj(line[8 * (H - k)]);
     }
     const float2 e = cadd(a, b);
-    const float2 o = cmulc(csub(a, b), twn[k]);     // (a - b) exp(+2 pi i k / N)
-    return make_float2(e.x - o.y, e.y + o.x);       // e + i o
-  };
-  zline_transform<N, L, +1>(lds, twh, load);
-  // the L3 output lines are contiguous: 3*N*L3 floats from out + line0*3N;
-  // each thread writes whole float4s of that stream (element e: cell e/3,
-  // field e%3; cell 2j / 2j+1 is the real / imaginary part of z_j)
-  const float* ldsf = reinterpret_cast<const float*>(lds);
-  float4* o4 = reinterpret_cast<float4*>(out + line0 * 3 * N);
-  constexpr int NQ = 3 * N * L3 / 4;
-  for (int q = threadIdx.x; q < NQ; q += kThreads) {
-    float v[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = 4 * q + u;
-      const int cell = e / 3, f = e - 3 * (e / 3);
-      const int m = cell / N, z = cell - m * N;
-      v[u] = ldsf[2 * ((f * L3 + m) * (H + 1) + (z >> 1)) + (z & 1)];
-    }
-    o4[q] = make_float4(v[0], v[1], v[2], v[3]);
+    const float2 o2 = cmulc(csub(a, b), twn[k]);    // (a - b) exp(+2 pi i k / N)
+    return make_float2(e.x - o2.y, e.y + o2.x);     // e + i o
+  });
+  // Z[m][j] = (x[2j], x[2j+1]) of line m: cells z = 2j, 2j+1 of xi = m
+  float* o = out + (long)row * N * 24 + f;
+  for (int idx = threadIdx.x; idx < L * H; idx += kThreads) {
+    const int m = idx & 7, j = idx >> 3;
+    const float2 v = lds[m * ZP + j];
+    o[((2 * j) * 8 + m) * 3] = v.x;
+    o[((2 * j + 1) * 8 + m) * 3] = v.y;
   }
 }
 
@@ -571,7 +629,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_fused(FusedArgs a) {
   const ColGeom& g = mode ? a.gp : a.gm;
   const int b = tile / g.ntc;
   const int c0 = (tile - b * g.ntc) * M;
-  const long off = b * g.sb + c0;
+  const long off = b * g.sb + (long)c0 * 8;
   const int tid = threadIdx.x;
   const SpecOp& op = a.op;
   const FftTables& t = a.t;
@@ -622,7 +680,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_fused(FusedArgs a) {
               const float2 cf = coef_of(tm, dy, dz);
               const float2* src = src_of(in);
 #pragma unroll
-              for (int j = 0; j < R1; ++j) X[j] = cadd(X[j], cmul(src[j * g.sn + m], cf));
+              for (int j = 0; j < R1; ++j) X[j] = cadd(X[j], cmul(src[row_off<true>(j, g.sn) + m * 8], cf));
             }
             dft<R1, -1>(X);
 #pragma unroll
@@ -633,11 +691,11 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_fused(FusedArgs a) {
           dft<R1, 1>(Y);
           float2* dst = dst_of(0);
 #pragma unroll
-          for (int j = 0; j < R1; ++j) dst[j * g.sn + m] = Y[j];
+          for (int j = 0; j < R1; ++j) dst[row_off<true>(j, g.sn) + m * 8] = Y[j];
         } else {
           const float2* src = src_of(0);
 #pragma unroll
-          for (int j = 0; j < R1; ++j) X[j] = src[j * g.sn + m];
+          for (int j = 0; j < R1; ++j) X[j] = src[row_off<true>(j, g.sn) + m * 8];
           dft<R1, -1>(X);
 #pragma unroll
           for (int kx = 0; kx < R1; ++kx) X[kx] = cscale(X[kx], common_factor<N>(op, t, kx, ky, kz));
@@ -652,7 +710,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_fused(FusedArgs a) {
               const float2 cf = coef_of(tm, dy, dz);
               float2* dst = dst_of(o);
 #pragma unroll
-              for (int j = 0; j < R1; ++j) dst[j * g.sn + m] = cmul(Y[j], cf);
+              for (int j = 0; j < R1; ++j) dst[row_off<true>(j, g.sn) + m * 8] = cmul(Y[j], cf);
             }
           }
         }
@@ -684,12 +742,12 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_fused(FusedArgs a) {
               const float2 cf = coef_of(tm, dy, dz);
               const float2* src = src_of(in);
 #pragma unroll
-              for (int j1 = 0; j1 < R1; ++j1) v[j1] = cadd(v[j1], cmul(src[(R2 * j1 + j2) * g.sn + m], cf));
+              for (int j1 = 0; j1 < R1; ++j1) v[j1] = cadd(v[j1], cmul(src[row_off<true>(R2 * j1 + j2, g.sn) + m * 8], cf));
             }
           } else {
             const float2* src = src_of(0);
 #pragma unroll
-            for (int j1 = 0; j1 < R1; ++j1) v[j1] = ok ? src[(R2 * j1 + j2) * g.sn + m] : make_float2(0.f, 0.f);
+            for (int j1 = 0; j1 < R1; ++j1) v[j1] = ok ? src[row_off<true>(R2 * j1 + j2, g.sn) + m * 8] : make_float2(0.f, 0.f);
           }
           dft<R1, -1>(v);
 #pragma unroll
@@ -738,7 +796,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_fused(FusedArgs a) {
             if (FANIN) {
               float2* dst = dst_of(0);
 #pragma unroll
-              for (int l2p = 0; l2p < R1; ++l2p) dst[(lp + R2 * l2p) * g.sn + m] = v[l2p];
+              for (int l2p = 0; l2p < R1; ++l2p) dst[row_off<true>(lp + R2 * l2p, g.sn) + m * 8] = v[l2p];
             } else {
               float dy, dz;
               col_d(m, dy, dz);
@@ -749,7 +807,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_fused(FusedArgs a) {
                 const float2 cf = coef_of(tm, dy, dz);
                 float2* dst = dst_of(o);
 #pragma unroll
-                for (int l2p = 0; l2p < R1; ++l2p) dst[(lp + R2 * l2p) * g.sn + m] = cmul(v[l2p], cf);
+                for (int l2p = 0; l2p < R1; ++l2p) dst[row_off<true>(lp + R2 * l2p, g.sn) + m * 8] = cmul(v[l2p], cf);
               }
             }
           }
@@ -779,12 +837,12 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_fused(FusedArgs a) {
           for (int l2 = 0; l2 < R2; ++l2) {
             const int kx = l1 + R1 * l2;
             float2 v = cscale(X[i][l2], common_factor<N>(op, t, kx, ky, kz) * powp(t.dxy[kx], p));
-            if (!a.first && c0 + m < g.ncols) v = cadd(v, park[kx * g.sn + m]);
+            if (!a.first && c0 + m < g.ncols) v = cadd(v, park[row_off<true>(kx, g.sn) + m * 8]);
             Y[i][l2] = v;
           }
           if (!a.last && c0 + m < g.ncols) {
 #pragma unroll
-            for (int l2 = 0; l2 < R2; ++l2) park[(l1 + R1 * l2) * g.sn + m] = Y[i][l2];
+            for (int l2 = 0; l2 < R2; ++l2) park[row_off<true>(l1 + R1 * l2, g.sn) + m * 8] = Y[i][l2];
           }
         }
       }
@@ -821,7 +879,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_fused(FusedArgs a) {
 // ---------------------------------------------------------------------------
 inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
-template <int N, int DIR>
+template <int N, int DIR, bool BLK>
 void launch_cols(float2* const* dm, float2* const* dq, int nf, ColGeom gm, int nbm, ColGeom gp, int nbp,
                  const float2* tw, hipStream_t s) {
   constexpr int M = Cols<N>::M;
@@ -836,7 +894,7 @@ void launch_cols(float2* const* dm, float2* const* dq, int nf, ColGeom gm, int n
   p.gp = gp;
   p.nb_main = nbm * gm.ntc;
   dim3 grid(p.nb_main + nbp * gp.ntc, nf);
-  hipLaunchKernelGGL((k_fft_cols<N, M, DIR>), grid, dim3(kThreads), 0, s, p, tw);
+  hipLaunchKernelGGL((k_fft_cols<N, M, DIR, BLK>), grid, dim3(kThreads), 0, s, p, tw);
 }
 
 // y pass over the main arrays and the Nyquist planes of nf fields
@@ -845,10 +903,10 @@ void ypass(const FftTables& t, Field* f, int nf, hipStream_t s) {
   float2* dm[3];
   float2* dq[3];
   for (int i = 0; i < nf; ++i) { dm[i] = f[i].c(); dq[i] = f[i].q; }
-  // main: element (b = x, n = y, c = z): sb = N*N/2, sn = N/2, ncols = N/2
-  // Nyquist plane q[x][y]: lines along y are contiguous: (b = x, n = y, c = 0)
-  launch_cols<N, DIR>(dm, dq, nf, ColGeom{(long)N * (N / 2), N / 2, N / 2, 0}, N, ColGeom{(long)N, 1, 1, 0}, N,
-                      t.tw_n, s);
+  // main c[xb][y][kz][xi]: (b = xb, n = y, c = kz*8 + xi): sb = 4N^2, sn = 4N, ncols = 4N
+  // Nyquist plane q[xb][y][xi]: (b = xb, n = y, c = xi): sb = 8N, sn = 8, ncols = 8
+  launch_cols<N, DIR, false>(dm, dq, nf, ColGeom{4L * N * N, 4L * N, 4 * N, 0}, N / 8,
+                             ColGeom{8L * N, 8, 8, 0}, N / 8, t.tw_n, s);
 }
 
 template <int N, int DIR>
@@ -856,10 +914,10 @@ void xpass(const FftTables& t, Field* f, int nf, hipStream_t s) {
   float2* dm[3];
   float2* dq[3];
   for (int i = 0; i < nf; ++i) { dm[i] = f[i].c(); dq[i] = f[i].q; }
-  // main: element (b = y, n = x, c = z): sb = N/2, sn = N*N/2
-  // Nyquist plane: (b = 0, n = x, c = y): sn = N
-  launch_cols<N, DIR>(dm, dq, nf, ColGeom{(long)N / 2, (long)N * (N / 2), N / 2, 0}, N, ColGeom{0, (long)N, N, 0},
-                      1, t.tw_n, s);
+  // main c[xb][y][kz][xi]: (b = y, n = x, c = kz): sb = 4N, row(x) = xb*4N^2 + xi, column stride 8
+  // Nyquist plane q[xb][y][xi]: (b = 0, n = x, c = y): row(x) = xb*8N + xi, column stride 8
+  launch_cols<N, DIR, true>(dm, dq, nf, ColGeom{4L * N, 4L * N * N, N / 2, 0}, N, ColGeom{0, 8L * N, N, 0}, 1,
+                            t.tw_n, s);
 }
 
 template <int N>
@@ -872,20 +930,19 @@ void zr2c(const FftTables& t, Field* f, int nf, hipStream_t s) {
 }
 
 template <int N>
+void zc2r3(const FftTables& t, const Field* f, float* out, hipStream_t s) {
+  dim3 grid(3 * (N * N) / Z3Geom<N>::L);
+  hipLaunchKernelGGL((k_c2r_z3<N>), grid, dim3(kThreads), 0, s, f[0].r, (long)(f[1].r - f[0].r), f[0].q,
+                     (long)(f[1].q - f[0].q), out, t.tw_h, t.tw_n);
+}
+
+template <int N>
 void zc2r(const FftTables& t, Field* f, int nf, hipStream_t s) {
   using G = ZGeom<N>;
   dim3 grid((N * N) / G::L, nf);
   hipLaunchKernelGGL((k_c2r_z<N>), grid, dim3(kThreads), 0, s, f[0].r, nf > 1 ? f[1].r : f[0].r,
                      nf > 2 ? f[2].r : f[0].r, f[0].q, nf > 1 ? f[1].q : f[0].q, nf > 2 ? f[2].q : f[0].q,
                      t.tw_h, t.tw_n);
-}
-
-template <int N>
-void zc2r3i(const FftTables& t, const Field* f, float* out, hipStream_t s) {
-  using G = ZGeom3<N>;
-  dim3 grid((N * N) / G::L3);
-  hipLaunchKernelGGL((k_c2r_z3i<N>), grid, dim3(kThreads), 0, s, f[0].r, f[1].r, f[2].r, f[0].q, f[1].q, f[2].q,
-                     out, t.tw_h, t.tw_n);
 }
 
 template <int N>
@@ -896,8 +953,8 @@ void xfused(const FftTables& t, const Field& in, const SpecOp& op, hipStream_t s
   a.t = t;
   a.in_main = in.c();
   a.in_nyq = in.q;
-  a.gm = ColGeom{(long)N / 2, (long)N * (N / 2), N / 2, cdiv(N / 2, M)};
-  a.gp = ColGeom{0, (long)N, N, cdiv(N, M)};
+  a.gm = ColGeom{4L * N, 4L * N * N, N / 2, cdiv(N / 2, M)};
+  a.gp = ColGeom{0, 8L * N, N, cdiv(N, M)};
   a.nb_main = N * a.gm.ntc;
   const dim3 grid(a.nb_main + a.gp.ntc);
   a.pbasis = 0;
@@ -1007,7 +1064,7 @@ void fft_x_fused(const FftTables& t, const Field& in, const SpecOp& op, hipStrea
 }
 
 void fft_z_c2r_interleaved3(const FftTables& t, const Field* f, float* out, hipStream_t s) {
-#define CALL(N) zc2r3i<N>(t, f, out, s)
+#define CALL(N) zc2r3<N>(t, f, out, s)
   PM_FFT_SWITCH(t.n, CALL)
 #undef CALL
 }

@@ -5,15 +5,21 @@
 
 #include <cstdint>
 
+#include "layout.h"
+
 namespace pmk {
 
 // Tiles of tx * ty * tz cells (tz is the contiguous axis): ntx * nty * ntz
 // tiles, tile index (ix * nty + iy) * ntz + iz.
+// Every size here is a power of two; the log2 fields let kernels split
+// indices with shifts and masks instead of integer division.
 struct TileGeom {
   int n = 0;                   // mesh cells per side
   int tx = 0, ty = 0, tz = 0;  // tile size in cells
   int ntx = 0, nty = 0, ntz = 0;
   int ntiles = 0;
+  int lx = 0, ly = 0, lz = 0;        // log2 of tx, ty, tz
+  int lnx = 0, lny = 0, lnz = 0;     // log2 of ntx, nty, ntz
 };
 
 struct LptParticleArgs {
@@ -59,7 +65,7 @@ struct ReadoutArgs {
   float* pos = nullptr;            // sorted
   float* mom = nullptr;            // sorted, may be null
   const uint32_t* id = nullptr;    // sorted ids
-  const float* fi = nullptr;       // force mesh, interleaved [n^3][3]
+  const float* fi = nullptr;       // force mesh, interleaved x-blocked [n/8][n][n][8][3]
   float kick_a = 0.f, kick_b = 0.f, drift = 0.f;
   int flags = 0;
   float* force_out = nullptr;
@@ -84,7 +90,10 @@ struct PowerArgs {
   double* partial = nullptr;
 };
 
-void launch_noise(uint64_t seed, long n, float* out, hipStream_t s);
+// white noise of n_side^3 sites; blocked: x-blocked layout, else [x][y][z]
+void launch_noise(uint64_t seed, int n_side, float* out, bool blocked, hipStream_t s);
+// plain [x][y][z] <-> x-blocked copy of a real n_side^3 mesh (out != in)
+void launch_relayout(const float* in, float* out, int n_side, bool to_blocked, hipStream_t s);
 void launch_lpt_delta2(float* const* phi6, long n, float* out, hipStream_t s);
 void launch_lpt_particles(const LptParticleArgs& a, hipStream_t s);
 void launch_fill_u32(uint32_t* p, long n, uint32_t v, hipStream_t s);
@@ -93,8 +102,9 @@ void launch_keys(const float* pos, long np, const TileGeom& g, uint32_t* key, ui
 long scan_scratch_words(long n);
 void launch_scan(const uint32_t* count, long n, uint32_t* off, uint32_t* bsum, hipStream_t s);
 void launch_scatter(const ScatterArgs& a, hipStream_t s);
+// std_layout: write [x][y][z] instead of the x-blocked layout
 void launch_paint(const float* pos_sorted, const uint32_t* off, const TileGeom& g, float* out, float scale,
-                  float offset, hipStream_t s);
+                  float offset, bool std_layout, hipStream_t s);
 void launch_readout(const ReadoutArgs& a, hipStream_t s);
 void launch_kick_drift(float* pos, float* mom, const float* f, long np, float kick, float drift, float nmesh,
                        hipStream_t s);
@@ -106,8 +116,9 @@ void launch_paint3w(const float* pos, const uint32_t* id, const uint32_t* off, c
                     float k, float* o0, float* o1, float* o2, hipStream_t s);
 void launch_readout_grad3(const float* pos, const uint32_t* id, long np, int n, const float* fi, const float* pbar,
                           float k, float* xbar, hipStream_t s);
+// m0: real mesh, x-blocked (std_layout: plain [x][y][z])
 void launch_readout_grad1(const float* pos, const uint32_t* id, long np, int n, const float* m0, float k, float* xbar,
-                          hipStream_t s);
+                          bool std_layout, hipStream_t s);
 void launch_axpy(float* y, const float* x, float a, long n, hipStream_t s);
 void launch_lpt_sbar(const float* xbar, const float* pbar, long n3, float cx1, float cp1, float cx2, float cp2,
                      float* const* s1, float* const* s2, hipStream_t s);

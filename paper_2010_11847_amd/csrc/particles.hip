@@ -11,8 +11,9 @@
 //    and those particles of the 7 lower neighbour tiles whose class says they
 //    reach into t, keeping only the corners inside t.  Every mesh cell is
 //    written once, by its owner, with no global float atomics.
-//  - Readout: the workgroup of tile t stages the (T+1)^3 force values its
-//    particles touch in LDS and interpolates from there.
+//  - Readout: one sorted particle per thread gathers its 8 corners from the
+//    interleaved force mesh; sorted neighbours share cache lines.
+// Meshes use the x-blocked layout of layout.h.
 #include "particles.h"
 #include "pm_device.h"
 
@@ -23,10 +24,18 @@ constexpr int kThreads = 256;
 
 // ---- white noise ------------------------------------------------------------
 // SplitMix64 output of the counter seed*2^40 + i, Box-Muller (cosine branch).
-__global__ void k_noise(uint64_t seed, long n, float* __restrict__ out) {
+// The counter is the site index (x*n + y)*n + z; blocked != 0 writes the
+// x-blocked layout (element e holds site blk_real_xyz(e)).
+__global__ void k_noise(uint64_t seed, long n3, int ln, int blocked, float* __restrict__ out) {
   const long stride = (long)gridDim.x * blockDim.x;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    uint64_t z = seed * (1ull << 40) + (uint64_t)i + 0x9E3779B97F4A7C15ull;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n3; i += stride) {
+    long site = i;
+    if (blocked) {
+      int x, y, zc;
+      blk_real_xyz(i, ln, x, y, zc);
+      site = ((((long)x << ln) + y) << ln) + zc;
+    }
+    uint64_t z = seed * (1ull << 40) + (uint64_t)site + 0x9E3779B97F4A7C15ull;
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     z ^= z >> 31;
@@ -55,10 +64,11 @@ __global__ void k_lpt_particles(LptParticleArgs a) {
   const long stride = (long)gridDim.x * blockDim.x;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n3; i += stride) {
     const int q[3] = {(int)(i / ((long)a.np * a.np)), (int)((i / a.np) % a.np), (int)(i % a.np)};
+    const long e = blk_real(q[0], q[1], q[2], a.np);   // lattice fields are x-blocked
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const float s1 = a.s1[d][i];
-      const float s2 = a.has_s2 ? a.s2[d][i] : 0.f;
+      const float s1 = a.s1[d][e];
+      const float s2 = a.has_s2 ? a.s2[d][e] : 0.f;
       const float dx = a.cx1 * s1 + a.cx2 * s2;
       const float x = (float)(a.ratio * q[d]) + a.shift + dx;
       a.pos[3 * i + d] = wrap_pos(x, a.nmesh);
@@ -175,30 +185,39 @@ __global__ void k_scatter(ScatterArgs a) {
 }
 
 // ---- paint ---------------------------------------------------------------------
+// LDS accumulator order of a tile: x-blocked like the mesh,
+// li = ((cx/8 * TY + cy) * TZ + cz) * 8 + cx%8, so that the store walks
+// contiguous runs of the x-blocked mesh.  STD writes the plain [x][y][z]
+// layout instead (caller-visible meshes).
+template <bool STD>
 __global__ __launch_bounds__(kThreads) void k_paint(const float* __restrict__ pos, const uint32_t* __restrict__ off,
                                                     TileGeom g, float* __restrict__ out, float scale, float offset) {
   __shared__ float acc[kTileCells];
   __shared__ RangeTable rt;
   const int TX = g.tx, TY = g.ty, TZ = g.tz, n = g.n;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int tz = tile % g.ntz, ty = (tile / g.ntz) % g.nty, tx = tile / (g.ntz * g.nty);
+  int tx, ty, tz;
+  tile_coords(tile, g, tx, ty, tz);
   const int ox = tx * TX, oy = ty * TY, oz = tz * TZ;
-  const int cells = TX * TY * TZ;
-  for (int c = threadIdx.x; c < cells; c += kThreads) acc[c] = 0.f;
+  for (int c = threadIdx.x; c < tile_cells(g); c += kThreads) acc[c] = 0.f;
   build_ranges(rt, off, tx, ty, tz, g);
   const uint32_t total = rt.pre[27];
-  constexpr int kBatch = 4;   // particles whose loads are in flight together
+  constexpr int kBatch = 8;   // particles whose loads are in flight together
   for (uint32_t base = 0; base < total; base += kThreads * kBatch) {
-    float px[kBatch][3];
+    // all range searches (LDS) first, then all loads, so that the kBatch
+    // loads of a thread are in flight together; positions past the end are
+    // clamped onto the last particle (a valid address) and skipped below
+    uint32_t jj[kBatch];
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
       const uint32_t idx = base + threadIdx.x + u * kThreads;
-      if (idx < total) {
-        const uint32_t j = range_particle(rt, idx);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) px[u][d] = pos[3 * (long)j + d];
-      }
+      jj[u] = range_particle(rt, idx < total ? idx : total - 1);
     }
+    float px[kBatch][3];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) px[u][d] = pos[3 * (long)jj[u] + d];
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
     if (base + threadIdx.x + u * kThreads >= total) continue;
@@ -226,16 +245,19 @@ __global__ __launch_bounds__(kThreads) void k_paint(const float* __restrict__ po
         for (int c = 0; c < 2; ++c) {
           const int cz = lz + c;
           if (cz < 0 || cz >= TZ) continue;
-          atomicAdd(&acc[(cx * TY + cy) * TZ + cz], wxy * wz[c]);
+          atomicAdd(&acc[tile_li(cx, cy, cz, g)], wxy * wz[c]);
         }
       }
     }
     }
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < cells; c += kThreads) {
-    const int cz = c % TZ, cy = (c / TZ) % TY, cx = c / (TZ * TY);
-    out[((long)(ox + cx) * n + (oy + cy)) * n + (oz + cz)] = acc[c] * scale + offset;
+  for (int c = threadIdx.x; c < store_walk_len(g); c += kThreads) {
+    int cx, cy, cz;
+    store_walk(c, g, cx, cy, cz);
+    if (cx >= TX) continue;
+    const int x = ox + cx, y = oy + cy, z = oz + cz;
+    out[STD ? ((long)x * n + y) * n + z : blk_real(x, y, z, n)] = acc[tile_li(cx, cy, cz, g)] * scale + offset;
   }
 }
 
@@ -245,12 +267,12 @@ __global__ __launch_bounds__(kThreads) void k_paint(const float* __restrict__ po
 // grid is too small for the neighbourhood to be unambiguous).
 __device__ __forceinline__ int key_slot(uint32_t key, int rx, int ry, int rz, const TileGeom& g) {
   if (g.ntx < 3 || g.nty < 3 || g.ntz < 3) return -1;
-  const uint32_t tile = key >> 3;
-  const int kz = tile % g.ntz, ky = (tile / g.ntz) % g.nty, kx = tile / (g.ntz * g.nty);
+  int kx, ky, kz;
+  tile_coords((int)(key >> 3), g, kx, ky, kz);
   auto d = [](int a, int b, int nt) {
     int v = a - b;
-    if (v > nt / 2) v -= nt;
-    if (v < -nt / 2) v += nt;
+    if (v > (nt >> 1)) v -= nt;
+    if (v < -(nt >> 1)) v += nt;
     return v;
   };
   const int dx = d(kx, rx, g.ntx), dy = d(ky, ry, g.nty), dz = d(kz, rz, g.ntz);
@@ -261,8 +283,8 @@ __device__ __forceinline__ int key_slot(uint32_t key, int rx, int ry, int rz, co
 __device__ __forceinline__ uint32_t slot_key(int slot, int rx, int ry, int rz, const TileGeom& g) {
   const int cls = slot & 7, s = slot >> 3;
   const int dz = s % 3 - 1, dy = (s / 3) % 3 - 1, dx = s / 9 - 1;
-  const int kx = (rx + dx + g.ntx) % g.ntx, ky = (ry + dy + g.nty) % g.nty, kz = (rz + dz + g.ntz) % g.ntz;
-  return ((((uint32_t)kx * g.nty + ky) * g.ntz + kz) << 3) | (uint32_t)cls;
+  const int kx = (rx + dx) & (g.ntx - 1), ky = (ry + dy) & (g.nty - 1), kz = (rz + dz) & (g.ntz - 1);
+  return ((((uint32_t)kx << g.lny | (uint32_t)ky) << g.lnz | (uint32_t)kz) << 3) | (uint32_t)cls;
 }
 
 // One tile-sorted particle per thread: CIC gather of the 8 corners from the
@@ -289,9 +311,9 @@ __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
     cic_base(a.pos[3 * j0 + 0], n, ix, t);
     cic_base(a.pos[3 * j0 + 1], n, iy, t);
     cic_base(a.pos[3 * j0 + 2], n, iz, t);
-    rx = ix / g.tx;
-    ry = iy / g.ty;
-    rz = iz / g.tz;
+    rx = ix >> g.lx;
+    ry = iy >> g.ly;
+    rz = iz >> g.lz;
     __syncthreads();
   }
   int slot = -1;
@@ -310,18 +332,22 @@ __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
     cic_base(x[1], n, iy, fy);
     cic_base(x[2], n, iz, fz);
     const int jx = (ix + 1) & (n - 1), jy = (iy + 1) & (n - 1), jz = (iz + 1) & (n - 1);
-    const long rows[4] = {((long)ix * n + iy) * n, ((long)ix * n + jy) * n, ((long)jx * n + iy) * n,
-                          ((long)jx * n + jy) * n};
-    const float wxy[4] = {(1.f - fx) * (1.f - fy), (1.f - fx) * fy, fx * (1.f - fy), fx * fy};
+    // corner (x, y, z) at fi + 3 * blk_real(x, y, z): x and x+1 of one block
+    // are adjacent 12-byte cells
+    const int xs[2] = {ix, jx}, ys[2] = {iy, jy}, zs[2] = {iz, jz};
+    const float wx[2] = {1.f - fx, fx}, wy[2] = {1.f - fy, fy}, wz[2] = {1.f - fz, fz};
     float F[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const float* c0 = a.fi + 3 * (rows[r] + iz);
-      const float* c1 = a.fi + 3 * (rows[r] + jz);
-      const float w0 = wxy[r] * (1.f - fz), w1 = wxy[r] * fz;
+    for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int d = 0; d < 3; ++d) F[d] += w0 * c0[d] + w1 * c1[d];
-    }
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const float* cp = a.fi + 3 * blk_real(xs[e], ys[b], zs[c], n);
+          const float w = wx[e] * wy[b] * wz[c];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) F[d] += w * cp[d];
+        }
     const uint32_t id = a.id ? a.id[j] : (uint32_t)j;
     if (a.flags & RO_FORCE_BYID) {
 #pragma unroll
@@ -406,21 +432,23 @@ __global__ __launch_bounds__(kThreads) void k_power_bins(PowerArgs a) {
   for (int i = threadIdx.x; i < a.n_bins; i += kThreads) sw[i] = sk[i] = sp[i] = 0.0;
   __syncthreads();
   const int n = a.n, h = n / 2;
+  const int ln = __builtin_ctz(n), lh = ln - 1;
   const long nmain = (long)n * n * h;
   const long ntot = nmain + (long)n * n;
   const long stride = (long)gridDim.x * blockDim.x;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < ntot; i += stride) {
     int kx, ky, kz;
     float2 v;
-    if (i < nmain) {
-      kz = (int)(i % h);
-      ky = (int)((i / h) % n);
-      kx = (int)(i / ((long)h * n));
+    if (i < nmain) {   // x-blocked c[kx/8][ky][kz][kx%8]; n, h = n/2 powers of two
+      const long r = i >> 3;
+      kz = (int)(r & (h - 1));
+      ky = (int)((r >> lh) & (n - 1));
+      kx = (int)((r >> (lh + ln)) << 3) + (int)(i & 7);
       v = a.c[i];
-    } else {
-      const long j = i - nmain;
-      ky = (int)(j % n);
-      kx = (int)(j / n);
+    } else {           // q[kx/8][ky][kx%8]
+      const long j = i - nmain, r = j >> 3;
+      ky = (int)(r & (n - 1));
+      kx = (int)((r >> ln) << 3) + (int)(j & 7);
       kz = h;
       v = a.q[j];
     }
@@ -466,13 +494,34 @@ __global__ void k_spec_pack(const float2* __restrict__ c, const float2* __restri
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
     const int kz = (int)(i % (h + 1));
     const long line = i / (h + 1);
+    const int kx = (int)(line / n), ky = (int)(line % n);
+    const long ec = blk_spec(kx, ky, kz < h ? kz : 0, n), eq = blk_nyq(kx, ky, n);
     if (to_numpy) {
-      const float2 v = kz < h ? c[line * h + kz] : q[line];
+      const float2 v = kz < h ? c[ec] : q[eq];
       out[i] = make_float2(v.x * scale, v.y * scale);
     } else {
-      float2* dst = kz < h ? const_cast<float2*>(c) + line * h + kz : const_cast<float2*>(q) + line;
+      float2* dst = kz < h ? const_cast<float2*>(c) + ec : const_cast<float2*>(q) + eq;
       const float2 v = out[i];
       *dst = make_float2(v.x * scale, v.y * scale);
+    }
+  }
+}
+
+// plain [x][y][z] <-> x-blocked real mesh (caller-visible buffers); the
+// output index runs over threads so that the stores are contiguous
+__global__ void k_relayout(const float* __restrict__ in, float* __restrict__ out, int ln, int to_blocked) {
+  const long n3 = 1L << (3 * ln);
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n3; e += stride) {
+    int x, y, z;
+    if (to_blocked) {
+      blk_real_xyz(e, ln, x, y, z);
+      out[e] = in[((((long)x << ln) + y) << ln) + z];
+    } else {
+      z = (int)(e & ((1L << ln) - 1));
+      y = (int)((e >> ln) & ((1L << ln) - 1));
+      x = (int)(e >> (2 * ln));
+      out[e] = in[blk_real(x, y, z, 1 << ln)];
     }
   }
 }
@@ -490,8 +539,16 @@ inline int grid_for(long n, int per = kThreads, int cap = 65536) {
 
 }  // namespace
 
-void launch_noise(uint64_t seed, long n, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_noise, dim3(grid_for(n)), dim3(kThreads), 0, s, seed, n, out);
+void launch_noise(uint64_t seed, int n_side, float* out, bool blocked, hipStream_t s) {
+  const long n3 = (long)n_side * n_side * n_side;
+  hipLaunchKernelGGL(k_noise, dim3(grid_for(n3)), dim3(kThreads), 0, s, seed, n3, __builtin_ctz(n_side),
+                     blocked ? 1 : 0, out);
+}
+
+void launch_relayout(const float* in, float* out, int n_side, bool to_blocked, hipStream_t s) {
+  const long n3 = (long)n_side * n_side * n_side;
+  hipLaunchKernelGGL(k_relayout, dim3(grid_for(n3)), dim3(kThreads), 0, s, in, out, __builtin_ctz(n_side),
+                     to_blocked ? 1 : 0);
 }
 
 void launch_lpt_delta2(float* const* phi6, long n, float* out, hipStream_t s) {
@@ -528,8 +585,12 @@ void launch_scatter(const ScatterArgs& a, hipStream_t s) {
 }
 
 void launch_paint(const float* pos_sorted, const uint32_t* off, const TileGeom& g, float* out, float scale,
-                  float offset, hipStream_t s) {
-  hipLaunchKernelGGL(k_paint, dim3(g.ntiles), dim3(kThreads), 0, s, pos_sorted, off, g, out, scale, offset);
+                  float offset, bool std_layout, hipStream_t s) {
+  if (std_layout)
+    hipLaunchKernelGGL(k_paint<true>, dim3(g.ntiles), dim3(kThreads), 0, s, pos_sorted, off, g, out, scale, offset);
+  else
+    hipLaunchKernelGGL(k_paint<false>, dim3(g.ntiles), dim3(kThreads), 0, s, pos_sorted, off, g, out, scale,
+                       offset);
 }
 
 void launch_readout(const ReadoutArgs& a, hipStream_t s) {

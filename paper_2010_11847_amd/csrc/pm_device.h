@@ -34,10 +34,47 @@ static __device__ __forceinline__ float wrap_pos(float x, float n) {
 }
 
 static __device__ __forceinline__ uint32_t tile_key(int ix, int iy, int iz, const TileGeom& g) {
-  const uint32_t tile = ((uint32_t)(ix / g.tx) * g.nty + (uint32_t)(iy / g.ty)) * g.ntz + (uint32_t)(iz / g.tz);
-  const uint32_t c = (uint32_t)((ix % g.tx) == g.tx - 1) | ((uint32_t)((iy % g.ty) == g.ty - 1) << 1) |
-                     ((uint32_t)((iz % g.tz) == g.tz - 1) << 2);
+  const uint32_t tile = ((((uint32_t)ix >> g.lx) << g.lny | ((uint32_t)iy >> g.ly)) << g.lnz) | ((uint32_t)iz >> g.lz);
+  const uint32_t c = (uint32_t)((ix & (g.tx - 1)) == g.tx - 1) | ((uint32_t)((iy & (g.ty - 1)) == g.ty - 1) << 1) |
+                     ((uint32_t)((iz & (g.tz - 1)) == g.tz - 1) << 2);
   return tile * 8u + c;
+}
+
+// (x, y, z) tile coordinates of a flattened tile index
+static __device__ __forceinline__ void tile_coords(int tile, const TileGeom& g, int& tx, int& ty, int& tz) {
+  tz = tile & (g.ntz - 1);
+  ty = (tile >> g.lnz) & (g.nty - 1);
+  tx = tile >> (g.lnz + g.lny);
+}
+
+// LDS slot of tile cell (cx, cy, cz): z fastest, rows of tz cells, with the
+// z bits XOR-swizzled by (cx%8, bit 1 of cy) so that
+//  - the atomics of a wave of lattice-ordered particles (steps of 2 cells in
+//    z and y) spread over all banks instead of the even ones, and
+//  - the store loop, whose lanes run over x%8 fastest (the x-blocked mesh),
+//    reads rows that start on different banks.
+// The swizzle permutes cells within a row, so slots stay in [0, tx*ty*tz).
+static __device__ __forceinline__ int tile_li(int cx, int cy, int cz, const TileGeom& g) {
+  const int swz = (((cx & 7) << 3) | ((cy >> 1) & 1)) & (g.tz - 1);
+  return ((((cx << g.ly) | cy) << g.lz) | (cz ^ swz));
+}
+static __device__ __forceinline__ int tile_cells(const TileGeom& g) { return g.tx * g.ty * g.tz; }
+// the i-th cell of the store walk: x%8 fastest, then z, y, x/8 (contiguous
+// runs of the x-blocked mesh); tiles narrower than 8 cells along x skip the
+// cells with cx >= tx
+static __device__ __forceinline__ int store_walk_len(const TileGeom& g) { return ((g.tx + 7) >> 3) * 8 * g.ty * g.tz; }
+static __device__ __forceinline__ void store_walk(int c, const TileGeom& g, int& cx, int& cy, int& cz) {
+  const int r = c >> 3;
+  cz = r & (g.tz - 1);
+  cy = (r >> g.lz) & (g.ty - 1);
+  cx = ((r >> (g.lz + g.ly)) << 3) | (c & 7);
+}
+
+// (x, y, z) cell offsets inside a tile of flattened cell index c (z fastest)
+static __device__ __forceinline__ void cell_coords(int c, const TileGeom& g, int& cx, int& cy, int& cz) {
+  cz = c & (g.tz - 1);
+  cy = (c >> g.lz) & (g.ty - 1);
+  cx = c >> (g.lz + g.ly);
 }
 
 // Rank of this lane's key among all keys counted so far: lanes of a wave
@@ -68,45 +105,53 @@ static __device__ __forceinline__ uint32_t agg_rank(uint32_t* count, uint32_t ke
 // prefix sums of the range lengths, rstart the first particle of each range.
 struct RangeTable {
   uint32_t start[27];
-  uint32_t pre[28];
+  uint32_t pre[32];   // exclusive prefix of the range lengths; pre[27] = total, pre[28..31] = ~0
 };
 
+// Ranges of the 27 (neighbour tile, class) bins whose particles deposit
+// into tile (tx, ty, tz).  Wave 0 loads the bin offsets and scans the
+// lengths with lane shuffles; one barrier publishes the table.
 static __device__ __forceinline__ void build_ranges(RangeTable& rt, const uint32_t* __restrict__ off, int tx, int ty,
                                                     int tz, const TileGeom& g) {
   const int r = threadIdx.x;
-  uint32_t len = 0;
-  if (r < 27) {
-    // enumerate (e, cls) pairs with (cls & e) == e in a fixed order
-    int k = 0, e_sel = 0, c_sel = 0;
-    for (int e = 0; e < 8; ++e)
-      for (int c = 0; c < 8; ++c)
-        if ((c & e) == e) {
-          if (k == r) { e_sel = e; c_sel = c; }
-          ++k;
-        }
-    const int sx = (tx - (e_sel & 1) + g.ntx) % g.ntx, sy = (ty - ((e_sel >> 1) & 1) + g.nty) % g.nty,
-              sz = (tz - ((e_sel >> 2) & 1) + g.ntz) % g.ntz;
-    const uint32_t bin = (((uint32_t)sx * g.nty + sy) * g.ntz + sz) * 8 + c_sel;
-    const uint32_t b0 = off[bin], b1 = off[bin + 1];
-    rt.start[r] = b0;
-    len = b1 - b0;
-    rt.pre[r + 1] = len;
-  }
-  if (r == 0) rt.pre[0] = 0;
-  __syncthreads();
-  if (r == 0) {
-    for (int i = 1; i <= 27; ++i) rt.pre[i] += rt.pre[i - 1];
+  if (r < 64) {
+    uint32_t len = 0;
+    if (r < 27) {
+      // enumerate (e, cls) pairs with (cls & e) == e in a fixed order
+      int k = 0, e_sel = 0, c_sel = 0;
+      for (int e = 0; e < 8; ++e)
+        for (int c = 0; c < 8; ++c)
+          if ((c & e) == e) {
+            if (k == r) { e_sel = e; c_sel = c; }
+            ++k;
+          }
+      const int sx = (tx - (e_sel & 1)) & (g.ntx - 1), sy = (ty - ((e_sel >> 1) & 1)) & (g.nty - 1),
+                sz = (tz - ((e_sel >> 2) & 1)) & (g.ntz - 1);
+      const uint32_t bin = (((uint32_t)sx * g.nty + sy) * g.ntz + sz) * 8 + c_sel;
+      const uint32_t b0 = off[bin], b1 = off[bin + 1];
+      rt.start[r] = b0;
+      len = b1 - b0;
+    }
+    uint32_t v = len;   // inclusive scan over lanes 0..31
+#pragma unroll
+    for (int d = 1; d < 32; d <<= 1) {
+      const uint32_t t = __shfl_up(v, d, 64);
+      if (r >= d) v += t;
+    }
+    if (r < 27) rt.pre[r + 1] = v;
+    if (r == 0) rt.pre[0] = 0;
+    if (r >= 28 && r < 32) rt.pre[r] = 0xFFFFFFFFu;
   }
   __syncthreads();
 }
 
-// particle index of flattened position idx < rt.pre[27]
+// particle index of flattened position idx < rt.pre[27]: the range r with
+// pre[r] <= idx < pre[r+1], by a fixed five-step search (no loop)
 static __device__ __forceinline__ uint32_t range_particle(const RangeTable& rt, uint32_t idx) {
-  int lo = 0, hi = 27;   // find r with pre[r] <= idx < pre[r+1]
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (rt.pre[mid] <= idx) lo = mid; else hi = mid;
-  }
+  uint32_t lo = 0;
+#pragma unroll
+  for (uint32_t step = 16; step > 0; step >>= 1)
+    if (rt.pre[lo + step] <= idx) lo += step;
   return rt.start[lo] + (idx - rt.pre[lo]);
 }
 

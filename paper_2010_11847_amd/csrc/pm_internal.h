@@ -8,14 +8,16 @@
 #include <string>
 #include <vector>
 
+#include "layout.h"
 #include "pm.h"
 
 namespace pmk {
 
-// A real N^3 mesh stored so that its r2c transform fits in place:
-//   real view   r[N][N][N]           (float)
-//   complex view c[N][N][N/2]        (float2, same bytes, kz = 0 .. N/2-1)
-//   Nyquist plane q[N][N]            (float2, kz = N/2, indexed [kx][ky])
+// A real N^3 mesh in the x-blocked layout (layout.h), stored so that its
+// r2c transform fits in place:
+//   real view    r[N/8][N][N][8]       (float)
+//   complex view c[N/8][N][N/2][8]     (float2, same bytes, kz = 0 .. N/2-1)
+//   Nyquist plane q[N/8][N][8]         (float2, kz = N/2)
 struct Field {
   float* r = nullptr;
   float2* q = nullptr;
@@ -89,7 +91,10 @@ void fft_x_fused(const FftTables& t, const Field& in, const SpecOp& op, hipStrea
 void fft_z_r2c(const FftTables& t, Field* f, int nf, hipStream_t s);
 void fft_y(const FftTables& t, Field* f, int nf, int dir, hipStream_t s);
 void fft_z_c2r(const FftTables& t, Field* f, int nf, hipStream_t s);
-// z pass of three fields written as one interleaved real mesh out[(x*N+y)*N+z][3]
+// z pass of three fields written as one interleaved real mesh
+// out[x/8][y][z][x%8][3] (the force meshes the particle readout gathers from).
+// The three fields must be equally spaced in memory (f[2] - f[1] == f[1] - f[0]
+// for both the arrays and the Nyquist planes), as the workspace meshes are.
 void fft_z_c2r_interleaved3(const FftTables& t, const Field* f, float* out, hipStream_t s);
 // Inverse: y pass then z pass (complex + Nyquist plane -> real), unnormalised.
 void fft_c2r_yz(const FftTables& t, Field* f, int nf, hipStream_t s);

@@ -64,3 +64,26 @@ def test_workspace_sizes_and_validation(lib):
 def test_strerror(lib):
     assert lib.pm_strerror(0) == b"ok"
     assert lib.pm_strerror(-2) == b"workspace too small"
+
+
+def test_no_kernel_uses_scratch():
+    """Every HIP kernel keeps its state in registers and LDS: a kernel that
+    spills to (or builds arrays in) private scratch memory pays HBM traffic
+    per lane.  Reads the compiler's resource report written by the build."""
+    import glob
+    import re
+    build = os.path.join(ROOT, "paper_2010_11847_amd", "_build")
+    reports = glob.glob(os.path.join(build, "*.usage.txt"))
+    if not reports:
+        pytest.skip("library not built")
+    bad = []
+    for path in reports:
+        name = None
+        for line in open(path):
+            m = re.search(r"Function Name: (\S+)", line)
+            if m:
+                name = m.group(1)
+            m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", line)
+            if m and int(m.group(1)) > 0:
+                bad.append((os.path.basename(path), name, int(m.group(1))))
+    assert not bad, bad
