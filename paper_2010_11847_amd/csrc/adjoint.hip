@@ -56,6 +56,10 @@ __global__ __launch_bounds__(kThreads) void k_paint3w(const float* __restrict__ 
     for (int u = 0; u < kBatch; ++u)
 #pragma unroll
       for (int d = 0; d < 3; ++d) m[u][d] = pbar[3 * pid[u] + d] * k;
+    // pin the loads above the per-particle branches (see the forward paint)
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+      asm volatile("" : "+v"(px[u][0]), "+v"(px[u][1]), "+v"(px[u][2]), "+v"(m[u][0]), "+v"(m[u][1]), "+v"(m[u][2]));
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
       if (base + threadIdx.x + u * kThreads >= total) continue;

@@ -217,10 +217,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(ColPass p, const float2* 
           v[j1] = ok ? base[row_off<BLK>(R2 * j1 + j2, g.sn) + m * CS] : make_float2(0.f, 0.f);
         dft<R1, DIR>(v);
 #pragma unroll
-        for (int l1 = 0; l1 < R1; ++l1) {
-          const float2 w = l1 == 0 ? v[l1] : cmul(v[l1], tw_get<DIR>(tw, j2 * l1));
-          lds[l1 * SA + j2 * M + m] = w;
-        }
+        for (int l1 = 0; l1 < R1; ++l1) lds[l1 * SA + j2 * M + m] = l1 == 0 ? v[l1] : cmul(v[l1], tw_get<DIR>(tw, j2 * l1));
       }
     }
     __syncthreads();
@@ -874,6 +871,149 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_fused(FusedArgs a) {
   }
 }
 
+// The force's x pass as three column passes over the x-blocked spectrum:
+//   SCALE : forward x transform, times the force's common factor
+//           c(k) = scale W(k)^-n S(k) / K^2(k), in place;
+//   OUT   : inverse x transform of D(w_x)^p times the scaled spectrum,
+//           stored with the coefficient of every output of power p.
+// Against the fused pass (forward, multiply and inverse in one tile, once
+// per basis) this does one forward transform instead of one per basis and
+// keeps each tile's compute short; it moves one more read and write of the
+// spectrum.  N >= 64 (two-stage columns).
+enum XOpMode { XOP_SCALE = 0, XOP_OUT = 1 };
+
+template <int N, int M, int MODE>
+__global__ __launch_bounds__(kThreads) void k_fft_x_op(FusedArgs a) {
+  constexpr int R1 = Split<N>::R1, R2 = Split<N>::R2;
+  static_assert(R2 > 1, "columns split over two stages");
+  constexpr int IA = (M * R2 + kThreads - 1) / kThreads;
+  constexpr int IB = (M * R1 + kThreads - 1) / kThreads;
+  constexpr int SA = ColLds<N, M>::SA;
+  constexpr int DIR = MODE == XOP_SCALE ? -1 : 1;
+  __shared__ float2 lds[ColLds<N, M>::size];
+  int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int mode = tile >= a.nb_main ? 1 : 0;
+  if (mode) tile -= a.nb_main;
+  const ColGeom& g = mode ? a.gp : a.gm;
+  const int b = tile / g.ntc;
+  const int c0 = (tile - b * g.ntc) * M;
+  const long off = b * g.sb + (long)c0 * 8;
+  const int tid = threadIdx.x;
+  const SpecOp& op = a.op;
+  const FftTables& t = a.t;
+  const int p = a.pbasis;
+  const float2* src = (mode == 0 ? a.in_main : a.in_nyq) + off;
+  // (ky, kz) of column m; masked columns map to the zero mode
+  auto freq = [&](int m, int& ky, int& kz) {
+    if (c0 + m >= g.ncols) { ky = 0; kz = 0; }
+    else if (mode == 0) { ky = b; kz = c0 + m; }
+    else { ky = c0 + m; kz = N / 2; }
+  };
+  // stage A: rows n = R2*j1 + j2 (kx for OUT, x for SCALE).  The symbol
+  // factors of OUT are loaded before the data and pinned in registers.
+#pragma unroll
+  for (int i = 0; i < IA; ++i) {
+    const int it = tid + i * kThreads;
+    if (it < M * R2) {
+      const int m = it % M, j2 = it / M;
+      const bool ok = c0 + m < g.ncols;
+      // every global load of the item first (twiddles, symbol factors,
+      // data), then one pin: sunk to their uses, they would go out a few
+      // at a time with waits in between
+      float2 tw[R1];
+      float fac[R1];
+      float2 v[R1];
+      const bool scale_in = MODE == XOP_OUT && p > 0;   // uniform
+#pragma unroll
+      for (int l1 = 1; l1 < R1; ++l1) tw[l1] = tw_get<DIR>(t.tw_n, j2 * l1);
+      if (scale_in) {
+#pragma unroll
+        for (int j1 = 0; j1 < R1; ++j1) fac[j1] = t.dxy[R2 * j1 + j2];
+      }
+#pragma unroll
+      for (int j1 = 0; j1 < R1; ++j1)
+        v[j1] = ok ? src[row_off<true>(R2 * j1 + j2, g.sn) + m * 8] : make_float2(0.f, 0.f);
+#pragma unroll
+      for (int l1 = 1; l1 < R1; ++l1) asm volatile("" : "+v"(tw[l1]));
+      if (scale_in) {
+#pragma unroll
+        for (int j1 = 0; j1 < R1; ++j1) v[j1] = cscale(v[j1], powp(fac[j1], p));
+      }
+      dft<R1, DIR>(v);
+#pragma unroll
+      for (int l1 = 0; l1 < R1; ++l1) lds[l1 * SA + j2 * M + m] = l1 == 0 ? v[l1] : cmul(v[l1], tw[l1]);
+    }
+  }
+  __syncthreads();
+  // stage B: outputs n = l1 + R1*l2
+#pragma unroll
+  for (int i = 0; i < IB; ++i) {
+    const int it = tid + i * kThreads;
+    if (it < M * R1) {
+      const int m = it % M, l1 = it / M;
+      float2 v[R2];
+#pragma unroll
+      for (int j2 = 0; j2 < R2; ++j2) v[j2] = lds[l1 * SA + j2 * M + m];
+      dft<R2, DIR>(v);
+      if (c0 + m < g.ncols) {
+        int ky, kz;
+        freq(m, ky, kz);
+        if (MODE == XOP_SCALE) {
+          // every factor before the first store: a table load issued after a
+          // store through another pointer would wait for that store
+          // the force's c(k) = scale W^-n S / K^2 with the per-kx table
+          // values loaded together (uniform branches outside the loops)
+          float fac[R2], aux[R2];
+#pragma unroll
+          for (int l2 = 0; l2 < R2; ++l2) fac[l2] = t.kxy[l1 + R1 * l2];
+#pragma unroll
+          for (int l2 = 0; l2 < R2; ++l2) asm volatile("" : "+v"(fac[l2]));
+          const float kyz = t.kxy[ky] + t.kz[kz];
+#pragma unroll
+          for (int l2 = 0; l2 < R2; ++l2) {
+            const float kk = fac[l2] + kyz;
+            fac[l2] = kk > 0.f ? op.scale / kk : 0.f;
+          }
+          if (op.deconv) {
+            const float wyz = t.wxy[ky] * t.wz[kz];
+#pragma unroll
+            for (int l2 = 0; l2 < R2; ++l2) aux[l2] = t.wxy[l1 + R1 * l2];
+#pragma unroll
+            for (int l2 = 0; l2 < R2; ++l2) {
+              const float wv = aux[l2] * wyz;
+              fac[l2] /= (op.deconv == 1 ? wv : wv * wv);
+            }
+          }
+          if (op.split) {
+            const float syz = t.sxy[ky] * t.sz[kz];
+#pragma unroll
+            for (int l2 = 0; l2 < R2; ++l2) aux[l2] = t.sxy[l1 + R1 * l2];
+#pragma unroll
+            for (int l2 = 0; l2 < R2; ++l2) {
+              const float sv = aux[l2] * syz;
+              fac[l2] *= (op.split == 1 ? sv : 1.f - sv);
+            }
+          }
+          float2* dst = (mode == 0 ? op.out_c[0] : op.out_q[0]) + off;
+#pragma unroll
+          for (int l2 = 0; l2 < R2; ++l2) dst[row_off<true>(l1 + R1 * l2, g.sn) + m * 8] = cscale(v[l2], fac[l2]);
+        } else {
+          const float dy = t.dxy[ky], dz = t.dz[kz];
+#pragma unroll 1
+          for (int o = 0; o < op.n_out; ++o) {
+            const Term tm = op_term(op.kind, o);
+            if (tm.p != p) continue;
+            const float2 cf = coef_of(tm, dy, dz);
+            float2* dst = (mode == 0 ? op.out_c[o] : op.out_q[o]) + off;
+#pragma unroll
+            for (int l2 = 0; l2 < R2; ++l2) dst[row_off<true>(l1 + R1 * l2, g.sn) + m * 8] = cmul(v[l2], cf);
+          }
+        }
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // host-side launch helpers
 // ---------------------------------------------------------------------------
@@ -970,6 +1110,22 @@ void xfused(const FftTables& t, const Field& in, const SpecOp& op, hipStream_t s
     return;
   }
   const int pfirst = __builtin_ctz(pmask), plast = 31 - __builtin_clz(pmask);
+  if constexpr (Split<N>::R2 > 1) {
+    if (op.kind == OP_FORCE) {
+      // scale in place (the spectrum buffer), then one inverse per basis in
+      // increasing p; the output that aliases the input has the highest p
+      FusedArgs sa = a;
+      sa.op.out_c[0] = const_cast<float2*>(a.in_main);
+      sa.op.out_q[0] = const_cast<float2*>(a.in_nyq);
+      hipLaunchKernelGGL((k_fft_x_op<N, M, XOP_SCALE>), grid, dim3(kThreads), 0, s, sa);
+      for (int p = pfirst; p <= plast; ++p) {
+        if (!(pmask >> p & 1)) continue;
+        a.pbasis = p;
+        hipLaunchKernelGGL((k_fft_x_op<N, M, XOP_OUT>), grid, dim3(kThreads), 0, s, a);
+      }
+      return;
+    }
+  }
   if (fan_in) {
     for (int o = 0; o < nterm && first_in < 0; ++o)
       if (op_term(op.kind, o).p == pfirst) first_in = o;

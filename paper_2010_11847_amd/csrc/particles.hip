@@ -218,6 +218,10 @@ __global__ __launch_bounds__(kThreads) void k_paint(const float* __restrict__ po
     for (int u = 0; u < kBatch; ++u)
 #pragma unroll
       for (int d = 0; d < 3; ++d) px[u][d] = pos[3 * (long)jj[u] + d];
+    // pin the loads here: each particle's use sits in its own branch, and
+    // sunk into those branches the loads would run one round trip at a time
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) asm volatile("" : "+v"(px[u][0]), "+v"(px[u][1]), "+v"(px[u][2]));
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
     if (base + threadIdx.x + u * kThreads >= total) continue;
