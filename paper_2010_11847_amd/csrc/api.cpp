@@ -40,7 +40,7 @@ pmk::TileGeom make_tiles(int n) {
   pmk::TileGeom g;
   g.n = n;
   g.tx = g.ty = n / 2 < 16 ? n / 2 : 16;
-  g.tz = n / 2 < 32 ? n / 2 : 32;
+  g.tz = n / 2 < 16 ? n / 2 : 16;
   g.ntx = n / g.tx;
   g.nty = n / g.ty;
   g.ntz = n / g.tz;

@@ -258,7 +258,9 @@ struct ZGeomL {
   static constexpr int R1 = Split<H>::R1, R2 = Split<H>::R2;
   static constexpr int L = LINES;
   static constexpr int LP = L + 1;                          // padded line stride of the exchange
-  static constexpr int ZP = H + 1;                          // padded natural-order Z
+  // padded natural-order Z: a row stride of 4 (mod 32) float2 puts lanes
+  // that run over the line index on different banks (<= 2-way conflicts)
+  static constexpr int ZP = H >= 32 ? H + 4 : H + 1;
   static constexpr int XS = (R2 > 1) ? H * LP : 1;          // exchange [l1][j2][m]
   static constexpr int ZS = L * ZP;                         // natural-order Z[m][k]
   static constexpr int RS = L * H;                          // staged region (complex)

@@ -9,7 +9,7 @@
 
 namespace pmk {
 
-constexpr int kTileCells = 16 * 16 * 32;   // largest tile (LDS sizing)
+constexpr int kTileCells = 16 * 16 * 16;   // largest tile (LDS sizing)
 
 // blockIdx -> tile so that consecutive tiles of one launch land on the same
 // XCD (workgroups are dispatched round-robin over the 8 XCDs).
