@@ -38,7 +38,9 @@ def kernel_bytes(w, np3):
     return {
         "fft_z_r2c": real + spec,                       # 1 field
         "fft_y_fwd": 2 * spec,                          # 1 field, in place
-        "fft_x_fused": spec + 3 * spec,                 # read 1 spectrum, write 3
+        "fft_x_scale": 2 * spec,                        # forward x times c(k), in place
+        "fft_x_inv0": spec + 2 * spec,                  # inverse x, basis D^0: F_y, F_z
+        "fft_x_inv1": 2 * spec,                         # inverse x, basis D^1: F_x
         "fft_y_inv": 3 * 2 * spec,                      # 3 fields
         "fft_z_c2r": 3 * (spec + real),                 # 3 fields
         "paint": 12.0 * np3 + real,                     # positions in, mesh out

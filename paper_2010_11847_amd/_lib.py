@@ -10,7 +10,9 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpm.so")
+# PM_LIBRARY may name another build of the same library (same ABI), e.g.
+# one compiled with different kernel options, to compare builds
+LIB_PATH = os.environ.get("PM_LIBRARY") or os.path.join(HERE, "libpm.so")
 
 PM_OK, PM_EINVAL, PM_ENOMEM, PM_EHIP, PM_ESTATE = 0, -1, -2, -3, -4
 

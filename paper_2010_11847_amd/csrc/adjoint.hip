@@ -5,12 +5,12 @@
 // cotangent F_bar = p_bar K (K the sum of the kicks that used F(x_j)):
 //   term A  the readout positions: x_bar += sum_c dW/dx (F_bar . M(c)),
 //           M the three force meshes recomputed from x_j;
-//   term B  the painting positions: R_d = paint(x, F_bar_d) (3 channels),
+//   term B  the painting positions: R_d = paint(x, F_bar_d) (3 channels,
+//           the forward paint kernel with signed per-particle masses),
 //           delta_bar = sum_d G_d^T R_d (G_d^T = -G_d, the FD kernel is odd),
 //           x_bar += sum_c dW/dx (s delta_bar(c)), s = Ng^3 / Np.
-// Both use the tile-sorted particles and LDS tiles like the forward paint and
-// readout; cotangents live in particle-index order and are gathered and
-// scattered through the sorted ids (each particle is owned by one thread).
+// Cotangents live in particle-index order and are gathered and scattered
+// through the sorted ids (each particle is owned by one thread).
 #include "particles.h"
 #include "pm_device.h"
 
@@ -18,95 +18,6 @@ namespace pmk {
 namespace {
 
 constexpr int kThreads = 256;
-
-// 3-channel CIC paint with per-particle weights w_d = pbar[id][d] * k.
-__global__ __launch_bounds__(kThreads) void k_paint3w(const float* __restrict__ pos, const uint32_t* __restrict__ id,
-                                                      const uint32_t* __restrict__ off, TileGeom g,
-                                                      const float* __restrict__ pbar, float k, float* __restrict__ o0,
-                                                      float* __restrict__ o1, float* __restrict__ o2) {
-  __shared__ float acc[3][kTileCells];
-  __shared__ RangeTable rt;
-  const int TX = g.tx, TY = g.ty, TZ = g.tz, n = g.n;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  int tx, ty, tz;
-  tile_coords(tile, g, tx, ty, tz);
-  const int ox = tx * TX, oy = ty * TY, oz = tz * TZ;
-  for (int c = threadIdx.x; c < tile_cells(g); c += kThreads) acc[0][c] = acc[1][c] = acc[2][c] = 0.f;
-  build_ranges(rt, off, tx, ty, tz, g);
-  const uint32_t total = rt.pre[27];
-  constexpr int kBatch = 4;   // particles whose loads are in flight together
-  for (uint32_t base = 0; base < total; base += kThreads * kBatch) {
-    // range searches first, then the position/id loads, then the weight
-    // loads; positions past the end are clamped onto the last particle
-    uint32_t jj[kBatch];
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      const uint32_t idx = base + threadIdx.x + u * kThreads;
-      jj[u] = range_particle(rt, idx < total ? idx : total - 1);
-    }
-    float px[kBatch][3], m[kBatch][3];
-    long pid[kBatch];
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-#pragma unroll
-      for (int d = 0; d < 3; ++d) px[u][d] = pos[3 * (long)jj[u] + d];
-      pid[u] = (long)id[jj[u]];
-    }
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u)
-#pragma unroll
-      for (int d = 0; d < 3; ++d) m[u][d] = pbar[3 * pid[u] + d] * k;
-    // pin the loads above the per-particle branches (see the forward paint)
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u)
-      asm volatile("" : "+v"(px[u][0]), "+v"(px[u][1]), "+v"(px[u][2]), "+v"(m[u][0]), "+v"(m[u][1]), "+v"(m[u][2]));
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      if (base + threadIdx.x + u * kThreads >= total) continue;
-      int ix, iy, iz;
-      float fx, fy, fz;
-      cic_base(px[u][0], n, ix, fx);
-      cic_base(px[u][1], n, iy, fy);
-      cic_base(px[u][2], n, iz, fz);
-      int lx = (ix - ox) & (n - 1), ly = (iy - oy) & (n - 1), lz = (iz - oz) & (n - 1);
-      if (lx > TX) lx -= n;
-      if (ly > TY) ly -= n;
-      if (lz > TZ) lz -= n;
-      const float wx[2] = {1.f - fx, fx}, wy[2] = {1.f - fy, fy}, wz[2] = {1.f - fz, fz};
-#pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        const int cx = lx + a;
-        if (cx < 0 || cx >= TX) continue;
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          const int cy = ly + b;
-          if (cy < 0 || cy >= TY) continue;
-#pragma unroll
-          for (int c = 0; c < 2; ++c) {
-            const int cz = lz + c;
-            if (cz < 0 || cz >= TZ) continue;
-            const float w = wx[a] * wy[b] * wz[c];
-            const int li = tile_li(cx, cy, cz, g);
-            atomicAdd(&acc[0][li], w * m[u][0]);
-            atomicAdd(&acc[1][li], w * m[u][1]);
-            atomicAdd(&acc[2][li], w * m[u][2]);
-          }
-        }
-      }
-    }
-  }
-  __syncthreads();
-  for (int c = threadIdx.x; c < store_walk_len(g); c += kThreads) {
-    int cx, cy, cz;
-    store_walk(c, g, cx, cy, cz);
-    if (cx >= TX) continue;
-    const long gi = blk_real(ox + cx, oy + cy, oz + cz, n);
-    const int li = tile_li(cx, cy, cz, g);
-    o0[gi] = acc[0][li];
-    o1[gi] = acc[1][li];
-    o2[gi] = acc[2][li];
-  }
-}
 
 // x_bar[id] += sum_corners dW/dx * V(c), one sorted particle per thread:
 //   NCH = 3: V(c) = k pbar[id] . F(c) with F the interleaved force mesh
@@ -211,11 +122,6 @@ inline int grid_for(long n) {
 }
 
 }  // namespace
-
-void launch_paint3w(const float* pos, const uint32_t* id, const uint32_t* off, const TileGeom& g, const float* pbar,
-                    float k, float* o0, float* o1, float* o2, hipStream_t s) {
-  hipLaunchKernelGGL(k_paint3w, dim3(g.ntiles), dim3(kThreads), 0, s, pos, id, off, g, pbar, k, o0, o1, o2);
-}
 
 void launch_readout_grad3(const float* pos, const uint32_t* id, long np, int n, const float* fi, const float* pbar,
                           float k, float* xbar, hipStream_t s) {

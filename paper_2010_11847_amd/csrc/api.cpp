@@ -63,6 +63,7 @@ struct Layout {
   size_t key = 0, rank = 0;
   size_t count = 0, off = 0, bsum = 0;
   size_t pw_partial = 0, pw_out = 0;
+  size_t misc = 0;   // small device words (the adjoint paint's max |weight|)
   size_t lat0 = 0;   // LPT lattice fields alias the mesh + particle region
   size_t total = 0;
   long n_keys = 0, cap = 0;
@@ -126,6 +127,7 @@ Layout make_layout(const pm_config* c) {
   L.bsum = take((size_t)(pmk::scan_scratch_words(L.n_keys) + 1) * 4);
   L.pw_partial = take((size_t)pmk::power_partial_doubles(L.n_bins_max) * 8);
   L.pw_out = take((size_t)3 * L.n_bins_max * 8);
+  L.misc = take(256);
   const size_t region = o;
   for (int i = 0; i < 3; ++i) L.mesh[i] = take(field_bytes(ng));
   L.force_i = take((size_t)ng * ng * ng * 12);
@@ -192,12 +194,12 @@ void build_fft_tables(long n, double rs, std::vector<char>& host, size_t base_of
 
 // Kernel classes timed by the optional event profiler.
 enum ProfCls : int {
-  PC_FILL, PC_KEYS, PC_SCAN, PC_SCATTER, PC_PAINT, PC_FFT_R2C_Z, PC_FFT_Y_FWD, PC_FFT_X_FUSED, PC_FFT_Y_INV,
-  PC_FFT_C2R_Z, PC_READOUT, PC_NCLS
+  PC_FILL, PC_KEYS, PC_SCAN, PC_SCATTER, PC_PAINT, PC_FFT_R2C_Z, PC_FFT_Y_FWD, PC_FFT_X_SCALE, PC_FFT_X_INV0,
+  PC_FFT_X_INV1, PC_FFT_Y_INV, PC_FFT_C2R_Z, PC_READOUT, PC_NCLS
 };
-const char* const kProfNames[PC_NCLS] = {"fill",        "keys",        "scan",         "scatter",
-                                         "paint",       "fft_z_r2c",   "fft_y_fwd",    "fft_x_fused",
-                                         "fft_y_inv",   "fft_z_c2r",   "readout_kdk"};
+const char* const kProfNames[PC_NCLS] = {"fill",        "keys",       "scan",       "scatter",   "paint",
+                                         "fft_z_r2c",   "fft_y_fwd",  "fft_x_scale", "fft_x_inv0", "fft_x_inv1",
+                                         "fft_y_inv",   "fft_z_c2r",  "readout_kdk"};
 
 struct Profiler {
   bool on = false;
@@ -217,7 +219,7 @@ struct Profiler {
     return pool[used++];
   }
   ~Profiler() {
-    for (auto e : pool) hipEventDestroy(e);
+    for (auto e : pool) (void)hipEventDestroy(e);   // teardown: nothing to report to
   }
 };
 
@@ -236,7 +238,8 @@ struct pm_ctx {
   pmk::TileGeom tg;
   FftTables tm, tl;
   Field mesh[3];
-  float* force_i = nullptr;   // interleaved force mesh [n^3][3]
+  float* force_i = nullptr;   // interleaved force mesh, x-blocked [n/8][n][n][8][3]
+  uint32_t* misc = nullptr;   // small device words
   float* pos_s[2] = {};
   float* mom_s[2] = {};
   uint32_t* id_s[2] = {};
@@ -265,10 +268,11 @@ struct pm_ctx {
       f();
       return;
     }
-    hipEventRecord(a, stream);
+    // a pair whose record failed is dropped (the work itself still runs)
+    const bool ok_a = hipEventRecord(a, stream) == hipSuccess;
     f();
-    hipEventRecord(b, stream);
-    prof.recs.push_back({cls, a, b});
+    const bool ok_b = hipEventRecord(b, stream) == hipSuccess;
+    if (ok_a && ok_b) prof.recs.push_back({cls, a, b});
   }
 
   int fail(int code, const std::string& m) {
@@ -330,7 +334,9 @@ struct pm_ctx {
       op.out_c[i] = mesh[i].c();
       op.out_q[i] = mesh[i].q;
     }
-    timed(PC_FFT_X_FUSED, [&] { pmk::fft_x_fused(tm, mesh[0], op, stream); });
+    timed(PC_FFT_X_SCALE, [&] { pmk::fft_x_force(tm, mesh[0], op, -1, stream); });
+    timed(PC_FFT_X_INV0, [&] { pmk::fft_x_force(tm, mesh[0], op, 0, stream); });
+    timed(PC_FFT_X_INV1, [&] { pmk::fft_x_force(tm, mesh[0], op, 1, stream); });
     timed(PC_FFT_Y_INV, [&] { pmk::fft_y(tm, mesh, 3, 1, stream); });
     timed(PC_FFT_C2R_Z, [&] { pmk::fft_z_c2r_interleaved3(tm, mesh, force_i, stream); });
   }
@@ -414,6 +420,7 @@ int pm_create(const pm_config* cfg, void* d_workspace, size_t bytes, void* strea
     return PM_EINVAL;
   }
   c->force_i = reinterpret_cast<float*>(w + L.force_i);
+  c->misc = reinterpret_cast<uint32_t*>(w + L.misc);
   for (int i = 0; i < 2; ++i) {
     c->pos_s[i] = reinterpret_cast<float*>(w + L.pos_s[i]);
     c->mom_s[i] = reinterpret_cast<float*>(w + L.mom_s[i]);
@@ -724,8 +731,10 @@ int pm_run_adjoint(pm_ctx* ctx, const double* h_a, int n_a, const float* d_ckpt,
       // term A: positions at which the force meshes are read out
       pmk::launch_readout_grad3(c.pos_s[0], c.id_s[0], np, c.ng, c.force_i, pbar, (float)kj, xbar, c.stream);
       // term B: positions that paint the density, through G^T
-      pmk::launch_paint3w(c.pos_s[0], c.id_s[0], c.off, c.tg, pbar, (float)kj, c.mesh[0].r, c.mesh[1].r,
-                          c.mesh[2].r, c.stream);
+      pmk::launch_absmax(pbar, 3 * np, c.misc, c.stream);
+      for (int d = 0; d < 3; ++d)
+        pmk::launch_paint_weighted(c.pos_s[0], c.id_s[0], c.off, c.tg, pbar, d, (float)kj, c.misc, c.mesh[d].r,
+                                   c.stream);
       pmk::fft_r2c_zy(c.tm, c.mesh, 3, c.stream);
       pmk::SpecOp op;
       op.kind = pmk::OP_FORCE_T;

@@ -578,7 +578,7 @@ __device__ __forceinline__ float2 coef_of(const Term& tm, float dy, float dz) {
 template <int N>
 __device__ __forceinline__ float common_factor(const SpecOp& op, const FftTables& t, int kx, int ky, int kz) {
   const float kk = t.kxy[kx] + t.kxy[ky] + t.kz[kz];
-  const float inv = kk > 0.f ? 1.f / kk : 0.f;
+  const float inv = kk > 0.f ? __builtin_amdgcn_rcpf(kk) : 0.f;   // <= 1 ulp
   auto pk = [&]() {
     const int fx = sfreq<N>(kx), fy = sfreq<N>(ky);
     return op.pk[fx * fx + fy * fy + kz * kz];
@@ -593,7 +593,7 @@ __device__ __forceinline__ float common_factor(const SpecOp& op, const FftTables
       float g = op.scale * inv;
       if (op.deconv) {
         const float w = t.wxy[kx] * t.wxy[ky] * t.wz[kz];
-        g /= (op.deconv == 1 ? w : w * w);
+        g *= __builtin_amdgcn_rcpf(op.deconv == 1 ? w : w * w);
       }
       if (op.split) {
         const float sv = t.sxy[kx] * t.sxy[ky] * t.sz[kz];
@@ -971,10 +971,12 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_op(FusedArgs a) {
 #pragma unroll
           for (int l2 = 0; l2 < R2; ++l2) asm volatile("" : "+v"(fac[l2]));
           const float kyz = t.kxy[ky] + t.kz[kz];
+          // hardware reciprocal (<= 1 ulp): an IEEE divide per element
+          // costs about ten instructions
 #pragma unroll
           for (int l2 = 0; l2 < R2; ++l2) {
             const float kk = fac[l2] + kyz;
-            fac[l2] = kk > 0.f ? op.scale / kk : 0.f;
+            fac[l2] = kk > 0.f ? op.scale * __builtin_amdgcn_rcpf(kk) : 0.f;
           }
           if (op.deconv) {
             const float wyz = t.wxy[ky] * t.wz[kz];
@@ -983,7 +985,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_op(FusedArgs a) {
 #pragma unroll
             for (int l2 = 0; l2 < R2; ++l2) {
               const float wv = aux[l2] * wyz;
-              fac[l2] /= (op.deconv == 1 ? wv : wv * wv);
+              fac[l2] *= __builtin_amdgcn_rcpf(op.deconv == 1 ? wv : wv * wv);
             }
           }
           if (op.split) {
@@ -1146,6 +1148,39 @@ void xfused(const FftTables& t, const Field& in, const SpecOp& op, hipStream_t s
   }
 }
 
+// One stage of the force's x pass (OP_FORCE): stage -1 is the forward
+// transform times c(k) in place, stage p >= 0 the inverse of basis power p.
+// Meshes of N <= 32 run the whole pass in one fused launch at stage -1.
+template <int N>
+void xforce(const FftTables& t, const Field& in, const SpecOp& op, int stage, hipStream_t s) {
+  constexpr int M = Cols<N>::M;
+  if constexpr (Split<N>::R2 == 1) {
+    if (stage < 0) xfused<N>(t, in, op, s);
+  } else {
+    FusedArgs a;
+    a.op = op;
+    a.t = t;
+    a.in_main = in.c();
+    a.in_nyq = in.q;
+    a.gm = ColGeom{4L * N, 4L * N * N, N / 2, cdiv(N / 2, M)};
+    a.gp = ColGeom{0, 8L * N, N, cdiv(N, M)};
+    a.nb_main = N * a.gm.ntc;
+    a.first = a.last = 1;
+    a.park_main = nullptr;
+    a.park_nyq = nullptr;
+    const dim3 grid(a.nb_main + a.gp.ntc);
+    if (stage < 0) {
+      a.pbasis = 0;
+      a.op.out_c[0] = in.c();
+      a.op.out_q[0] = in.q;
+      hipLaunchKernelGGL((k_fft_x_op<N, M, XOP_SCALE>), grid, dim3(kThreads), 0, s, a);
+    } else {
+      a.pbasis = stage;
+      hipLaunchKernelGGL((k_fft_x_op<N, M, XOP_OUT>), grid, dim3(kThreads), 0, s, a);
+    }
+  }
+}
+
 // chunks of at most 3 fields per launch (blockIdx.y selects the field)
 template <class Fn>
 void by3(Field* f, int nf, Fn fn) {
@@ -1217,6 +1252,12 @@ void fft_x_inverse(const FftTables& t, Field* f, int nf, hipStream_t s) {
 
 void fft_x_fused(const FftTables& t, const Field& in, const SpecOp& op, hipStream_t s) {
 #define CALL(N) xfused<N>(t, in, op, s)
+  PM_FFT_SWITCH(t.n, CALL)
+#undef CALL
+}
+
+void fft_x_force(const FftTables& t, const Field& in, const SpecOp& op, int stage, hipStream_t s) {
+#define CALL(N) xforce<N>(t, in, op, stage, s)
   PM_FFT_SWITCH(t.n, CALL)
 #undef CALL
 }

@@ -106,14 +106,18 @@ void launch_scatter(const ScatterArgs& a, hipStream_t s);
 void launch_paint(const float* pos_sorted, const uint32_t* off, const TileGeom& g, float* out, float scale,
                   float offset, bool std_layout, hipStream_t s);
 void launch_readout(const ReadoutArgs& a, hipStream_t s);
+// *bits = bit pattern of max_i |v_i| over n floats
+void launch_absmax(const float* v, long n, uint32_t* bits, hipStream_t s);
+// x-blocked paint of signed masses wts[3 id + comp] * k (the adjoint's
+// cotangent channels); *maxbits must hold max |wts| (launch_absmax)
+void launch_paint_weighted(const float* pos_sorted, const uint32_t* id_sorted, const uint32_t* off, const TileGeom& g,
+                           const float* wts, int comp, float k, const uint32_t* maxbits, float* out, hipStream_t s);
 void launch_kick_drift(float* pos, float* mom, const float* f, long np, float kick, float drift, float nmesh,
                        hipStream_t s);
 void launch_spec_to_numpy(const float2* c, const float2* q, float2* out, int n, float scale, hipStream_t s);
 void launch_spec_from_numpy(const float2* in, float2* c, float2* q, int n, float scale, hipStream_t s);
 void launch_scale(float* p, long n, float v, hipStream_t s);
 // adjoint kernels (adjoint.hip)
-void launch_paint3w(const float* pos, const uint32_t* id, const uint32_t* off, const TileGeom& g, const float* pbar,
-                    float k, float* o0, float* o1, float* o2, hipStream_t s);
 void launch_readout_grad3(const float* pos, const uint32_t* id, long np, int n, const float* fi, const float* pbar,
                           float k, float* xbar, hipStream_t s);
 // m0: real mesh, x-blocked (std_layout: plain [x][y][z])

@@ -190,14 +190,28 @@ __global__ void k_scatter(ScatterArgs a) {
 // contiguous runs of the x-blocked mesh.  STD writes the plain [x][y][z]
 // layout instead (caller-visible meshes).
 //
-// The tile accumulates in 64-bit fixed point, weight * 2^31 per deposit
-// (ds_add_u64): LDS float atomics run about 25x slower than integer ones on
-// gfx950 (measured), and integer sums are exact and independent of the
-// order of the deposits, so the painted mesh is bitwise deterministic.  A
-// deposit is exact to 2^-31; 2^33 unit deposits fit in one cell.
-template <bool STD>
+// The tile accumulates in 64-bit fixed point (ds_add_u64): LDS float atomics
+// run about 25x slower than integer ones on gfx950 (measured), and integer
+// sums are exact and independent of the order of the deposits, so the
+// painted mesh is bitwise deterministic.
+//  - unit masses: weight * 2^31 per deposit, exact to 2^-31; 2^33 unit
+//    deposits fit in one cell;
+//  - WT (signed per-particle masses m_p = wts[3 id_p + comp] * k, the
+//    adjoint's cotangent channels): the float value w m_p S per deposit,
+//    with S = 2^(40 - e) and 2^e > max |m_p| (from *maxbits), so every
+//    |deposit| < 2^40 is an integer held exactly and 2^23 of them fit.
+struct PaintWeights {
+  const uint32_t* id = nullptr;     // sorted particle ids
+  const float* wts = nullptr;       // [np][3] in particle-id order
+  int comp = 0;
+  float k = 1.f;
+  const uint32_t* maxbits = nullptr;   // bits of max |wts| (non-negative float)
+};
+
+template <bool STD, bool WT>
 __global__ __launch_bounds__(kThreads) void k_paint(const float* __restrict__ pos, const uint32_t* __restrict__ off,
-                                                    TileGeom g, float* __restrict__ out, float scale, float offset) {
+                                                    TileGeom g, float* __restrict__ out, float scale, float offset,
+                                                    PaintWeights pw) {
   __shared__ unsigned long long acc[kTileCells];
   __shared__ RangeTable rt;
   const int TX = g.tx, TY = g.ty, TZ = g.tz, n = g.n;
@@ -206,6 +220,15 @@ __global__ __launch_bounds__(kThreads) void k_paint(const float* __restrict__ po
   tile_coords(tile, g, tx, ty, tz);
   const int ox = tx * TX, oy = ty * TY, oz = tz * TZ;
   for (int c = threadIdx.x; c < tile_cells(g); c += kThreads) acc[c] = 0ull;
+  float S = 1.f;   // WT: fixed-point scale, a power of two
+  if (WT) {
+    const float mx = __uint_as_float(*pw.maxbits) * fabsf(pw.k);
+    if (mx > 0.f && mx < INFINITY) {
+      int e;
+      frexpf(mx, &e);   // mx < 2^e
+      S = ldexpf(1.f, 40 - e);
+    }
+  }
   build_ranges(rt, off, tx, ty, tz, g);
   const uint32_t total = rt.pre[27];
   constexpr int kBatch = 8;   // particles whose loads are in flight together
@@ -224,10 +247,22 @@ __global__ __launch_bounds__(kThreads) void k_paint(const float* __restrict__ po
     for (int u = 0; u < kBatch; ++u)
 #pragma unroll
       for (int d = 0; d < 3; ++d) px[u][d] = pos[3 * (long)jj[u] + d];
+    float mp[kBatch];
+    if (WT) {
+      uint32_t pid[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) pid[u] = pw.id[jj[u]];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) mp[u] = pw.wts[3 * (long)pid[u] + pw.comp] * pw.k;
+    }
     // pin the loads here: each particle's use sits in its own branch, and
     // sunk into those branches the loads would run one round trip at a time
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) asm volatile("" : "+v"(px[u][0]), "+v"(px[u][1]), "+v"(px[u][2]));
+    if (WT) {
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) asm volatile("" : "+v"(mp[u]));
+    }
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
     if (base + threadIdx.x + u * kThreads >= total) continue;
@@ -255,9 +290,14 @@ __global__ __launch_bounds__(kThreads) void k_paint(const float* __restrict__ po
         for (int c = 0; c < 2; ++c) {
           const int cz = lz + c;
           if (cz < 0 || cz >= TZ) continue;
-          // w <= 1, so w * 2^31 <= 2^31 fits in 32 bits
-          const uint32_t q = (uint32_t)(wxy * wz[c] * 2147483648.0f);
-          atomicAdd(&acc[tile_li(cx, cy, cz, g)], (unsigned long long)q);
+          unsigned long long q;
+          if (WT) {
+            q = (unsigned long long)__float2ll_rn(wxy * wz[c] * mp[u] * S);
+          } else {
+            // w <= 1, so w * 2^31 <= 2^31 fits in 32 bits
+            q = (unsigned long long)(uint32_t)(wxy * wz[c] * 2147483648.0f);
+          }
+          atomicAdd(&acc[tile_li(cx, cy, cz, g)], q);
         }
       }
     }
@@ -269,7 +309,8 @@ __global__ __launch_bounds__(kThreads) void k_paint(const float* __restrict__ po
     store_walk(c, g, cx, cy, cz);
     if (cx >= TX) continue;
     const int x = ox + cx, y = oy + cy, z = oz + cz;
-    const double rho = (double)acc[tile_li(cx, cy, cz, g)] * 0x1p-31;
+    const unsigned long long v = acc[tile_li(cx, cy, cz, g)];
+    const double rho = WT ? (double)(long long)v / (double)S : (double)v * 0x1p-31;
     out[STD ? ((long)x * n + y) * n + z : blk_real(x, y, z, n)] = (float)(rho * (double)scale + (double)offset);
   }
 }
@@ -300,21 +341,25 @@ __device__ __forceinline__ uint32_t slot_key(int slot, int rx, int ry, int rz, c
   return ((((uint32_t)kx << g.lny | (uint32_t)ky) << g.lnz | (uint32_t)kz) << 3) | (uint32_t)cls;
 }
 
-// One tile-sorted particle per thread: CIC gather of the 8 corners from the
-// interleaved force mesh (one 12-byte load per corner; sorted neighbours
-// share cache lines), kicks, drift, wrap, and the tile key + rank of the new
-// position.  Ranks are counted per workgroup in LDS by slot (27 neighbour
-// tiles x 8 classes of the workgroup's first particle), then one global
-// atomic per used slot reserves the range.
+// Two tile-sorted particles per thread (a workgroup takes 512 consecutive
+// ones, thread t the t-th and (256+t)-th): CIC gather of the 8 corners of
+// each from the interleaved force mesh (one 12-byte load per corner; sorted
+// neighbours share cache lines), kicks, drift, wrap, and the tile key +
+// rank of the new position.  All loads of both particles are issued before
+// any is used (every lane computes, on a clamped index, and only the stores
+// are predicated).  Ranks are counted per workgroup in LDS by slot (27
+// neighbour tiles x 8 classes of the workgroup's first particle), then one
+// global atomic per used slot reserves the range.
+constexpr int kReadoutPPT = 2;
+
 __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
+  constexpr int PPT = kReadoutPPT;
   __shared__ uint32_t slot_cnt[216];
   __shared__ uint32_t slot_base[216];
   const TileGeom& g = a.g;
   const int n = g.n;
   const long chunk = xcd_tile(blockIdx.x, gridDim.x);
-  const long j0 = chunk * kThreads;
-  const long j = j0 + threadIdx.x;
-  const bool valid = j < a.np;
+  const long j0 = chunk * (long)(kThreads * PPT);
   const bool keys = (a.flags & RO_KEYS) != 0;
   int rx = 0, ry = 0, rz = 0;
   if (keys) {
@@ -329,86 +374,113 @@ __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
     rz = iz >> g.lz;
     __syncthreads();
   }
-  int slot = -1;
-  if (valid) {
-    const float nf = (float)n;
-    float x[3], p[3] = {0.f, 0.f, 0.f};
+  long jj[PPT];
+  bool valid[PPT];
+  float x[PPT][3], p[PPT][3];
+  uint32_t id[PPT];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) x[d] = a.pos[3 * j + d];
-    if (a.mom) {
+  for (int u = 0; u < PPT; ++u) {
+    jj[u] = j0 + threadIdx.x + u * kThreads;
+    valid[u] = jj[u] < a.np;
+    const long jc = valid[u] ? jj[u] : a.np - 1;
 #pragma unroll
-      for (int d = 0; d < 3; ++d) p[d] = a.mom[3 * j + d];
+    for (int d = 0; d < 3; ++d) {
+      x[u][d] = a.pos[3 * jc + d];
+      p[u][d] = a.mom ? a.mom[3 * jc + d] : 0.f;
     }
+    id[u] = a.id ? a.id[jc] : (uint32_t)jc;
+  }
+  // all 8 x PPT corner loads first, pinned, then the weighted sums
+  float cv[PPT][8][3], wgt[PPT][8];
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) {
     int ix, iy, iz;
     float fx, fy, fz;
-    cic_base(x[0], n, ix, fx);
-    cic_base(x[1], n, iy, fy);
-    cic_base(x[2], n, iz, fz);
+    cic_base(x[u][0], n, ix, fx);
+    cic_base(x[u][1], n, iy, fy);
+    cic_base(x[u][2], n, iz, fz);
     const int jx = (ix + 1) & (n - 1), jy = (iy + 1) & (n - 1), jz = (iz + 1) & (n - 1);
     // corner (x, y, z) at fi + 3 * blk_real(x, y, z): x and x+1 of one block
     // are adjacent 12-byte cells
     const int xs[2] = {ix, jx}, ys[2] = {iy, jy}, zs[2] = {iz, jz};
     const float wx[2] = {1.f - fx, fx}, wy[2] = {1.f - fy, fy}, wz[2] = {1.f - fz, fz};
-    float F[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int c8 = 0; c8 < 8; ++c8) {
+      const int e = c8 & 1, b = (c8 >> 1) & 1, c = c8 >> 2;
+      const float* cp = a.fi + 3 * blk_real(xs[e], ys[b], zs[c], n);
 #pragma unroll
-      for (int c = 0; c < 2; ++c)
+      for (int d = 0; d < 3; ++d) cv[u][c8][d] = cp[d];
+      wgt[u][c8] = wx[e] * wy[b] * wz[c];
+    }
+  }
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          const float* cp = a.fi + 3 * blk_real(xs[e], ys[b], zs[c], n);
-          const float w = wx[e] * wy[b] * wz[c];
+  for (int u = 0; u < PPT; ++u)
 #pragma unroll
-          for (int d = 0; d < 3; ++d) F[d] += w * cp[d];
-        }
-    const uint32_t id = a.id ? a.id[j] : (uint32_t)j;
+    for (int c8 = 0; c8 < 8; ++c8) asm volatile("" : "+v"(cv[u][c8][0]), "+v"(cv[u][c8][1]), "+v"(cv[u][c8][2]));
+  float F[PPT][3];
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) F[u][d] = 0.f;
+#pragma unroll
+    for (int c8 = 0; c8 < 8; ++c8)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) F[u][d] += wgt[u][c8] * cv[u][c8][d];
+  }
+  const float nf = (float)n;
+  int slot[PPT];
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) {
+    slot[u] = -1;
+    if (!valid[u]) continue;
+    const long j = jj[u];
     if (a.flags & RO_FORCE_BYID) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) a.force_out[3 * (long)id + d] = F[d];
+      for (int d = 0; d < 3; ++d) a.force_out[3 * (long)id[u] + d] = F[u][d];
     }
     if (a.flags & RO_KICK) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) p[d] += F[d] * a.kick_a;
+      for (int d = 0; d < 3; ++d) p[u][d] += F[u][d] * a.kick_a;
     }
     if (a.flags & RO_CKPT) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        a.ckpt_x[3 * (long)id + d] = x[d];
-        a.ckpt_p[3 * (long)id + d] = p[d];
+        a.ckpt_x[3 * (long)id[u] + d] = x[u][d];
+        a.ckpt_p[3 * (long)id[u] + d] = p[u][d];
       }
     }
     if (a.flags & RO_KICK) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) p[d] += F[d] * a.kick_b;
+      for (int d = 0; d < 3; ++d) p[u][d] += F[u][d] * a.kick_b;
     }
     if (a.flags & RO_DRIFT) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) x[d] = wrap_pos(x[d] + p[d] * a.drift, nf);
+      for (int d = 0; d < 3; ++d) x[u][d] = wrap_pos(x[u][d] + p[u][d] * a.drift, nf);
     }
     if (a.flags & RO_WRITE_SORTED) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        a.pos[3 * j + d] = x[d];
-        if (a.mom) a.mom[3 * j + d] = p[d];
+        a.pos[3 * j + d] = x[u][d];
+        if (a.mom) a.mom[3 * j + d] = p[u][d];
       }
     }
     if (a.flags & RO_XP_BYID) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        a.pos_out[3 * (long)id + d] = x[d];
-        a.mom_out[3 * (long)id + d] = p[d];
+        a.pos_out[3 * (long)id[u] + d] = x[u][d];
+        a.mom_out[3 * (long)id[u] + d] = p[u][d];
       }
     }
     if (keys) {
       int kx, ky, kz;
       float t;
-      cic_base(x[0], n, kx, t);
-      cic_base(x[1], n, ky, t);
-      cic_base(x[2], n, kz, t);
+      cic_base(x[u][0], n, kx, t);
+      cic_base(x[u][1], n, ky, t);
+      cic_base(x[u][2], n, kz, t);
       const uint32_t key = tile_key(kx, ky, kz, g);
-      slot = key_slot(key, rx, ry, rz, g);
+      slot[u] = key_slot(key, rx, ry, rz, g);
       a.key_out[j] = key;
-      a.rank_out[j] = slot >= 0 ? atomicAdd(&slot_cnt[slot], 1u) : atomicAdd(&a.count[key], 1u);
+      a.rank_out[j] = slot[u] >= 0 ? atomicAdd(&slot_cnt[slot[u]], 1u) : atomicAdd(&a.count[key], 1u);
     }
   }
   if (!keys) return;
@@ -418,7 +490,9 @@ __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
     slot_base[i] = c ? atomicAdd(&a.count[slot_key(i, rx, ry, rz, g)], c) : 0u;
   }
   __syncthreads();
-  if (valid && slot >= 0) a.rank_out[j] += slot_base[slot];
+#pragma unroll
+  for (int u = 0; u < PPT; ++u)
+    if (valid[u] && slot[u] >= 0) a.rank_out[jj[u]] += slot_base[slot[u]];
 }
 
 // elementwise kick + drift with a given per-particle force (first half of a
@@ -520,6 +594,16 @@ __global__ void k_spec_pack(const float2* __restrict__ c, const float2* __restri
   }
 }
 
+// bits of max_i |v_i| (non-negative floats order like their bit patterns);
+// NaNs are ignored by fmaxf
+__global__ __launch_bounds__(kThreads) void k_absmax(const float* __restrict__ v, long n, uint32_t* __restrict__ bits) {
+  float m = 0.f;
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) m = fmaxf(m, fabsf(v[i]));
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(bits, __float_as_uint(m));
+}
+
 // plain [x][y][z] <-> x-blocked real mesh (caller-visible buffers); the
 // output index runs over threads so that the stores are contiguous
 __global__ void k_relayout(const float* __restrict__ in, float* __restrict__ out, int ln, int to_blocked) {
@@ -601,15 +685,35 @@ void launch_scatter(const ScatterArgs& a, hipStream_t s) {
 
 void launch_paint(const float* pos_sorted, const uint32_t* off, const TileGeom& g, float* out, float scale,
                   float offset, bool std_layout, hipStream_t s) {
+  const PaintWeights pw;
   if (std_layout)
-    hipLaunchKernelGGL(k_paint<true>, dim3(g.ntiles), dim3(kThreads), 0, s, pos_sorted, off, g, out, scale, offset);
+    hipLaunchKernelGGL((k_paint<true, false>), dim3(g.ntiles), dim3(kThreads), 0, s, pos_sorted, off, g, out, scale,
+                       offset, pw);
   else
-    hipLaunchKernelGGL(k_paint<false>, dim3(g.ntiles), dim3(kThreads), 0, s, pos_sorted, off, g, out, scale,
-                       offset);
+    hipLaunchKernelGGL((k_paint<false, false>), dim3(g.ntiles), dim3(kThreads), 0, s, pos_sorted, off, g, out,
+                       scale, offset, pw);
+}
+
+void launch_absmax(const float* v, long n, uint32_t* bits, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kThreads), 0, s, bits, 1L, 0u);
+  hipLaunchKernelGGL(k_absmax, dim3(grid_for(n, kThreads, 4096)), dim3(kThreads), 0, s, v, n, bits);
+}
+
+void launch_paint_weighted(const float* pos_sorted, const uint32_t* id_sorted, const uint32_t* off, const TileGeom& g,
+                           const float* wts, int comp, float k, const uint32_t* maxbits, float* out, hipStream_t s) {
+  PaintWeights pw;
+  pw.id = id_sorted;
+  pw.wts = wts;
+  pw.comp = comp;
+  pw.k = k;
+  pw.maxbits = maxbits;
+  hipLaunchKernelGGL((k_paint<false, true>), dim3(g.ntiles), dim3(kThreads), 0, s, pos_sorted, off, g, out, 1.f,
+                     0.f, pw);
 }
 
 void launch_readout(const ReadoutArgs& a, hipStream_t s) {
-  const int grid = (int)((a.np + kThreads - 1) / kThreads);
+  const long per = (long)kThreads * kReadoutPPT;
+  const int grid = (int)((a.np + per - 1) / per);
   hipLaunchKernelGGL(k_readout, dim3(grid), dim3(kThreads), 0, s, a);
 }
 

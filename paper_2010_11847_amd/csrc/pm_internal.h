@@ -87,6 +87,12 @@ void fft_x_forward(const FftTables& t, Field* f, int nf, hipStream_t s);
 // Fused x pass: forward x transform of `in`, spectral op, inverse x
 // transforms written to op.out_*.  `in` may alias out[0].
 void fft_x_fused(const FftTables& t, const Field& in, const SpecOp& op, hipStream_t s);
+// The force's x pass (op.kind == OP_FORCE) one stage at a time: stage -1
+// transforms `in` forward and multiplies by the Green's function in place;
+// stage p (0, 1) inverse transforms D(w_x)^p times it into the outputs of
+// power p (p = 0: y and z components, p = 1: x, which may alias `in`, so
+// stage 1 runs last).  fft_x_fused(OP_FORCE) runs the three in order.
+void fft_x_force(const FftTables& t, const Field& in, const SpecOp& op, int stage, hipStream_t s);
 // Single passes (the composites above call these).
 void fft_z_r2c(const FftTables& t, Field* f, int nf, hipStream_t s);
 void fft_y(const FftTables& t, Field* f, int nf, int dir, hipStream_t s);
