@@ -341,16 +341,17 @@ __device__ __forceinline__ uint32_t slot_key(int slot, int rx, int ry, int rz, c
   return ((((uint32_t)kx << g.lny | (uint32_t)ky) << g.lnz | (uint32_t)kz) << 3) | (uint32_t)cls;
 }
 
-// Two tile-sorted particles per thread (a workgroup takes 512 consecutive
-// ones, thread t the t-th and (256+t)-th): CIC gather of the 8 corners of
-// each from the interleaved force mesh (one 12-byte load per corner; sorted
-// neighbours share cache lines), kicks, drift, wrap, and the tile key +
-// rank of the new position.  All loads of both particles are issued before
-// any is used (every lane computes, on a clamped index, and only the stores
-// are predicated).  Ranks are counted per workgroup in LDS by slot (27
-// neighbour tiles x 8 classes of the workgroup's first particle), then one
-// global atomic per used slot reserves the range.
-constexpr int kReadoutPPT = 2;
+// One tile-sorted particle per thread: CIC gather of the 8 corners from the
+// interleaved force mesh (one 12-byte load per corner; sorted neighbours
+// share cache lines), kicks, drift, wrap, and the tile key + rank of the
+// new position.  All loads are issued before any is used (every lane
+// computes, on a clamped index, and only the stores are predicated).  Ranks
+// are counted per workgroup in LDS by slot (27 neighbour tiles x 8 classes
+// of the workgroup's first particle), then one global atomic per used slot
+// reserves the range.  (Two particles per thread measured slower: a
+// 512-particle workgroup spans more tiles in voids, and particles outside
+// the 27-tile neighbourhood take a global atomic each.)
+constexpr int kReadoutPPT = 1;
 
 __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
   constexpr int PPT = kReadoutPPT;
