@@ -87,12 +87,12 @@ def measured_traffic(workload, kernel_class):
 def cpu_baseline(seconds_hint=20.0):
     """The oracle (FP64 NumPy, unmodified) on a bounded sample: the same
     recipe (B = 2, 1 Mpc/h cells, no-wiggle P(k), 2LPT at a = 0.1) at
-    128^3 particles on a 256^3 mesh, 2 KDK steps; reported in
-    particle-steps/s."""
+    128^3 particles on a 256^3 mesh, 8 KDK steps (10-20 s on 16 host
+    threads); reported in particle-steps/s."""
     import numpy as np
     from oracle import lpt, pm
     from paper_2010_11847_amd import inputs
-    w = inputs.scaled(inputs.LARGE, 256, 128, n_steps=2)
+    w = inputs.scaled(inputs.LARGE, 256, 128, n_steps=8)
     x, p = lpt.generate(w)
     t0 = time.perf_counter()
     pm.kdk_run(x, p, w.a_list, w.n_mesh, w.n_particles, w.cosmo.omega_m)
