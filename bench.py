@@ -104,6 +104,47 @@ def cpu_baseline(seconds_hint=20.0):
                       f"{dt:.1f} s wall; DFTs on {pm._WORKERS} threads (scipy.fft), paint/readout 1 thread"}
 
 
+def adjoint_section(names=("adj128_mesh256_box400", "pm512_mesh1024_box1024"), reps=2):
+    """Forward run with per-step checkpoints plus the reverse sweep (gradient
+    of a loss on the final overdensity with respect to the white noise),
+    timed with HIP events; one untimed warm-up each."""
+    import torch
+    from paper_2010_11847_amd import inputs
+    from paper_2010_11847_amd.binding import PMContext
+    out = {}
+    for name in names:
+        w = inputs.PRESETS[name]
+        c = PMContext(w)
+        n, m = w.n_part, w.n_mesh
+        g = torch.Generator(device="cuda").manual_seed(w.seed + 2000)
+        noise = torch.randn((n, n, n), device="cuda", generator=g)
+        gd = torch.randn((m, m, m), device="cuda", generator=g)
+        ckpt = torch.empty((len(w.a_list), 2, c.np3, 3), device="cuda")
+        delta = torch.empty((m, m, m), device="cuda")
+
+        def once():
+            pos, mom = c.pm_init_lpt(0, w.a_list[0], noise=noise)
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            e0.record()
+            c.pm_run(w.a_list, pos, mom, ckpt=ckpt, delta_final=delta)
+            e1.record()
+            c.pm_run_adjoint(w.a_list, ckpt, noise=noise, grad_delta=gd)
+            e2.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1), e1.elapsed_time(e2)
+
+        once()
+        fw, bw = zip(*[once() for _ in range(reps)])
+        f, b = min(fw), min(bw)
+        out[name] = {"n_part": n, "n_mesh": m, "steps": w.n_steps, "forward_ckpt_ms": round(f, 2),
+                     "adjoint_ms": round(b, 2), "gradients_per_s": round(1e3 / (f + b), 3),
+                     "adjoint_over_forward": round(b / f, 2)}
+        print(f"[bench] adjoint {name} {out[name]}", file=sys.stderr, flush=True)
+        del c, noise, gd, ckpt, delta
+        torch.cuda.empty_cache()
+    return out
+
+
 def serving_section(n_requests, rate=20.0, seed=5, budget_gb=64.0, slots=4):
     """Continuous batching vs one-at-a-time on the same Poisson trace."""
     from paper_2010_11847_amd import serve
@@ -141,6 +182,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="skip the event-timed profile pass")
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device-to-device copy of GIB GiB (counter calibration) and exit")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient (adjoint) timing section")
     ap.add_argument("--serve", type=int, default=200,
                     help="requests of the serving trace (Poisson 20/s); 0 skips the serving section")
     args = ap.parse_args()
@@ -221,10 +263,11 @@ def main():
                     "bytes_per_launch": nbytes[dom], "avg_launch_ms": kernels[dom]["avg_ms"]}
         print(f"[bench] kernels {json.dumps(kernels)}", file=sys.stderr, flush=True)
 
+    del ctx, pos, mom, pos0, mom0
+    torch.cuda.empty_cache()
+    adjoint = None if args.no_adjoint else adjoint_section()
     serving = None
     if args.serve > 0:
-        del ctx, pos, mom, pos0, mom0
-        torch.cuda.empty_cache()
         serving = serving_section(args.serve)
 
     base = None
@@ -249,6 +292,7 @@ def main():
                    "pk": "eisenstein_hu_nowiggle", "init_lpt_ms": round(init_s * 1e3, 1)},
         "roofline": roofline,
         "cpu_baseline": base,
+        "adjoint": adjoint,
         "serving": serving,
         "kernels": kernels,
     }

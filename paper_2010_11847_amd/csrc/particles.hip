@@ -389,7 +389,8 @@ __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
       x[u][d] = a.pos[3 * jc + d];
       p[u][d] = a.mom ? a.mom[3 * jc + d] : 0.f;
     }
-    id[u] = a.id ? a.id[jc] : (uint32_t)jc;
+    // ids are needed only for writes by id (not on ordinary steps)
+    id[u] = (a.id && (a.flags & (RO_FORCE_BYID | RO_XP_BYID | RO_CKPT))) ? a.id[jc] : (uint32_t)jc;
   }
   // all 8 x PPT corner loads first, pinned, then the weighted sums
   float cv[PPT][8][3], wgt[PPT][8];
