@@ -31,6 +31,8 @@ def kernel_bytes(w, np3):
 
     Mesh field F = N^3 reals = N^2 (N/2) complex, plus the Nyquist plane of
     N^2 complex values.  Particle state 24 B (x, p), id 4 B, key+rank 8 B.
+    The x_inv0 and y_inv figures are those of meshes from 64^3 up, where F_y
+    and F_z share one inverse x transform.
     """
     n = w.n_mesh
     real = 4.0 * n ** 3
@@ -39,12 +41,12 @@ def kernel_bytes(w, np3):
         "fft_z_r2c": real + spec,                       # 1 field
         "fft_y_fwd": 2 * spec,                          # 1 field, in place
         "fft_x_scale": 2 * spec,                        # forward x times c(k), in place
-        "fft_x_inv0": spec + 2 * spec,                  # inverse x, basis D^0: F_y, F_z
+        "fft_x_inv0": 2 * spec,                         # inverse x, basis D^0: i g X shared by F_y, F_z
         "fft_x_inv1": 2 * spec,                         # inverse x, basis D^1: F_x
-        "fft_y_inv": 3 * 2 * spec,                      # 3 fields
+        "fft_y_inv": 2 * spec + 3 * spec,               # F_x and the shared factor in; F_x, F_y, F_z out
         "fft_z_c2r": 3 * (spec + real),                 # 3 fields
         "paint": 12.0 * np3 + real,                     # positions in, mesh out
-        "readout_kdk": 3 * real + np3 * (24 + 4 + 24 + 8),  # 3 meshes + x,p,id in; x,p,key,rank out
+        "readout_kdk": 3 * real + np3 * (24 + 24 + 8),  # 3 meshes + x,p in; x,p,key,rank out
         "scatter": np3 * (8 + 28 + 28),                 # key+rank, state in, state out
     }
 

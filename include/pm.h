@@ -116,6 +116,14 @@ const char* pm_last_error(const pm_ctx* ctx);
  * out[0..5] = D1, f1, D2, f2, E, G_f at scale factor a (D1(1) = 1). */
 int pm_growth(const pm_ctx* ctx, double a, double* h_out6);
 
+/* Time-step factors of n_a - 1 FastPM KDK steps over h_a[0] < ... < h_a[n_a-1]
+ * (section 2; kick and drift exact for the Zel'dovich growing mode):
+ * h_k1[i] opening kick a_i -> a_c, h_dr[i] drift a_i -> a_{i+1}, h_k2[i]
+ * closing kick a_c -> a_{i+1}, a_c = sqrt(a_i a_{i+1}).  Host arrays of
+ * n_a - 1 doubles each, owned by the caller.  PM_EINVAL for a NULL pointer,
+ * n_a < 2 or scale factors not positive and increasing. */
+int pm_kdk_factors(const pm_ctx* ctx, const double* h_a, int n_a, double* h_k1, double* h_dr, double* h_k2);
+
 /* Gen-IC step 1 (section 6): unit white noise on the n_part^3 lattice from the
  * counter-based generator (SplitMix64 output of seed*2^40 + site, Box-Muller,
  * cosine branch).  d_noise: [n_part^3] float32. */

@@ -42,6 +42,8 @@ _SIGS = {
     "pm_strerror": (C.c_char_p, [C.c_int]),
     "pm_last_error": (C.c_char_p, [C.c_void_p]),
     "pm_growth": (C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_double)]),
+    "pm_kdk_factors": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_double),
+                                 C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "pm_noise": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p]),
     "pm_init_lpt": (C.c_int, [C.c_void_p, C.c_uint64, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
                               C.c_void_p]),

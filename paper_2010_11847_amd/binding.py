@@ -100,6 +100,15 @@ class PMContext:
         self._check(self.lib.pm_growth(self.ctx, a, out), "pm_growth")
         return dict(zip(("D1", "f1", "D2", "f2", "E", "Gf"), list(out)))
 
+    def pm_kdk_factors(self, a_list: Sequence[float]):
+        """(k1, dr, k2) arrays of the KDK steps over a_list."""
+        a = np.ascontiguousarray(a_list, dtype=np.float64)
+        ns = max(len(a) - 1, 0)
+        k1, dr, k2 = (C.c_double * max(ns, 1))(), (C.c_double * max(ns, 1))(), (C.c_double * max(ns, 1))()
+        self._check(self.lib.pm_kdk_factors(self.ctx, a.ctypes.data_as(C.POINTER(C.c_double)), len(a), k1, dr, k2),
+                    "pm_kdk_factors")
+        return np.array(k1[:ns]), np.array(dr[:ns]), np.array(k2[:ns])
+
     def pm_noise(self, seed: int, out: Optional[torch.Tensor] = None):
         n = self.workload.n_part
         out = torch.empty((n, n, n), dtype=torch.float32, device=self.device) if out is None else out

@@ -325,19 +325,26 @@ struct pm_ctx {
     timed(PC_FFT_R2C_Z, [&] { pmk::fft_z_r2c(tm, &mesh[0], 1, stream); });
     timed(PC_FFT_Y_FWD, [&] { pmk::fft_y(tm, &mesh[0], 1, -1, stream); });
     pmk::SpecOp op;
-    op.kind = pmk::OP_FORCE;
-    op.n_out = 3;
     op.scale = (float)(1.5 * cfg.cosmo.omega_m / ((double)ng * ng * ng));
     op.deconv = cfg.deconv_order;
     op.split = cfg.split_mode;
-    for (int i = 0; i < 3; ++i) {
-      op.out_c[i] = mesh[i].c();
-      op.out_q[i] = mesh[i].q;
+    // from 64^3 up F_y and F_z share one x transform (i g X) and get their
+    // D(w_y), D(w_z) in the y pass; smaller meshes take the fused x pass
+    const bool xs = ng >= 64;
+    op.kind = xs ? pmk::OP_FORCE_XS : pmk::OP_FORCE;
+    op.n_out = xs ? 2 : 3;
+    const int dst[3] = {0, xs ? 2 : 1, 2};
+    for (int i = 0; i < op.n_out; ++i) {
+      op.out_c[i] = mesh[dst[i]].c();
+      op.out_q[i] = mesh[dst[i]].q;
     }
     timed(PC_FFT_X_SCALE, [&] { pmk::fft_x_force(tm, mesh[0], op, -1, stream); });
     timed(PC_FFT_X_INV0, [&] { pmk::fft_x_force(tm, mesh[0], op, 0, stream); });
     timed(PC_FFT_X_INV1, [&] { pmk::fft_x_force(tm, mesh[0], op, 1, stream); });
-    timed(PC_FFT_Y_INV, [&] { pmk::fft_y(tm, mesh, 3, 1, stream); });
+    if (xs)
+      timed(PC_FFT_Y_INV, [&] { pmk::fft_y_force(tm, mesh, stream); });
+    else
+      timed(PC_FFT_Y_INV, [&] { pmk::fft_y(tm, mesh, 3, 1, stream); });
     timed(PC_FFT_C2R_Z, [&] { pmk::fft_z_c2r_interleaved3(tm, mesh, force_i, stream); });
   }
   void readout(const pmk::ReadoutArgs& a) {
@@ -486,6 +493,14 @@ int pm_growth(const pm_ctx* ctx, double a, double* out6) {
   return PM_OK;
 }
 
+int pm_kdk_factors(const pm_ctx* ctx, const double* h_a, int n_a, double* h_k1, double* h_dr, double* h_k2) {
+  if (!ctx || !h_a || !h_k1 || !h_dr || !h_k2 || n_a < 2) return PM_EINVAL;
+  for (int i = 0; i < n_a; ++i)
+    if (!(h_a[i] > 0) || (i && !(h_a[i] > h_a[i - 1]))) return PM_EINVAL;
+  ctx->cosmo.kdk_factors(h_a, n_a, h_k1, h_dr, h_k2);
+  return PM_OK;
+}
+
 int pm_noise(pm_ctx* ctx, uint64_t seed, float* d_noise) {
   if (!ctx || !d_noise) return PM_EINVAL;
   pmk::launch_noise(seed, ctx->npart, d_noise, false, ctx->stream);
@@ -581,8 +596,9 @@ int pm_force(pm_ctx* ctx, const float* d_pos, int64_t np, float* d_force) {
 int pm_kdk_step(pm_ctx* ctx, float* d_pos, float* d_mom, float* d_force, double a0, double a1) {
   if (!ctx || !d_pos || !d_mom || !d_force || !(a0 > 0) || !(a1 > a0)) return PM_EINVAL;
   pm_ctx& c = *ctx;
-  const double ac = std::sqrt(a0 * a1);
-  const double k1 = c.cosmo.kick(a0, ac, a0), dr = c.cosmo.drift(a0, a1, ac), k2 = c.cosmo.kick(ac, a1, a1);
+  const double aa[2] = {a0, a1};
+  double k1, dr, k2;
+  c.cosmo.kdk_factors(aa, 2, &k1, &dr, &k2);
   pmk::launch_kick_drift(d_pos, d_mom, d_force, c.np3, (float)k1, (float)dr, (float)c.ng, c.stream);
   c.sort(d_pos, d_mom, nullptr, c.np3, 0);
   c.paint(0, c.np3, c.mesh[0].r);
@@ -609,12 +625,7 @@ int pm_run_begin(pm_ctx* ctx, const double* h_a, int n_a, float* d_pos, float* d
   r.k1.resize(r.ns);
   r.dr.resize(r.ns);
   r.k2.resize(r.ns);
-  for (int i = 0; i < r.ns; ++i) {
-    const double ai = h_a[i], aj = h_a[i + 1], ac = std::sqrt(ai * aj);
-    r.k1[i] = c.cosmo.kick(ai, ac, ai);
-    r.dr[i] = c.cosmo.drift(ai, aj, ac);
-    r.k2[i] = c.cosmo.kick(ac, aj, aj);
-  }
+  c.cosmo.kdk_factors(h_a, n_a, r.k1.data(), r.dr.data(), r.k2.data());
   r.pos = d_pos;
   r.mom = d_mom;
   r.ckpt = d_ckpt;
@@ -703,12 +714,7 @@ int pm_run_adjoint(pm_ctx* ctx, const double* h_a, int n_a, const float* d_ckpt,
     if (!(h_a[i] > 0) || (i && !(h_a[i] > h_a[i - 1]))) return c.fail(PM_EINVAL, "a must be > 0 and increasing");
   const int ns = n_a - 1;
   std::vector<double> k1(ns), dr(ns), k2(ns);
-  for (int i = 0; i < ns; ++i) {
-    const double ai = h_a[i], aj = h_a[i + 1], ac = std::sqrt(ai * aj);
-    k1[i] = c.cosmo.kick(ai, ac, ai);
-    dr[i] = c.cosmo.drift(ai, aj, ac);
-    k2[i] = c.cosmo.kick(ac, aj, aj);
-  }
+  c.cosmo.kdk_factors(h_a, n_a, k1.data(), dr.data(), k2.data());
   const long np = c.np3;
   const size_t ck = (size_t)np * 3;
   float* xbar = d_grad_pos;

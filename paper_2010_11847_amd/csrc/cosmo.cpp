@@ -37,27 +37,80 @@ void Cosmo::rhs(double lna, const double* y, double* dy) const {
   dy[3] = -c * y[3] + 1.5 * oma * y[2] - 1.5 * oma * y[0] * y[0];
 }
 
-void Cosmo::integrate(double a, double* y) const {
+void Cosmo::rk4_step(double l, double h, const double* y, double* out) const {
+  double k1[4], k2[4], k3[4], k4[4], t[4];
+  rhs(l, y, k1);
+  for (int i = 0; i < 4; ++i) t[i] = y[i] + 0.5 * h * k1[i];
+  rhs(l + 0.5 * h, t, k2);
+  for (int i = 0; i < 4; ++i) t[i] = y[i] + 0.5 * h * k2[i];
+  rhs(l + 0.5 * h, t, k3);
+  for (int i = 0; i < 4; ++i) t[i] = y[i] + h * k3[i];
+  rhs(l + h, t, k4);
+  for (int i = 0; i < 4; ++i) out[i] = y[i] + h / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+}
+
+static void growing_mode_start(double* y) {
   const double a0 = std::exp(kLnAInit);
   y[0] = a0;
   y[1] = a0;
   y[2] = -3.0 / 7.0 * a0 * a0;
   y[3] = -6.0 / 7.0 * a0 * a0;
+}
+
+void Cosmo::integrate(double a, double* y) const {
+  growing_mode_start(y);
   const double l1 = std::log(a);
   const int n = std::max(1, (int)std::ceil((l1 - kLnAInit) / kStep));
   const double h = (l1 - kLnAInit) / n;
-  double k1[4], k2[4], k3[4], k4[4], t[4];
   double l = kLnAInit;
   for (int s = 0; s < n; ++s) {
-    rhs(l, y, k1);
-    for (int i = 0; i < 4; ++i) t[i] = y[i] + 0.5 * h * k1[i];
-    rhs(l + 0.5 * h, t, k2);
-    for (int i = 0; i < 4; ++i) t[i] = y[i] + 0.5 * h * k2[i];
-    rhs(l + 0.5 * h, t, k3);
-    for (int i = 0; i < 4; ++i) t[i] = y[i] + h * k3[i];
-    rhs(l + h, t, k4);
-    for (int i = 0; i < 4; ++i) y[i] += h / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+    rk4_step(l, h, y, y);
     l += h;
+  }
+}
+
+// Fixed steps of kStep in ln a along one trajectory; each target is reached
+// from the last grid point below it by one shorter step taken on a copy.
+void Cosmo::growth_sorted(const double* a, int n, double* out6) const {
+  double y[4], t[4];
+  growing_mode_start(y);
+  double l = kLnAInit;
+  for (int j = 0; j < n; ++j) {
+    const double lt = std::log(a[j]);
+    while (l + kStep <= lt) {
+      rk4_step(l, kStep, y, y);
+      l += kStep;
+    }
+    if (lt > l)
+      rk4_step(l, lt - l, y, t);
+    else
+      for (int i = 0; i < 4; ++i) t[i] = y[i];
+    double* o = out6 + 6 * j;
+    const double e = E(a[j]);
+    o[0] = t[0] / d1_today;
+    o[1] = t[1] / t[0];
+    o[2] = t[2] / (d1_today * d1_today);
+    o[3] = t[3] / t[2];
+    o[4] = e;
+    o[5] = a[j] * a[j] * e * o[1] * o[0];
+  }
+}
+
+void Cosmo::kdk_factors(const double* a, int n_a, double* k1, double* dr, double* k2) const {
+  const int ns = n_a - 1;
+  if (ns < 1) return;
+  // a_i, a_c, a_j of every step interleave as a_0 < a_c0 < a_1 < a_c1 < ...
+  std::vector<double> pts(2 * ns + 1), g(6 * (2 * ns + 1));
+  for (int i = 0; i <= ns; ++i) pts[2 * i] = a[i];
+  for (int i = 0; i < ns; ++i) pts[2 * i + 1] = std::sqrt(a[i] * a[i + 1]);
+  growth_sorted(pts.data(), 2 * ns + 1, g.data());
+  auto d1 = [&](int p) { return g[6 * p]; };
+  auto gf = [&](int p) { return g[6 * p + 5]; };
+  for (int i = 0; i < ns; ++i) {
+    const int pi = 2 * i, pc = 2 * i + 1, pj = 2 * i + 2;
+    k1[i] = (gf(pc) - gf(pi)) / (1.5 * om * d1(pi));
+    dr[i] = (d1(pj) - d1(pi)) / gf(pc);
+    k2[i] = (gf(pj) - gf(pc)) / (1.5 * om * d1(pj));
   }
 }
 

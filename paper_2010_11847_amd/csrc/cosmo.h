@@ -22,6 +22,10 @@ struct Cosmo {
   double Gf(double a) const;
   double drift(double ai, double aj, double ac) const;
   double kick(double ai, double aj, double ar) const;
+  // Factors of n_a - 1 KDK steps over a[0] < ... < a[n_a-1]: the opening
+  // kick k1 (a_i -> a_c), drift dr (a_i -> a_j) and closing kick k2
+  // (a_c -> a_j), a_c = sqrt(a_i a_j), from one sweep of the growth ODE.
+  void kdk_factors(const double* a, int n_a, double* k1, double* dr, double* k2) const;
   double eh_transfer(double k) const;
   double shape(double k) const;
   double pk(double k) const;          // linear P(k) at a = 1, (Mpc/h)^3
@@ -30,6 +34,9 @@ struct Cosmo {
  private:
   void rhs(double lna, const double* y, double* dy) const;
   void integrate(double a, double* y) const;
+  void rk4_step(double l, double h, const double* y, double* out) const;
+  // growth() at n ascending scale factors from a single integration
+  void growth_sorted(const double* a, int n, double* out6) const;
 };
 
 }  // namespace pmk

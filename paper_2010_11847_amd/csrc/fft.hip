@@ -239,6 +239,95 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(ColPass p, const float2* 
   }
 }
 
+// Inverse y pass of the force meshes after an OP_FORCE_XS x pass
+// (blockIdx.y = 0: F_x in place; 1: the shared factor i g X).  A shared-
+// factor tile is transformed twice: first times D(w_y), which varies along
+// y and so must come before the transform, stored to F_y; then, read again
+// (the tile was just read, so mostly from cache), plain and in place, its
+// output times D(w_z), constant along a column, as F_z.  p.main/p.plane
+// hold F_x, the shared factor (F_z) and F_y, in that order.
+template <int N, int M>
+__global__ __launch_bounds__(kThreads) void k_fft_cols_force(ColPass p, const float2* __restrict__ tw,
+                                                             const float* __restrict__ dy_tab,
+                                                             const float* __restrict__ dz_tab) {
+  constexpr int R1 = Split<N>::R1, R2 = Split<N>::R2;
+  static_assert(R2 > 1, "columns split over two stages");
+  constexpr int IA = (M * R2 + kThreads - 1) / kThreads;
+  constexpr int IB = (M * R1 + kThreads - 1) / kThreads;
+  constexpr int SA = ColLds<N, M>::SA;
+  __shared__ float2 lds[ColLds<N, M>::size];
+  int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const bool is_plane = tile >= p.nb_main;
+  if (is_plane) tile -= p.nb_main;
+  const ColGeom& g = is_plane ? p.gp : p.gm;
+  const bool shared = blockIdx.y == 1;   // uniform
+  const int b = tile / g.ntc;
+  const int c0 = (tile - b * g.ntc) * M;
+  const long off = b * g.sb + c0;
+  float2* base = (is_plane ? p.plane[blockIdx.y] : p.main[blockIdx.y]) + off;
+  const int tid = threadIdx.x;
+
+  // stage A: columns in (times D(w_y) of the row when row_factor), R1-point
+  // transforms, twiddles, into the exchange
+  auto stage_a = [&](bool row_factor) {
+#pragma unroll
+    for (int i = 0; i < IA; ++i) {
+      const int it = tid + i * kThreads;
+      if (it < M * R2) {
+        const int m = it % M, j2 = it / M;
+        const bool ok = c0 + m < g.ncols;
+        float2 v[R1];
+        float d[R1];
+        if (row_factor) {
+#pragma unroll
+          for (int j1 = 0; j1 < R1; ++j1) d[j1] = dy_tab[R2 * j1 + j2];
+        }
+#pragma unroll
+        for (int j1 = 0; j1 < R1; ++j1) v[j1] = ok ? base[(long)(R2 * j1 + j2) * g.sn + m] : make_float2(0.f, 0.f);
+        if (row_factor) {
+#pragma unroll
+          for (int j1 = 0; j1 < R1; ++j1) v[j1] = cscale(v[j1], d[j1]);
+        }
+        dft<R1, 1>(v);
+#pragma unroll
+        for (int l1 = 0; l1 < R1; ++l1) lds[l1 * SA + j2 * M + m] = l1 == 0 ? v[l1] : cmul(v[l1], tw_get<1>(tw, j2 * l1));
+      }
+    }
+  };
+  // stage B: R2-point transforms out of the exchange, stored through dst
+  // times D(w_z) of the column when col_factor
+  auto stage_b = [&](float2* dst, bool col_factor) {
+#pragma unroll
+    for (int i = 0; i < IB; ++i) {
+      const int it = tid + i * kThreads;
+      if (it < M * R1) {
+        const int m = it % M, l1 = it / M;
+        const bool ok = c0 + m < g.ncols;
+        // kz = c / 8 in the main array, N/2 on the Nyquist plane
+        const float cf = col_factor && ok ? dz_tab[is_plane ? N / 2 : (c0 + m) >> 3] : 1.f;
+        float2 v[R2];
+#pragma unroll
+        for (int j2 = 0; j2 < R2; ++j2) v[j2] = lds[l1 * SA + j2 * M + m];
+        dft<R2, 1>(v);
+        if (ok) {
+#pragma unroll
+          for (int l2 = 0; l2 < R2; ++l2) dst[(long)(l1 + R1 * l2) * g.sn + m] = cscale(v[l2], cf);
+        }
+      }
+    }
+  };
+
+  if (shared) {
+    stage_a(true);
+    __syncthreads();
+    stage_b((is_plane ? p.plane[2] : p.main[2]) + off, false);
+    __syncthreads();   // the exchange buffer is reused
+  }
+  stage_a(false);
+  __syncthreads();
+  stage_b(base, shared);
+}
+
 // ===========================================================================
 // Contiguous z passes over the x-blocked layout.  A workgroup takes L lines
 // l0 .. l0+L-1 (L a multiple of 8): L/8 whole (x/8, y) rows, one contiguous
@@ -552,6 +641,7 @@ __host__ __device__ __forceinline__ Term op_term(int kind, int o) {
   constexpr int ls[9] = {0, 1, 2, 0, 3, 4, 1, 2, 5};
   switch (kind) {
     case OP_FORCE: return Term{o == 0 ? 1 : 0, o, 1};
+    case OP_FORCE_XS: return Term{o == 0 ? 1 : 0, 0, 1};
     case OP_FORCE_T: return Term{o == 0 ? 1 : 0, o, 2};
     case OP_LPT2: return Term{o == 0 ? 1 : 0, o, 2};
     case OP_LPT2_T: return Term{o == 0 ? 1 : 0, o, 1};
@@ -589,6 +679,7 @@ __device__ __forceinline__ float common_factor(const SpecOp& op, const FftTables
     case OP_LINEAR:
       return pk();
     case OP_FORCE:
+    case OP_FORCE_XS:
     case OP_FORCE_T: {
       float g = op.scale * inv;
       if (op.deconv) {
@@ -1181,6 +1272,25 @@ void xforce(const FftTables& t, const Field& in, const SpecOp& op, int stage, hi
   }
 }
 
+template <int N>
+void yforce(const FftTables& t, Field* f, hipStream_t s) {
+  if constexpr (Split<N>::R2 > 1) {
+    constexpr int M = Cols<N>::M;
+    ColPass p;
+    const int order[3] = {0, 2, 1};   // F_x, shared factor (F_z), F_y
+    for (int i = 0; i < 3; ++i) {
+      p.main[i] = f[order[i]].c();
+      p.plane[i] = f[order[i]].q;
+    }
+    // geometry of ypass: main c[xb][y][kz][xi], Nyquist plane q[xb][y][xi]
+    p.gm = ColGeom{4L * N * N, 4L * N, 4 * N, cdiv(4 * N, M)};
+    p.gp = ColGeom{8L * N, 8, 8, cdiv(8, M)};
+    p.nb_main = (N / 8) * p.gm.ntc;
+    const dim3 grid(p.nb_main + (N / 8) * p.gp.ntc, 2);
+    hipLaunchKernelGGL((k_fft_cols_force<N, M>), grid, dim3(kThreads), 0, s, p, t.tw_n, t.dxy, t.dz);
+  }
+}
+
 // chunks of at most 3 fields per launch (blockIdx.y selects the field)
 template <class Fn>
 void by3(Field* f, int nf, Fn fn) {
@@ -1258,6 +1368,12 @@ void fft_x_fused(const FftTables& t, const Field& in, const SpecOp& op, hipStrea
 
 void fft_x_force(const FftTables& t, const Field& in, const SpecOp& op, int stage, hipStream_t s) {
 #define CALL(N) xforce<N>(t, in, op, stage, s)
+  PM_FFT_SWITCH(t.n, CALL)
+#undef CALL
+}
+
+void fft_y_force(const FftTables& t, Field* f, hipStream_t s) {
+#define CALL(N) yforce<N>(t, f, s)
   PM_FFT_SWITCH(t.n, CALL)
 #undef CALL
 }

@@ -54,6 +54,8 @@ enum SpecOpKind : int {
   OP_LPT2 = 3,       // 3 outputs: -i D_d / K^2 X * scale
   OP_LINEAR = 4,     // 1 output: X * pk[n^2]
   OP_LPT_PHI = 5,    // 6 outputs: phi_ij of delta_L = X * pk[n^2] (xx, yy, zz, xy, xz, yz)
+  OP_FORCE_XS = 6,   // 2 outputs after the x pass: i D_x g X (F_x) and i g X, the factor
+                     // F_y and F_z share until their y and z passes (N >= 64 only)
   OP_FORCE_T = 16,   // fan-in 3: sum_d conj(i D_d g) X_d
   OP_LPT2_T = 17,    // fan-in 3: sum_d conj(-i D_d scale / K^2) X_d
   OP_LPT1_T = 18,    // fan-in 9: pk[n^2] (sum_d conj(i D_d / K^2) X_d + sum_ij D_i D_j / K^2 X_ij)
@@ -93,6 +95,11 @@ void fft_x_fused(const FftTables& t, const Field& in, const SpecOp& op, hipStrea
 // power p (p = 0: y and z components, p = 1: x, which may alias `in`, so
 // stage 1 runs last).  fft_x_fused(OP_FORCE) runs the three in order.
 void fft_x_force(const FftTables& t, const Field& in, const SpecOp& op, int stage, hipStream_t s);
+// Inverse y pass of the three force meshes after an OP_FORCE_XS x pass:
+// f[0] holds F_x, f[2] the shared factor i g X.  f[2] becomes F_z times
+// D(w_z) in place and f[1] receives F_y = transform of D(w_y) i g X; one
+// read of the shared factor feeds both.  N >= 64.
+void fft_y_force(const FftTables& t, Field* f, hipStream_t s);
 // Single passes (the composites above call these).
 void fft_z_r2c(const FftTables& t, Field* f, int nf, hipStream_t s);
 void fft_y(const FftTables& t, Field* f, int nf, int dir, hipStream_t s);
