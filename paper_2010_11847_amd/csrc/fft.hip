@@ -136,6 +136,22 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
 }
 
+// Tile -> (batch b, first column c0) of a column pass with nbat batches of
+// ntc column tiles.  The y pass walks columns fastest: neighbouring tiles
+// share 128-byte lines.  The x passes walk batches (ky rows) fastest: the
+// workgroups in flight then spread over many rows of every x block instead
+// of a few (measured 10% faster at 1024^3).
+template <bool BATCH_FAST>
+__device__ __forceinline__ void tile_bc(int tile, int nbat, int ntc, int M, int& b, int& c0) {
+  if (BATCH_FAST) {
+    b = tile % nbat;
+    c0 = (tile / nbat) * M;
+  } else {
+    b = tile / ntc;
+    c0 = (tile - b * ntc) * M;
+  }
+}
+
 // ===========================================================================
 // Strided (column-tile) pass: element (batch b, row n, column c) at
 //   data + b*sb + row(n) + c*CS,  n in [0, N), c in [0, ncols)
@@ -184,8 +200,8 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(ColPass p, const float2* 
   if (is_plane) tile -= p.nb_main;
   const ColGeom& g = is_plane ? p.gp : p.gm;
   float2* data = is_plane ? p.plane[blockIdx.y] : p.main[blockIdx.y];
-  const int b = tile / g.ntc;
-  const int c0 = (tile - b * g.ntc) * M;
+  int b, c0;
+  tile_bc<BLK>(tile, is_plane ? ((int)gridDim.x - p.nb_main) / g.ntc : p.nb_main / g.ntc, g.ntc, M, b, c0);
   float2* base = data + b * g.sb + (long)c0 * CS;
   const int tid = threadIdx.x;
 
@@ -717,8 +733,8 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_fused(FusedArgs a) {
   const int mode = tile >= a.nb_main ? 1 : 0;
   if (mode) tile -= a.nb_main;
   const ColGeom& g = mode ? a.gp : a.gm;
-  const int b = tile / g.ntc;
-  const int c0 = (tile - b * g.ntc) * M;
+  int b, c0;
+  tile_bc<true>(tile, mode ? ((int)gridDim.x - a.nb_main) / g.ntc : a.nb_main / g.ntc, g.ntc, M, b, c0);
   const long off = b * g.sb + (long)c0 * 8;
   const int tid = threadIdx.x;
   const SpecOp& op = a.op;
@@ -988,8 +1004,8 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_op(FusedArgs a) {
   const int mode = tile >= a.nb_main ? 1 : 0;
   if (mode) tile -= a.nb_main;
   const ColGeom& g = mode ? a.gp : a.gm;
-  const int b = tile / g.ntc;
-  const int c0 = (tile - b * g.ntc) * M;
+  int b, c0;
+  tile_bc<true>(tile, mode ? ((int)gridDim.x - a.nb_main) / g.ntc : a.nb_main / g.ntc, g.ntc, M, b, c0);
   const long off = b * g.sb + (long)c0 * 8;
   const int tid = threadIdx.x;
   const SpecOp& op = a.op;
