@@ -51,6 +51,18 @@ def kernel_bytes(w, np3):
     }
 
 
+def end_to_end(w, np3, sec_per_step):
+    """Bytes the method itself must move per step (paint: positions in, mesh
+    out; r2c; Green + 3 inverse transforms: spectrum in once, 3 meshes out;
+    readout: 3 meshes and 48 B of particle state) against the step time."""
+    n = w.n_mesh
+    real = 4.0 * n ** 3
+    spec = 4.0 * n ** 3 + 8.0 * n * n
+    b = (12.0 * np3 + real) + (real + spec) + (spec + 3 * real) + (3 * real + 48.0 * np3)
+    gbs = b / sec_per_step / 1e9
+    return {"method_bytes_per_step": b, "achieved_GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def kernel_source_hash():
     """sha256 over the kernel sources (csrc/*.hip, *.h, *.cpp and include/pm.h),
     the key that ties a committed counter summary to the code it measured."""
@@ -293,6 +305,7 @@ def main():
                    "seed": w.seed, "a0": w.a_list[0], "a1": w.a_list[-1], "lpt_order": w.lpt_order,
                    "pk": "eisenstein_hu_nowiggle", "init_lpt_ms": round(init_s * 1e3, 1)},
         "roofline": roofline,
+        "end_to_end": end_to_end(w, np3, t / args.steps),
         "cpu_baseline": base,
         "adjoint": adjoint,
         "serving": serving,

@@ -346,35 +346,30 @@ __device__ __forceinline__ uint32_t slot_key(int slot, int rx, int ry, int rz, c
 // share cache lines), kicks, drift, wrap, and the tile key + rank of the
 // new position.  All loads are issued before any is used (every lane
 // computes, on a clamped index, and only the stores are predicated).  Ranks
-// are counted per workgroup in LDS by slot (27 neighbour tiles x 8 classes
-// of the workgroup's first particle), then one global atomic per used slot
-// reserves the range.  (Two particles per thread measured slower: a
-// 512-particle workgroup spans more tiles in voids, and particles outside
-// the 27-tile neighbourhood take a global atomic each.)
+// are counted per wave in LDS by slot (27 neighbour tiles x 8 classes of
+// the tile of the wave's first particle after the drift), then one global
+// atomic per used slot reserves the range; particles outside the
+// neighbourhood take a global atomic each.  Nothing waits on a workgroup
+// barrier, and each rank is written once.  (Two particles per thread
+// measured slower: the tile span per wave grows in voids.)
 constexpr int kReadoutPPT = 1;
+constexpr int kSlots = 27 * 8;
 
 __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
   constexpr int PPT = kReadoutPPT;
-  __shared__ uint32_t slot_cnt[216];
-  __shared__ uint32_t slot_base[216];
+  constexpr int kWaves = kThreads / 64;
+  __shared__ uint32_t slot_cnt[kWaves][kSlots];
+  __shared__ uint32_t slot_base[kWaves][kSlots];
   const TileGeom& g = a.g;
   const int n = g.n;
   const long chunk = xcd_tile(blockIdx.x, gridDim.x);
   const long j0 = chunk * (long)(kThreads * PPT);
   const bool keys = (a.flags & RO_KEYS) != 0;
-  int rx = 0, ry = 0, rz = 0;
-  if (keys) {
-    for (int i = threadIdx.x; i < 216; i += kThreads) slot_cnt[i] = 0u;
-    int ix, iy, iz;
-    float t;
-    cic_base(a.pos[3 * j0 + 0], n, ix, t);
-    cic_base(a.pos[3 * j0 + 1], n, iy, t);
-    cic_base(a.pos[3 * j0 + 2], n, iz, t);
-    rx = ix >> g.lx;
-    ry = iy >> g.ly;
-    rz = iz >> g.lz;
-    __syncthreads();
-  }
+  const int lane = threadIdx.x & 63;
+  uint32_t* cnt = slot_cnt[threadIdx.x >> 6];
+  uint32_t* sbase = slot_base[threadIdx.x >> 6];
+  if (keys)
+    for (int i = lane; i < kSlots; i += 64) cnt[i] = 0u;
   long jj[PPT];
   bool valid[PPT];
   float x[PPT][3], p[PPT][3];
@@ -430,13 +425,10 @@ __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
       for (int d = 0; d < 3; ++d) F[u][d] += wgt[u][c8] * cv[u][c8][d];
   }
   const float nf = (float)n;
-  int slot[PPT];
 #pragma unroll
   for (int u = 0; u < PPT; ++u) {
-    slot[u] = -1;
-    if (!valid[u]) continue;
     const long j = jj[u];
-    if (a.flags & RO_FORCE_BYID) {
+    if (valid[u] && (a.flags & RO_FORCE_BYID)) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) a.force_out[3 * (long)id[u] + d] = F[u][d];
     }
@@ -444,7 +436,7 @@ __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) p[u][d] += F[u][d] * a.kick_a;
     }
-    if (a.flags & RO_CKPT) {
+    if (valid[u] && (a.flags & RO_CKPT)) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         a.ckpt_x[3 * (long)id[u] + d] = x[u][d];
@@ -459,6 +451,7 @@ __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) x[u][d] = wrap_pos(x[u][d] + p[u][d] * a.drift, nf);
     }
+    if (!valid[u]) continue;
     if (a.flags & RO_WRITE_SORTED) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
@@ -473,28 +466,51 @@ __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
         a.mom_out[3 * (long)id[u] + d] = p[u][d];
       }
     }
-    if (keys) {
-      int kx, ky, kz;
-      float t;
-      cic_base(x[u][0], n, kx, t);
-      cic_base(x[u][1], n, ky, t);
-      cic_base(x[u][2], n, kz, t);
-      const uint32_t key = tile_key(kx, ky, kz, g);
-      slot[u] = key_slot(key, rx, ry, rz, g);
-      a.key_out[j] = key;
-      a.rank_out[j] = slot[u] >= 0 ? atomicAdd(&slot_cnt[slot[u]], 1u) : atomicAdd(&a.count[key], 1u);
-    }
   }
   if (!keys) return;
-  __syncthreads();
-  for (int i = threadIdx.x; i < 216; i += kThreads) {
-    const uint32_t c = slot_cnt[i];
-    slot_base[i] = c ? atomicAdd(&a.count[slot_key(i, rx, ry, rz, g)], c) : 0u;
+  // reference tile: that of lane 0's new position (an invalid lane 0 holds
+  // the clamped last particle, still a valid position)
+  int rx, ry, rz;
+  {
+    int cx, cy, cz;
+    float t;
+    cic_base(__shfl(x[0][0], 0, 64), n, cx, t);
+    cic_base(__shfl(x[0][1], 0, 64), n, cy, t);
+    cic_base(__shfl(x[0][2], 0, 64), n, cz, t);
+    rx = cx >> g.lx;
+    ry = cy >> g.ly;
+    rz = cz >> g.lz;
   }
-  __syncthreads();
+  int slot[PPT];
+  uint32_t rank[PPT];
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) {
+    slot[u] = -1;
+    rank[u] = 0u;
+    if (!valid[u]) continue;
+    int kx, ky, kz;
+    float t;
+    cic_base(x[u][0], n, kx, t);
+    cic_base(x[u][1], n, ky, t);
+    cic_base(x[u][2], n, kz, t);
+    const uint32_t key = tile_key(kx, ky, kz, g);
+    slot[u] = key_slot(key, rx, ry, rz, g);
+    a.key_out[jj[u]] = key;
+    rank[u] = slot[u] >= 0 ? atomicAdd(&cnt[slot[u]], 1u) : atomicAdd(&a.count[key], 1u);
+  }
+  // the wave's own LDS operations complete in order; the fence keeps the
+  // compiler from moving the reads of other lanes' counts above the atomics
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  for (int i = lane; i < kSlots; i += 64) {
+    const uint32_t c = cnt[i];
+    sbase[i] = c ? atomicAdd(&a.count[slot_key(i, rx, ry, rz, g)], c) : 0u;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 #pragma unroll
   for (int u = 0; u < PPT; ++u)
-    if (valid[u] && slot[u] >= 0) a.rank_out[jj[u]] += slot_base[slot[u]];
+    if (valid[u]) a.rank_out[jj[u]] = rank[u] + (slot[u] >= 0 ? sbase[slot[u]] : 0u);
 }
 
 // elementwise kick + drift with a given per-particle force (first half of a
