@@ -159,6 +159,42 @@ def adjoint_section(names=("adj128_mesh256_box400", "pm512_mesh1024_box1024"), r
     return out
 
 
+def recon_section(n_iter=10):
+    """Iterations of the section 7 reconstruction (dark-matter observable):
+    the paper's own problem (5 KDK steps, 128^3 grid, 400 Mpc/h, force
+    resolution 1) and the 128^3/256^3 adjoint workload.  Data: the final
+    overdensity of another noise realisation plus Gaussian noise (sigma 0.1)."""
+    import torch
+    from paper_2010_11847_amd import inputs
+    from paper_2010_11847_amd.binding import PMContext
+    from paper_2010_11847_amd.recon import Reconstruction
+    out = {}
+    from dataclasses import replace
+    paper = replace(inputs.ADJ_MEDIUM, name="recon128_mesh128_box400", n_mesh=128)
+    for w in (paper, inputs.ADJ_MEDIUM):
+        c = PMContext(w)
+        m = w.n_mesh
+        pos, mom = c.pm_init_lpt(w.seed + 1000, w.a_list[0])
+        data = torch.empty((m, m, m), device="cuda")
+        c.pm_run(w.a_list, pos, mom, delta_final=data)
+        g = torch.Generator(device="cuda").manual_seed(w.seed + 2000)
+        data += 0.1 * torch.randn((m, m, m), device="cuda", generator=g)
+        r = Reconstruction(c, w.a_list, data, 0.1, lr=0.01)
+        r.run(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hist = r.run(n_iter)
+        dt = (time.perf_counter() - t0) / n_iter
+        out[w.name] = {"n_part": w.n_part, "n_mesh": w.n_mesh, "box_mpc_h": w.box_size, "steps": w.n_steps,
+                       "ms_per_iteration": round(dt * 1e3, 2), "iterations": n_iter,
+                       "loss_first": round(sum(hist[0]), 1), "loss_last": round(sum(hist[-1]), 1)}
+        print(f"[bench] recon {w.name} {out[w.name]}", file=sys.stderr, flush=True)
+        del r, c, data, pos, mom
+        torch.cuda.empty_cache()
+    out["paper_s_per_iteration_v100"] = 1.1
+    return out
+
+
 def serving_section(n_requests, rate=20.0, seed=5, budget_gb=64.0, slots=4):
     """Continuous batching vs one-at-a-time on the same Poisson trace."""
     from paper_2010_11847_amd import serve
@@ -196,7 +232,8 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="skip the event-timed profile pass")
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device-to-device copy of GIB GiB (counter calibration) and exit")
-    ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient (adjoint) timing section")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the gradient (adjoint) and reconstruction timing sections")
     ap.add_argument("--serve", type=int, default=200,
                     help="requests of the serving trace (Poisson 20/s); 0 skips the serving section")
     args = ap.parse_args()
@@ -280,6 +317,7 @@ def main():
     del ctx, pos, mom, pos0, mom0
     torch.cuda.empty_cache()
     adjoint = None if args.no_adjoint else adjoint_section()
+    reconstruction = None if args.no_adjoint else recon_section()
     serving = None
     if args.serve > 0:
         serving = serving_section(args.serve)
@@ -308,6 +346,7 @@ def main():
         "end_to_end": end_to_end(w, np3, t / args.steps),
         "cpu_baseline": base,
         "adjoint": adjoint,
+        "reconstruction": reconstruction,
         "serving": serving,
         "kernels": kernels,
     }

@@ -198,6 +198,26 @@ int pm_run_adjoint(pm_ctx* ctx, const double* h_a, int n_a, const float* d_ckpt,
                    const float* d_grad_delta_final, float* d_grad_pos, float* d_grad_mom,
                    float* d_grad_noise);
 
+/* MAP reconstruction of the initial conditions from the final dark-matter
+ * overdensity (section 7): minimise
+ *   loss(w) = sum_cells ((delta_m(w) - delta_e) / sigma)^2 + sum_lattice w^2
+ * over the white noise w that sets the initial field (the prior of the
+ * initial modes in whitened variables).  One call: Gen-IC from w, the run
+ * over h_a with checkpoints, the chi^2 residual, the adjoint of the run, and
+ * one Adam update (Kingma & Ba, Algorithm 1) of w at step count t >= 1.
+ * d_data: [n_mesh^3] observed overdensity, C order.  d_noise: [n_part^3],
+ * inout.  d_adam_m, d_adam_v: [n_part^3] moment estimates, inout, zero
+ * before t = 1.  d_work: 256-byte aligned scratch of at least
+ * pm_recon_work_bytes(ctx, n_a) bytes (checkpoints, state, residual).
+ * h_loss2: out, {chi^2, sum w^2} at the noise before the update; the call
+ * synchronises the stream to return them.  PM_EINVAL for NULL pointers,
+ * n_a < 2, sigma <= 0, t < 1, lr <= 0, beta outside [0, 1) or eps < 0;
+ * PM_ENOMEM if work_bytes is too small; PM_ESTATE during a resumable run. */
+size_t pm_recon_work_bytes(const pm_ctx* ctx, int n_a);
+int pm_recon_step(pm_ctx* ctx, const double* h_a, int n_a, const float* d_data, double sigma, float* d_noise,
+                  float* d_adam_m, float* d_adam_v, int t, double lr, double beta1, double beta2, double eps,
+                  void* d_work, size_t work_bytes, double* h_loss2);
+
 /* Binned power spectrum of a real mesh (section 5.1 two-point statistics):
  * P(k_j) = (L^3/N^6) sum_w |delta^|^2 / sum_w, mode weight 2 on interior
  * n_z planes and 1 on n_z = 0 and N/2, bins |n| in [j-1/2, j+1/2),

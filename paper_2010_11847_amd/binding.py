@@ -238,6 +238,29 @@ class PMContext:
                                             _ptr(gx), _ptr(gp), _ptr(gn)), "pm_run_adjoint")
         return gx, gp, gn
 
+    # ---- MAP reconstruction ----------------------------------------------------
+    def pm_recon_work_bytes(self, n_a: int) -> int:
+        return int(self.lib.pm_recon_work_bytes(self.ctx, n_a))
+
+    def pm_recon_step(self, a_list, data, sigma: float, noise, adam_m, adam_v, t: int, lr: float,
+                      beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, work=None):
+        """One Adam iteration of the reconstruction; updates noise, adam_m,
+        adam_v in place and returns (chi^2, prior) before the update."""
+        a = np.ascontiguousarray(a_list, dtype=np.float64)
+        n, m = self.workload.n_part, self.workload.n_mesh
+        self._dev(data, (m, m, m), name="data")
+        for arr, nm in ((noise, "noise"), (adam_m, "adam_m"), (adam_v, "adam_v")):
+            self._dev(arr, (n, n, n), name=nm)
+        need = self.pm_recon_work_bytes(len(a))
+        if work is None:
+            work = torch.empty(need, dtype=torch.uint8, device=self.device)
+        self._dev(work, dtype=torch.uint8, name="work")
+        out = (C.c_double * 2)()
+        self._check(self.lib.pm_recon_step(self.ctx, a.ctypes.data_as(C.POINTER(C.c_double)), len(a), _ptr(data),
+                                           sigma, _ptr(noise), _ptr(adam_m), _ptr(adam_v), t, lr, beta1, beta2, eps,
+                                           _ptr(work), work.numel(), out), "pm_recon_step")
+        return float(out[0]), float(out[1])
+
     # ---- resumable run (continuous batching) ---------------------------------
     def pm_run_begin(self, a_list, pos, mom, ckpt: Optional[torch.Tensor] = None):
         self._dev(pos, (self.np3, 3), name="pos")

@@ -13,6 +13,7 @@
 
 #include "cosmo.h"
 #include "particles.h"
+#include "recon.h"
 #include "pm.h"
 #include "pm_internal.h"
 
@@ -829,6 +830,72 @@ int pm_run_adjoint(pm_ctx* ctx, const double* h_a, int n_a, const float* d_ckpt,
   pmk::fft_c2r_yz(c.tl, &f[0], 1, c.stream);
   pmk::launch_relayout(f[0].r, d_grad_noise, c.npart, false, c.stream);
   return c.check("pm_run_adjoint");
+}
+
+// ---- MAP reconstruction (section 7) --------------------------------------
+namespace {
+struct ReconWork {
+  float *ckpt, *pos, *mom, *resid, *gnoise;
+  double *partials, *out;
+  size_t total;
+};
+
+ReconWork recon_work(const pm_ctx& c, int n_a, char* base) {
+  ReconWork w{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base ? base + o : nullptr;
+    o += align_up(bytes);
+    return p;
+  };
+  const size_t st = (size_t)c.np3 * 3 * sizeof(float);
+  w.ckpt = reinterpret_cast<float*>(take((size_t)n_a * 2 * st));
+  w.pos = reinterpret_cast<float*>(take(st));
+  w.mom = reinterpret_cast<float*>(take(st));
+  w.resid = reinterpret_cast<float*>(take((size_t)c.ng * c.ng * c.ng * sizeof(float)));
+  w.gnoise = reinterpret_cast<float*>(take((size_t)c.np3 * sizeof(float)));
+  w.partials = reinterpret_cast<double*>(take(pmk::kReducePartials * sizeof(double)));
+  w.out = reinterpret_cast<double*>(take(2 * sizeof(double)));
+  w.total = o;
+  return w;
+}
+}  // namespace
+
+size_t pm_recon_work_bytes(const pm_ctx* ctx, int n_a) {
+  if (!ctx || n_a < 2) return 0;
+  return recon_work(*ctx, n_a, nullptr).total;
+}
+
+int pm_recon_step(pm_ctx* ctx, const double* h_a, int n_a, const float* d_data, double sigma, float* d_noise,
+                  float* d_adam_m, float* d_adam_v, int t, double lr, double beta1, double beta2, double eps,
+                  void* d_work, size_t work_bytes, double* h_loss2) {
+  if (!ctx || !h_a || n_a < 2 || !d_data || !d_noise || !d_adam_m || !d_adam_v || !d_work || !h_loss2)
+    return PM_EINVAL;
+  pm_ctx& c = *ctx;
+  if (!(sigma > 0) || t < 1 || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps >= 0))
+    return c.fail(PM_EINVAL, "need sigma > 0, t >= 1, lr > 0, 0 <= beta < 1, eps >= 0");
+  if ((uintptr_t)d_work % kAlign) return c.fail(PM_EINVAL, "d_work must be 256-byte aligned");
+  if (c.run.active) return c.fail(PM_ESTATE, "a resumable run is in progress");
+  const ReconWork w = recon_work(c, n_a, static_cast<char*>(d_work));
+  if (work_bytes < w.total) return c.fail(PM_ENOMEM, "reconstruction work buffer too small");
+  int st = pm_init_lpt(ctx, 0, h_a[0], d_noise, nullptr, w.pos, w.mom);
+  if (st != PM_OK) return st;
+  st = pm_run(ctx, h_a, n_a, w.pos, w.mom, w.ckpt, w.resid);
+  if (st != PM_OK) return st;
+  const long ncell = (long)c.ng * c.ng * c.ng;
+  pmk::launch_residual(w.resid, d_data, ncell, (float)(1.0 / sigma), w.partials, w.out, c.stream);
+  // the state buffers become the zeroed cotangent accumulators of the adjoint
+  pmk::launch_fill_u32(reinterpret_cast<uint32_t*>(w.pos), c.np3 * 3, 0u, c.stream);
+  pmk::launch_fill_u32(reinterpret_cast<uint32_t*>(w.mom), c.np3 * 3, 0u, c.stream);
+  st = pm_run_adjoint(ctx, h_a, n_a, w.ckpt, d_noise, w.resid, w.pos, w.mom, w.gnoise);
+  if (st != PM_OK) return st;
+  pmk::launch_adam(d_noise, w.gnoise, d_adam_m, d_adam_v, c.np3, (float)lr, (float)beta1, (float)beta2, (float)eps,
+                   (float)(1.0 / (1.0 - std::pow(beta1, t))), (float)(1.0 / (1.0 - std::pow(beta2, t))), w.partials,
+                   w.out + 1, c.stream);
+  if (hipMemcpyAsync(h_loss2, w.out, 2 * sizeof(double), hipMemcpyDeviceToHost, c.stream) != hipSuccess ||
+      hipStreamSynchronize(c.stream) != hipSuccess)
+    return c.check("pm_recon_step");
+  return c.check("pm_recon_step");
 }
 
 int pm_power(pm_ctx* ctx, const float* d_delta, int n_bins, int n_max, int deconv, double* h_k, double* h_pk,
