@@ -28,8 +28,11 @@ def problem(n_mesh=32, n_part=16, n_steps=3):
 def test_recon_step_matches_oracle(gpu):
     banner("recon step 32/16 3 steps")
     w, noise, target = problem()
+    # both sides start from the same float32 noise
+    noise = noise.astype(np.float32).astype(np.float64)
     c = PMContext(w)
-    r = Reconstruction(c, w.a_list, to_dev(target.astype(np.float32)), SIGMA, noise0=to_dev(noise), lr=0.01)
+    r = Reconstruction(c, w.a_list, to_dev(target.astype(np.float32)), SIGMA,
+                       noise0=to_dev(noise.astype(np.float32)), lr=0.01)
     chi2, prior = r.step()
     chi2_o, prior_o, g_o = orecon.posterior_loss_and_grad(noise, w, target, SIGMA)
     assert chi2 == pytest.approx(chi2_o, rel=1e-4)
