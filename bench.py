@@ -159,6 +159,42 @@ def adjoint_section(names=("adj128_mesh256_box400", "pm512_mesh1024_box1024"), r
     return out
 
 
+def pyramid_section(w, steps):
+    """The same run with the two-level pyramid force (section 4.2, f = 2):
+    step time and the extra kernel classes (the paper's scheme targets
+    distributed meshes; on one device it adds its passes to the full force)."""
+    import torch
+    from dataclasses import replace
+    from paper_2010_11847_amd.binding import PMContext
+    wp = replace(w, pyramid_levels=2)
+    c = PMContext(wp)
+    pos, mom = c.pm_init_lpt(wp.seed, wp.a_list[0])
+    a = inputs_a(wp, steps)
+    c.pm_run(a, pos.clone(), mom.clone())
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    c.pm_run(a, pos, mom)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    c.pm_profile(True)
+    c.pm_run(a, pos, mom)
+    prof = c.pm_profile_read()
+    c.pm_profile(False)
+    out = {"levels": 2, "coarse_mesh": wp.n_mesh >> 2, "ms_per_step": round(ms, 2),
+           "kernels_ms_per_step": {k: round(v[0] / (steps + 1), 3) for k, v in prof.items() if k.startswith("pyr")}}
+    print(f"[bench] pyramid {out}", file=sys.stderr, flush=True)
+    del c, pos, mom
+    torch.cuda.empty_cache()
+    return out
+
+
+def inputs_a(w, steps):
+    from paper_2010_11847_amd import inputs
+    return inputs.a_linear(w.a_list[0], w.a_list[-1], steps)
+
+
 def recon_section(n_iter=10):
     """Iterations of the section 7 reconstruction (dark-matter observable):
     the paper's own problem (5 KDK steps, 128^3 grid, 400 Mpc/h, force
@@ -233,7 +269,7 @@ def main():
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device-to-device copy of GIB GiB (counter calibration) and exit")
     ap.add_argument("--no-adjoint", action="store_true",
-                    help="skip the gradient (adjoint) and reconstruction timing sections")
+                    help="skip the pyramid, gradient (adjoint) and reconstruction timing sections")
     ap.add_argument("--serve", type=int, default=200,
                     help="requests of the serving trace (Poisson 20/s); 0 skips the serving section")
     args = ap.parse_args()
@@ -316,6 +352,7 @@ def main():
 
     del ctx, pos, mom, pos0, mom0
     torch.cuda.empty_cache()
+    pyramid = None if args.no_adjoint else pyramid_section(w, args.steps)
     adjoint = None if args.no_adjoint else adjoint_section()
     reconstruction = None if args.no_adjoint else recon_section()
     serving = None
@@ -345,6 +382,7 @@ def main():
         "roofline": roofline,
         "end_to_end": end_to_end(w, np3, t / args.steps),
         "cpu_baseline": base,
+        "pyramid": pyramid,
         "adjoint": adjoint,
         "reconstruction": reconstruction,
         "serving": serving,

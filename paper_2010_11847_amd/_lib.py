@@ -29,7 +29,7 @@ class pm_config(C.Structure):
     _fields_ = [("box_size", C.c_double), ("n_mesh", C.c_int), ("n_part", C.c_int),
                 ("cosmo", pm_cosmo), ("lpt_order", C.c_int), ("deconv_order", C.c_int),
                 ("split_rs", C.c_double), ("split_mode", C.c_int),
-                ("lattice_shift", C.c_double), ("max_particles", C.c_int64)]
+                ("lattice_shift", C.c_double), ("max_particles", C.c_int64), ("pyramid_levels", C.c_int)]
 
 
 # name -> (restype, argtypes)

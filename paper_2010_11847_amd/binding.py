@@ -26,7 +26,7 @@ def make_config(w: Workload, max_particles: int = 0) -> _lib.pm_config:
     cos = _lib.pm_cosmo(c.omega_m, c.omega_b, c.h, c.n_s, c.sigma8, c.t_cmb, c.pk_kind,
                         c.pk_amp, c.pk_index, None, None, 0)
     return _lib.pm_config(w.box_size, w.n_mesh, w.n_part, cos, w.lpt_order, w.deconv_order,
-                          w.split_rs, w.split_mode, w.lattice_shift, max_particles)
+                          w.split_rs, w.split_mode, w.lattice_shift, max_particles, w.pyramid_levels)
 
 
 def _ptr(t: Optional[torch.Tensor]):

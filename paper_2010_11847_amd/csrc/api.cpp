@@ -13,6 +13,7 @@
 
 #include "cosmo.h"
 #include "particles.h"
+#include "pyramid.h"
 #include "recon.h"
 #include "pm.h"
 #include "pm_internal.h"
@@ -65,6 +66,7 @@ struct Layout {
   size_t count = 0, off = 0, bsum = 0;
   size_t pw_partial = 0, pw_out = 0;
   size_t misc = 0;   // small device words (the adjoint paint's max |weight|)
+  size_t tab_coarse = 0, coarse[3] = {0, 0, 0}, force_c = 0;   // pyramid coarse grid
   size_t lat0 = 0;   // LPT lattice fields alias the mesh + particle region
   size_t total = 0;
   long n_keys = 0, cap = 0;
@@ -104,6 +106,12 @@ int validate(const pm_config* c, std::string* why) {
   if (c->max_particles < 0) return bad("max_particles must be >= 0");
   if (c->max_particles > 0 && c->max_particles < np3) return bad("max_particles must be 0 or >= n_part^3");
   if ((c->max_particles > 0 ? c->max_particles : np3) > (1L << 31) - 1) return bad("too many particles");
+  if (c->pyramid_levels < 0 || c->pyramid_levels > 4) return bad("pyramid_levels must be in [0, 4]");
+  if (c->pyramid_levels > 0) {
+    if ((c->n_mesh >> c->pyramid_levels) < 8) return bad("the pyramid's coarse grid needs >= 8 cells per side");
+    if (c->deconv_order != 0 || c->split_mode != PM_SPLIT_NONE)
+      return bad("the pyramid force takes neither deconvolution nor a force split");
+  }
   return PM_OK;
 }
 
@@ -129,6 +137,8 @@ Layout make_layout(const pm_config* c) {
   L.pw_partial = take((size_t)pmk::power_partial_doubles(L.n_bins_max) * 8);
   L.pw_out = take((size_t)3 * L.n_bins_max * 8);
   L.misc = take(256);
+  const long nc = c->pyramid_levels > 0 ? ng >> c->pyramid_levels : 0;
+  if (nc) L.tab_coarse = take(fft_table_bytes(nc));
   const size_t region = o;
   for (int i = 0; i < 3; ++i) L.mesh[i] = take(field_bytes(ng));
   L.force_i = take((size_t)ng * ng * ng * 12);
@@ -137,6 +147,10 @@ Layout make_layout(const pm_config* c) {
   for (int i = 0; i < 2; ++i) L.id_s[i] = take((size_t)L.cap * 4);
   L.key = take((size_t)L.cap * 4);
   L.rank = take((size_t)L.cap * 4);
+  if (nc) {
+    for (int i = 0; i < 3; ++i) L.coarse[i] = take(field_bytes(nc));
+    L.force_c = take((size_t)nc * nc * nc * 12);
+  }
   // initial conditions (and their adjoint) use up to 13 lattice fields
   // inside the (then idle) mesh and particle region
   L.lat0 = region;
@@ -196,11 +210,12 @@ void build_fft_tables(long n, double rs, std::vector<char>& host, size_t base_of
 // Kernel classes timed by the optional event profiler.
 enum ProfCls : int {
   PC_FILL, PC_KEYS, PC_SCAN, PC_SCATTER, PC_PAINT, PC_FFT_R2C_Z, PC_FFT_Y_FWD, PC_FFT_X_SCALE, PC_FFT_X_INV0,
-  PC_FFT_X_INV1, PC_FFT_Y_INV, PC_FFT_C2R_Z, PC_READOUT, PC_NCLS
+  PC_FFT_X_INV1, PC_FFT_Y_INV, PC_FFT_C2R_Z, PC_READOUT, PC_PYR_REDUCE, PC_PYR_COARSE, PC_PYR_EXPAND, PC_NCLS
 };
-const char* const kProfNames[PC_NCLS] = {"fill",        "keys",       "scan",       "scatter",   "paint",
+const char* const kProfNames[PC_NCLS] = {"fill",        "keys",       "scan",        "scatter",    "paint",
                                          "fft_z_r2c",   "fft_y_fwd",  "fft_x_scale", "fft_x_inv0", "fft_x_inv1",
-                                         "fft_y_inv",   "fft_z_c2r",  "readout_kdk"};
+                                         "fft_y_inv",   "fft_z_c2r",  "readout_kdk", "pyr_reduce", "pyr_coarse_force",
+                                         "pyr_expand"};
 
 struct Profiler {
   bool on = false;
@@ -240,6 +255,11 @@ struct pm_ctx {
   FftTables tm, tl;
   Field mesh[3];
   float* force_i = nullptr;   // interleaved force mesh, x-blocked [n/8][n][n][8][3]
+  // pyramid: coarse grid of nc = ng / 2^levels cells per side
+  int nc = 0;
+  FftTables tc;
+  Field coarse[3];
+  float* force_c = nullptr;   // interleaved coarse force, fine-cell units
   uint32_t* misc = nullptr;   // small device words
   float* pos_s[2] = {};
   float* mom_s[2] = {};
@@ -321,32 +341,102 @@ struct pm_ctx {
     const double scale = (double)ng * ng * ng / (double)np;
     timed(PC_PAINT, [&] { pmk::launch_paint(pos_s[cur], off, tg, out, (float)scale, -1.f, std_layout, stream); });
   }
-  // force meshes from the overdensity in mesh[0].r (overwritten)
-  void force_meshes() {
-    timed(PC_FFT_R2C_Z, [&] { pmk::fft_z_r2c(tm, &mesh[0], 1, stream); });
-    timed(PC_FFT_Y_FWD, [&] { pmk::fft_y(tm, &mesh[0], 1, -1, stream); });
+  // force meshes of an n^3 grid (tables t, fields f[0..2], overdensity in
+  // f[0].r, overwritten) into the interleaved mesh out; scale multiplies the
+  // force (the inverse transform's 1/n^3 and any change of cell units); the
+  // stages are timed by class when cls < 0, else as one class
+  void force_on(const FftTables& t, Field* f, float* out, long n, double scale, int deconv, int split, int cls) {
+    auto tm_ = [&](int c, auto&& fn) { timed(cls < 0 ? c : cls, fn); };
+    tm_(PC_FFT_R2C_Z, [&] { pmk::fft_z_r2c(t, &f[0], 1, stream); });
+    tm_(PC_FFT_Y_FWD, [&] { pmk::fft_y(t, &f[0], 1, -1, stream); });
     pmk::SpecOp op;
-    op.scale = (float)(1.5 * cfg.cosmo.omega_m / ((double)ng * ng * ng));
-    op.deconv = cfg.deconv_order;
-    op.split = cfg.split_mode;
+    op.scale = (float)scale;
+    op.deconv = deconv;
+    op.split = split;
     // from 64^3 up F_y and F_z share one x transform (i g X) and get their
     // D(w_y), D(w_z) in the y pass; smaller meshes take the fused x pass
-    const bool xs = ng >= 64;
+    const bool xs = n >= 64;
     op.kind = xs ? pmk::OP_FORCE_XS : pmk::OP_FORCE;
     op.n_out = xs ? 2 : 3;
     const int dst[3] = {0, xs ? 2 : 1, 2};
     for (int i = 0; i < op.n_out; ++i) {
-      op.out_c[i] = mesh[dst[i]].c();
-      op.out_q[i] = mesh[dst[i]].q;
+      op.out_c[i] = f[dst[i]].c();
+      op.out_q[i] = f[dst[i]].q;
     }
-    timed(PC_FFT_X_SCALE, [&] { pmk::fft_x_force(tm, mesh[0], op, -1, stream); });
-    timed(PC_FFT_X_INV0, [&] { pmk::fft_x_force(tm, mesh[0], op, 0, stream); });
-    timed(PC_FFT_X_INV1, [&] { pmk::fft_x_force(tm, mesh[0], op, 1, stream); });
+    tm_(PC_FFT_X_SCALE, [&] { pmk::fft_x_force(t, f[0], op, -1, stream); });
+    tm_(PC_FFT_X_INV0, [&] { pmk::fft_x_force(t, f[0], op, 0, stream); });
+    tm_(PC_FFT_X_INV1, [&] { pmk::fft_x_force(t, f[0], op, 1, stream); });
     if (xs)
-      timed(PC_FFT_Y_INV, [&] { pmk::fft_y_force(tm, mesh, stream); });
+      tm_(PC_FFT_Y_INV, [&] { pmk::fft_y_force(t, f, stream); });
     else
-      timed(PC_FFT_Y_INV, [&] { pmk::fft_y(tm, mesh, 3, 1, stream); });
-    timed(PC_FFT_C2R_Z, [&] { pmk::fft_z_c2r_interleaved3(tm, mesh, force_i, stream); });
+      tm_(PC_FFT_Y_INV, [&] { pmk::fft_y(t, f, 3, 1, stream); });
+    tm_(PC_FFT_C2R_Z, [&] { pmk::fft_z_c2r_interleaved3(t, f, out, stream); });
+  }
+
+  // REDUCE (expand = false) or EXPAND of ch channels over `levels` levels,
+  // as three one-axis passes per level; intermediates alternate between the
+  // halves of each channel's scratch (scr[c], 2 * half floats).  The last
+  // pass writes `out` with `mode`.
+  void pyr_chain(bool expand, int ch, pmk::PyrField in, const pmk::PyrField& out, int levels, float* const* scr,
+                 size_t half, int mode, const float* aux, float alpha) {
+    int k = 0;
+    for (int lv = 0; lv < levels; ++lv)
+      for (int ax = 0; ax < 3; ++ax) {
+        const bool last = lv == levels - 1 && ax == 2;
+        pmk::PyrField nx;
+        if (last) {
+          nx = out;
+        } else {
+          nx.kind = pmk::PYR_PLAIN;
+          nx.nx = in.nx;
+          nx.ny = in.ny;
+          nx.nz = in.nz;
+          int* d = ax == 0 ? &nx.nx : (ax == 1 ? &nx.ny : &nx.nz);
+          *d = expand ? *d * 2 : *d / 2;
+          for (int c = 0; c < ch; ++c) nx.p[c] = scr[c] + (k & 1) * half;
+        }
+        pmk::launch_pyr_pass(expand, ax, ch, in, nx, last ? mode : pmk::PYR_STORE, aux, alpha, stream);
+        in = nx;
+        ++k;
+      }
+  }
+
+  // force meshes from the overdensity in mesh[0].r (overwritten) into force_i
+  void force_meshes() {
+    const double g = 1.5 * cfg.cosmo.omega_m;
+    if (!nc) {
+      force_on(tm, mesh, force_i, ng, g / ((double)ng * ng * ng), cfg.deconv_order, cfg.split_mode, -1);
+      return;
+    }
+    // Algorithm 3 with one device holding the periodic mesh:
+    //   F = EXPAND(F_L) + F_S - EXPAND(REDUCE(F_S)) = F_S + EXPAND(F_L - REDUCE(F_S))
+    // (EXPAND is linear); F_L is the coarse-grid force of REDUCE(delta),
+    // converted to fine cells by 2^levels.
+    const int lv = cfg.pyramid_levels;
+    const size_t half = (size_t)ng * ng * ng / 2;
+    pmk::PyrField fine1, coarse1;
+    fine1.kind = pmk::PYR_BLOCKED;
+    fine1.p[0] = mesh[0].r;
+    fine1.nx = fine1.ny = fine1.nz = (int)ng;
+    coarse1.kind = pmk::PYR_BLOCKED;
+    coarse1.p[0] = coarse[0].r;
+    coarse1.nx = coarse1.ny = coarse1.nz = nc;
+    float* scr_d[1] = {mesh[1].r};
+    timed(PC_PYR_REDUCE, [&] { pyr_chain(false, 1, fine1, coarse1, lv, scr_d, half, pmk::PYR_STORE, nullptr, 0.f); });
+    force_on(tc, coarse, force_c, nc, g / ((double)nc * nc * nc) * (double)(1 << lv), 0, 0, PC_PYR_COARSE);
+    force_on(tm, mesh, force_i, ng, g / ((double)ng * ng * ng), 0, 0, -1);
+    // D = F_L - REDUCE(F_S) on the coarse grid (three plain channels in the
+    // now idle coarse fields), then F_S += EXPAND(D)
+    pmk::PyrField fs, dc;
+    fs.kind = pmk::PYR_INTERLEAVED;
+    fs.p[0] = force_i;
+    fs.nx = fs.ny = fs.nz = (int)ng;
+    dc.kind = pmk::PYR_PLAIN;
+    for (int c = 0; c < 3; ++c) dc.p[c] = coarse[c].r;
+    dc.nx = dc.ny = dc.nz = nc;
+    float* scr3[3] = {mesh[0].r, mesh[1].r, mesh[2].r};
+    timed(PC_PYR_REDUCE, [&] { pyr_chain(false, 3, fs, dc, lv, scr3, half, pmk::PYR_COMBINE, force_c, 1.f); });
+    timed(PC_PYR_EXPAND, [&] { pyr_chain(true, 3, dc, fs, lv, scr3, half, pmk::PYR_ADD, nullptr, 0.f); });
   }
   void readout(const pmk::ReadoutArgs& a) {
     timed(PC_READOUT, [&] { pmk::launch_readout(a, stream); });
@@ -429,6 +519,14 @@ int pm_create(const pm_config* cfg, void* d_workspace, size_t bytes, void* strea
   }
   c->force_i = reinterpret_cast<float*>(w + L.force_i);
   c->misc = reinterpret_cast<uint32_t*>(w + L.misc);
+  c->nc = cfg->pyramid_levels > 0 ? c->ng >> cfg->pyramid_levels : 0;
+  if (c->nc) {
+    for (int i = 0; i < 3; ++i) {
+      c->coarse[i].r = reinterpret_cast<float*>(w + L.coarse[i]);
+      c->coarse[i].q = reinterpret_cast<float2*>(w + L.coarse[i] + align_up((size_t)c->nc * c->nc * c->nc * 4));
+    }
+    c->force_c = reinterpret_cast<float*>(w + L.force_c);
+  }
   for (int i = 0; i < 2; ++i) {
     c->pos_s[i] = reinterpret_cast<float*>(w + L.pos_s[i]);
     c->mom_s[i] = reinterpret_cast<float*>(w + L.mom_s[i]);
@@ -448,6 +546,7 @@ int pm_create(const pm_config* cfg, void* d_workspace, size_t bytes, void* strea
   const double rs = cfg->split_mode != PM_SPLIT_NONE ? cfg->split_rs : 0.0;
   build_fft_tables(c->ng, rs, host, L.tab_mesh, c->tm, w);
   build_fft_tables(c->npart, 0.0, host, L.tab_lat, c->tl, w);
+  if (c->nc) build_fft_tables(c->nc, 0.0, host, L.tab_coarse, c->tc, w);
   {
     float* pk = reinterpret_cast<float*>(host.data() + L.pk_lat);
     const long h = c->npart / 2;
@@ -710,6 +809,7 @@ int pm_run_adjoint(pm_ctx* ctx, const double* h_a, int n_a, const float* d_ckpt,
                    const float* d_grad_delta_final, float* d_grad_pos, float* d_grad_mom, float* d_grad_noise) {
   if (!ctx || !h_a || n_a < 1 || !d_ckpt || !d_grad_pos || !d_grad_mom) return PM_EINVAL;
   pm_ctx& c = *ctx;
+  if (c.nc) return c.fail(PM_EINVAL, "the adjoint covers the single-grid force only");
   if (d_grad_noise && !d_noise) return c.fail(PM_EINVAL, "d_grad_noise needs d_noise");
   for (int i = 0; i < n_a; ++i)
     if (!(h_a[i] > 0) || (i && !(h_a[i] > h_a[i - 1]))) return c.fail(PM_EINVAL, "a must be > 0 and increasing");
@@ -876,6 +976,7 @@ int pm_recon_step(pm_ctx* ctx, const double* h_a, int n_a, const float* d_data, 
     return c.fail(PM_EINVAL, "need sigma > 0, t >= 1, lr > 0, 0 <= beta < 1, eps >= 0");
   if ((uintptr_t)d_work % kAlign) return c.fail(PM_EINVAL, "d_work must be 256-byte aligned");
   if (c.run.active) return c.fail(PM_ESTATE, "a resumable run is in progress");
+  if (c.nc) return c.fail(PM_EINVAL, "the adjoint covers the single-grid force only");
   const ReconWork w = recon_work(c, n_a, static_cast<char*>(d_work));
   if (work_bytes < w.total) return c.fail(PM_ENOMEM, "reconstruction work buffer too small");
   int st = pm_init_lpt(ctx, 0, h_a[0], d_noise, nullptr, w.pos, w.mom);

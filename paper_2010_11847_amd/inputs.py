@@ -60,6 +60,7 @@ class Workload:
     split_rs: float = 0.0
     split_mode: int = SPLIT_NONE
     lattice_shift: float = 0.0   # particle lattice offset from mesh nodes, in cells
+    pyramid_levels: int = 0      # 0: single-grid force; f: two-level pyramid force, grid n_mesh / 2^f
 
     @property
     def n_particles(self) -> int:
