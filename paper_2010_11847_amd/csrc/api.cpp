@@ -387,7 +387,7 @@ struct pm_ctx {
         if (last) {
           nx = out;
         } else {
-          nx.kind = pmk::PYR_PLAIN;
+          nx.kind = pmk::PYR_SEPARATE;
           nx.nx = in.nx;
           nx.ny = in.ny;
           nx.nz = in.nz;
@@ -415,23 +415,23 @@ struct pm_ctx {
     const int lv = cfg.pyramid_levels;
     const size_t half = (size_t)ng * ng * ng / 2;
     pmk::PyrField fine1, coarse1;
-    fine1.kind = pmk::PYR_BLOCKED;
+    fine1.kind = pmk::PYR_SEPARATE;
     fine1.p[0] = mesh[0].r;
     fine1.nx = fine1.ny = fine1.nz = (int)ng;
-    coarse1.kind = pmk::PYR_BLOCKED;
+    coarse1.kind = pmk::PYR_SEPARATE;
     coarse1.p[0] = coarse[0].r;
     coarse1.nx = coarse1.ny = coarse1.nz = nc;
     float* scr_d[1] = {mesh[1].r};
     timed(PC_PYR_REDUCE, [&] { pyr_chain(false, 1, fine1, coarse1, lv, scr_d, half, pmk::PYR_STORE, nullptr, 0.f); });
     force_on(tc, coarse, force_c, nc, g / ((double)nc * nc * nc) * (double)(1 << lv), 0, 0, PC_PYR_COARSE);
     force_on(tm, mesh, force_i, ng, g / ((double)ng * ng * ng), 0, 0, -1);
-    // D = F_L - REDUCE(F_S) on the coarse grid (three plain channels in the
-    // now idle coarse fields), then F_S += EXPAND(D)
+    // D = F_L - REDUCE(F_S) on the coarse grid (three channels in the now
+    // idle coarse fields), then F_S += EXPAND(D)
     pmk::PyrField fs, dc;
     fs.kind = pmk::PYR_INTERLEAVED;
     fs.p[0] = force_i;
     fs.nx = fs.ny = fs.nz = (int)ng;
-    dc.kind = pmk::PYR_PLAIN;
+    dc.kind = pmk::PYR_SEPARATE;
     for (int c = 0; c < 3; ++c) dc.p[c] = coarse[c].r;
     dc.nx = dc.ny = dc.nz = nc;
     float* scr3[3] = {mesh[0].r, mesh[1].r, mesh[2].r};

@@ -5,15 +5,17 @@
 
 namespace pmk {
 
-// A 3-D field of up to three channels in one of the library's layouts:
-//   PYR_PLAIN       p[c] + (x * ny + y) * nz + z          (any power-of-2 dims)
-//   PYR_BLOCKED     p[c] + blk_real(x, y, z, n)           (cube, x-blocked)
-//   PYR_INTERLEAVED p[0] + 3 * blk_real(x, y, z, n) + c   (cube, three channels)
-enum PyrKind : int { PYR_PLAIN = 0, PYR_BLOCKED = 1, PYR_INTERLEAVED = 2 };
+// A 3-D field of up to three channels, x-blocked by 8 like every mesh of the
+// library, with power-of-2 dims (nx >= 8):
+//   PYR_SEPARATE    p[c] + xoff(x, y, z)
+//   PYR_INTERLEAVED p[0] + 3 * xoff(x, y, z) + c
+// xoff(x, y, z) = (((x / 8) * ny + y) * nz + z) * 8 + x % 8, which for a cube
+// is blk_real.  All passes walk their destination in this memory order.
+enum PyrKind : int { PYR_SEPARATE = 0, PYR_INTERLEAVED = 1 };
 
 struct PyrField {
   float* p[3] = {nullptr, nullptr, nullptr};
-  int kind = PYR_PLAIN;
+  int kind = PYR_SEPARATE;
   int nx = 0, ny = 0, nz = 0;
 };
 

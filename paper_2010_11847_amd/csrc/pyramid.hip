@@ -7,7 +7,9 @@
 // its destination with 7 (REDUCE) or 4 (EXPAND) taps along the axis, the
 // neighbouring taps served from cache: HBM-bound at one read of the source
 // and one write of the destination.  Boundaries wrap (one device holds the
-// whole periodic mesh); coarse cell i sits on fine cell 2 i.
+// whole periodic mesh); coarse cell i sits on fine cell 2 i.  Every field,
+// intermediates included, is x-blocked by 8, so a wave's lanes walk
+// consecutive addresses of both source and destination whatever the axis.
 #include "layout.h"
 #include "pyramid.h"
 
@@ -27,13 +29,16 @@ __device__ __forceinline__ float bw(int t) {
 }
 
 struct Dims {
-  int lx, ly, lz;   // log2 of the destination dims
+  int ly, lz;   // log2 of the destination's ny, nz
 };
 
+__device__ __forceinline__ long xoff(int x, int y, int z, int ny, int nz) {
+  return ((((long)(x >> 3) * ny + y) * nz + z) << 3) + (x & 7);
+}
+
 __device__ __forceinline__ long pf_off(const PyrField& f, int c, int x, int y, int z) {
-  if (f.kind == PYR_PLAIN) return ((long)x * f.ny + y) * f.nz + z;
-  if (f.kind == PYR_BLOCKED) return blk_real(x, y, z, f.nx);
-  return 3 * blk_real(x, y, z, f.nx) + c;
+  const long e = xoff(x, y, z, f.ny, f.nz);
+  return f.kind == PYR_SEPARATE ? e : 3 * e + c;
 }
 
 __device__ __forceinline__ float pf_load(const PyrField& f, int c, int x, int y, int z) {
@@ -48,14 +53,10 @@ __global__ __launch_bounds__(kThreads) void k_pyr_pass(PyrField src, PyrField ds
   for (long e = (long)blockIdx.x * kThreads + threadIdx.x; e < total; e += stride) {
     // destination coordinates in its memory order (consecutive threads,
     // consecutive addresses)
-    int x, y, z;
-    if (dst.kind == PYR_PLAIN) {
-      z = (int)(e & ((1L << dd.lz) - 1));
-      y = (int)((e >> dd.lz) & ((1L << dd.ly) - 1));
-      x = (int)(e >> (dd.lz + dd.ly));
-    } else {
-      blk_real_xyz(e, dd.lx, x, y, z);
-    }
+    const long r = e >> 3;
+    const int z = (int)(r & ((1L << dd.lz) - 1));
+    const int y = (int)((r >> dd.lz) & ((1L << dd.ly) - 1));
+    const int x = (int)(((r >> (dd.lz + dd.ly)) << 3) + (e & 7));
     const int o = AXIS == 0 ? x : (AXIS == 1 ? y : z);
     const int nin = AXIS == 0 ? src.nx : (AXIS == 1 ? src.ny : src.nz);
     float acc[CH];
@@ -90,7 +91,7 @@ __global__ __launch_bounds__(kThreads) void k_pyr_pass(PyrField src, PyrField ds
       if (mode == PYR_STORE)
         *dp = acc[c];
       else if (mode == PYR_COMBINE)
-        *dp = alpha * aux[3 * blk_real(x, y, z, dst.nx) + c] - acc[c];
+        *dp = alpha * aux[3 * xoff(x, y, z, dst.ny, dst.nz) + c] - acc[c];
       else
         *dp += acc[c];
     }
@@ -114,7 +115,7 @@ void launch_axis(int ch, const PyrField& src, const PyrField& dst, Dims dd, int 
 
 void launch_pyr_pass(bool expand, int axis, int ch, const PyrField& src, const PyrField& dst, int mode,
                      const float* aux, float alpha, hipStream_t s) {
-  const Dims dd{__builtin_ctz(dst.nx), __builtin_ctz(dst.ny), __builtin_ctz(dst.nz)};
+  const Dims dd{__builtin_ctz(dst.ny), __builtin_ctz(dst.nz)};
   if (expand) {
     if (axis == 0) launch_axis<true, 0>(ch, src, dst, dd, mode, aux, alpha, s);
     else if (axis == 1) launch_axis<true, 1>(ch, src, dst, dd, mode, aux, alpha, s);
