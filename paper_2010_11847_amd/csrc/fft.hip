@@ -186,6 +186,7 @@ struct ColPass {
   float2* plane[3];
   ColGeom gm, gp;
   int nb_main;
+  int ntiles;   // main + plane tiles per field
 };
 
 template <int N, int M, int DIR, bool BLK>
@@ -1144,7 +1145,8 @@ void launch_cols(float2* const* dm, float2* const* dq, int nf, ColGeom gm, int n
   p.gm = gm;
   p.gp = gp;
   p.nb_main = nbm * gm.ntc;
-  dim3 grid(p.nb_main + nbp * gp.ntc, nf);
+  p.ntiles = p.nb_main + nbp * gp.ntc;
+  dim3 grid(p.ntiles, nf);
   hipLaunchKernelGGL((k_fft_cols<N, M, DIR, BLK>), grid, dim3(kThreads), 0, s, p, tw);
 }
 
