@@ -355,7 +355,6 @@ __device__ __forceinline__ uint32_t slot_key(int slot, int rx, int ry, int rz, c
 constexpr int kReadoutPPT = 1;
 constexpr int kSlots = 27 * 8;
 
-
 __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
   constexpr int PPT = kReadoutPPT;
   constexpr int kWaves = kThreads / 64;
