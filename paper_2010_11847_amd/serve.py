@@ -72,7 +72,7 @@ class Completion:
 
 def poisson_trace(n: int, rate: float, seed: int, mix=None, max_steps: int = 10, min_steps: int = 5,
                   box_per_particle: float = 2.0) -> List[SimRequest]:
-    """Seeded Poisson arrivals with the serving mix of the spec config:
+    """Seeded Poisson arrivals with the benchmark's serving mix:
     60% forward 64^3 on 64^3, 30% forward + gradient 128^3 on 128^3, 10%
     forward 256^3 on 512^3; steps uniform in [min_steps, max_steps]; box =
     box_per_particle Mpc/h per lattice spacing; request seed = 1000 + id."""

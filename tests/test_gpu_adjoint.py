@@ -50,10 +50,13 @@ def gpu_run_and_grad(w, noise, target):
 
 
 def record(name, value):
+    """Keep a measured error; written to $PM_METRICS_DIR/adjoint_metrics.json when set."""
     METRICS[name] = value
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open("gpurun_out/adjoint_metrics.json", "w") as fh:
-        json.dump(METRICS, fh, indent=1)
+    out = os.environ.get("PM_METRICS_DIR")
+    if out:
+        os.makedirs(out, exist_ok=True)
+        with open(os.path.join(out, "adjoint_metrics.json"), "w") as fh:
+            json.dump(METRICS, fh, indent=1)
 
 
 @pytest.mark.parametrize("n_mesh,n_part,steps", [(32, 16, 3), (64, 32, 5), (128, 64, 5)])

@@ -1,6 +1,6 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
-Tolerances (spec bar): relative 1e-5 (norm-wise) on painted density
+Tolerances: relative 1e-5 (norm-wise) on painted density
 and forces per step, positions rms < 1e-3 cell after a full run.  FFTs and
 spectra are compared at the float32 rounding level of the transform.
 """
