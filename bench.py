@@ -250,12 +250,18 @@ def serving_section(n_requests, rate=20.0, seed=5, budget_gb=64.0, slots=4):
     print(f"[bench] serving burst continuous {cb_sat}", file=sys.stderr, flush=True)
     fifo_sat = serve.serve_fifo(burst, ex, realtime=True).summary()
     print(f"[bench] serving burst fifo {fifo_sat}", file=sys.stderr, flush=True)
+    # the same burst with every step launched kernel by kernel
+    ex_eager = serve.GpuExecutor(keep_results=False, graphs=False)
+    serve.serve(warm, ex_eager, budget, slots, realtime=False)
+    cb_eager = serve.serve(burst, ex_eager, budget, slots, realtime=True).summary()
+    print(f"[bench] serving burst continuous, no graphs {cb_eager}", file=sys.stderr, flush=True)
+    del ex_eager
     grad = [r for r in trace if r.with_grad]
     return {"requests": n_requests, "rate_per_s": rate, "arrival_seed": seed, "hbm_budget_gb": budget_gb,
             "slots_per_class": slots, "grad_requests": len(grad),
             "mix": "60% fwd 64^3/64^3, 30% fwd+grad 128^3/128^3, 10% fwd 256^3/512^3, 5-10 steps",
             "poisson": {"continuous": cb, "fifo": fifo},
-            "burst": {"continuous": cb_sat, "fifo": fifo_sat}}
+            "burst": {"continuous": cb_sat, "continuous_no_graphs": cb_eager, "fifo": fifo_sat}}
 
 
 def main():

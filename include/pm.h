@@ -167,7 +167,7 @@ int pm_kdk_step(pm_ctx* ctx, float* d_pos, float* d_mom, float* d_force,
  * d_pos, d_mom: [n_part^3][3] in/out, lattice order.  d_ckpt: NULL or
  * [n_a][2][n_part^3][3] receives (x, p) at every a[i] (the adjoint's
  * checkpoints).  d_delta_final: NULL or [n_mesh^3] receives the overdensity
- * painted from the final positions. */
+ * painted from the final positions.  At most 65536 steps (PM_EINVAL). */
 int pm_run(pm_ctx* ctx, const double* h_a, int n_a, float* d_pos, float* d_mom,
            float* d_ckpt, float* d_delta_final);
 
@@ -242,6 +242,16 @@ int pm_rfft(pm_ctx* ctx, const float* d_real, float* d_spec);
  * imaginary parts of the kz = 0 and kz = n/2 planes after the x and y
  * inverse transforms are ignored. d_spec is left unchanged. */
 int pm_irfft(pm_ctx* ctx, const float* d_spec, float* d_real);
+
+/* Run the step loop of pm_run_advance (and so pm_run) as one captured HIP
+ * graph per step (two graphs per context, one per ping-pong buffer, built on
+ * first use and kept until the particle count or checkpointing changes):
+ * one launch per step instead of about fifteen, for small meshes where
+ * launches dominate.  The step's factors and checkpoint slot live in device
+ * memory, so replays need no new parameters.  Needs a non-default stream
+ * (PM_EHIP at the first advance otherwise); ignored while profiling.
+ * enable = 0 drops the graphs.  Results are identical to the eager loop. */
+int pm_use_graphs(pm_ctx* ctx, int enable);
 
 /* Optional per-kernel-class timing with HIP events recorded on the
  * context's stream around every kernel the library enqueues (measurement

@@ -62,6 +62,7 @@ _SIGS = {
     "pm_recon_step": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int, C.c_void_p, C.c_double, C.c_void_p,
                                 C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
                                 C.c_void_p, C.c_size_t, C.POINTER(C.c_double)]),
+    "pm_use_graphs": (C.c_int, [C.c_void_p, C.c_int]),
     "pm_rfft": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "pm_irfft": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "pm_profile": (C.c_int, [C.c_void_p, C.c_int]),

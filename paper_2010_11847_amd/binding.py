@@ -195,6 +195,9 @@ class PMContext:
         self._check(self.lib.pm_irfft(self.ctx, _ptr(spec), _ptr(real)), "pm_irfft")
         return real
 
+    def pm_use_graphs(self, enable: bool):
+        self._check(self.lib.pm_use_graphs(self.ctx, int(enable)), "pm_use_graphs")
+
     def pm_profile(self, enable: bool):
         self._check(self.lib.pm_profile(self.ctx, int(enable)), "pm_profile")
 

@@ -25,6 +25,7 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr size_t kAlign = 256;
+constexpr int kMaxSteps = 65536;   // steps per run (the device step table)
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -66,6 +67,7 @@ struct Layout {
   size_t count = 0, off = 0, bsum = 0;
   size_t pw_partial = 0, pw_out = 0;
   size_t misc = 0;   // small device words (the adjoint paint's max |weight|)
+  size_t steps = 0;  // a run's step loop: counter, checkpoint base, factor table
   size_t tab_coarse = 0, coarse[3] = {0, 0, 0}, force_c = 0;   // pyramid coarse grid
   size_t lat0 = 0;   // LPT lattice fields alias the mesh + particle region
   size_t total = 0;
@@ -137,6 +139,7 @@ Layout make_layout(const pm_config* c) {
   L.pw_partial = take((size_t)pmk::power_partial_doubles(L.n_bins_max) * 8);
   L.pw_out = take((size_t)3 * L.n_bins_max * 8);
   L.misc = take(256);
+  L.steps = take(256 + (size_t)kMaxSteps * 16);
   const long nc = c->pyramid_levels > 0 ? ng >> c->pyramid_levels : 0;
   if (nc) L.tab_coarse = take(fft_table_bytes(nc));
   const size_t region = o;
@@ -261,6 +264,24 @@ struct pm_ctx {
   Field coarse[3];
   float* force_c = nullptr;   // interleaved coarse force, fine-cell units
   uint32_t* misc = nullptr;   // small device words
+  // the step loop of a run: step counter, checkpoint base and per-step
+  // factors in device memory, and the captured graphs of one step starting
+  // from either ping-pong buffer
+  uint32_t* step_ctr = nullptr;
+  float** ckpt_base_dev = nullptr;
+  float4* step_tab = nullptr;
+  bool use_graphs = false;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  long g_np = -1;
+  bool g_ckpt = false;
+  void drop_graphs() {
+    for (auto& g : gexec)
+      if (g) {
+        (void)hipGraphExecDestroy(g);   // nothing to report to: the graph is rebuilt on demand
+        g = nullptr;
+      }
+  }
+  ~pm_ctx() { drop_graphs(); }
   float* pos_s[2] = {};
   float* mom_s[2] = {};
   uint32_t* id_s[2] = {};
@@ -274,6 +295,7 @@ struct pm_ctx {
     bool active = false;
     int ns = 0, step = 0, cur = 0;
     std::vector<double> k1, dr, k2;
+    std::vector<float4> tab;   // host copy of the device step table
     float *pos = nullptr, *mom = nullptr, *ckpt = nullptr;
   } run;
 
@@ -519,6 +541,9 @@ int pm_create(const pm_config* cfg, void* d_workspace, size_t bytes, void* strea
   }
   c->force_i = reinterpret_cast<float*>(w + L.force_i);
   c->misc = reinterpret_cast<uint32_t*>(w + L.misc);
+  c->step_ctr = reinterpret_cast<uint32_t*>(w + L.steps);
+  c->ckpt_base_dev = reinterpret_cast<float**>(w + L.steps + 64);
+  c->step_tab = reinterpret_cast<float4*>(w + L.steps + 256);
   c->nc = cfg->pyramid_levels > 0 ? c->ng >> cfg->pyramid_levels : 0;
   if (c->nc) {
     for (int i = 0; i < 3; ++i) {
@@ -726,12 +751,22 @@ int pm_run_begin(pm_ctx* ctx, const double* h_a, int n_a, float* d_pos, float* d
   r.dr.resize(r.ns);
   r.k2.resize(r.ns);
   c.cosmo.kdk_factors(h_a, n_a, r.k1.data(), r.dr.data(), r.k2.data());
+  if (r.ns > kMaxSteps) return c.fail(PM_EINVAL, "at most 65536 steps per run");
+  r.tab.resize(r.ns);
+  for (int i = 0; i < r.ns; ++i)
+    r.tab[i] = make_float4(i ? (float)r.k2[i - 1] : 0.f, (float)r.k1[i], (float)r.dr[i], 0.f);
   r.pos = d_pos;
   r.mom = d_mom;
   r.ckpt = d_ckpt;
   r.cur = 0;
   r.step = 0;
   const long np = c.np3;
+  if (r.ns > 0 && (hipMemcpyAsync(c.step_tab, r.tab.data(), (size_t)r.ns * sizeof(float4), hipMemcpyHostToDevice,
+                                  c.stream) != hipSuccess ||
+                   hipMemcpyAsync(c.ckpt_base_dev, &r.ckpt, sizeof(float*), hipMemcpyHostToDevice, c.stream) !=
+                       hipSuccess))
+    return c.check("pm_run_begin");
+  pmk::launch_fill_u32(c.step_ctr, 1, 0u, c.stream);
   c.sort(d_pos, d_mom, nullptr, np, r.cur);
   c.paint(r.cur, np, c.mesh[0].r);
   c.force_meshes();
@@ -745,25 +780,49 @@ int pm_run_advance(pm_ctx* ctx, int max_steps, int* h_remaining) {
   auto& r = c.run;
   if (!r.active) return c.fail(PM_ESTATE, "no run in progress");
   const long np = c.np3;
-  const size_t ck = (size_t)np * 3;
-  for (int k = 0; k < max_steps && r.step < r.ns; ++k) {
-    const int i = r.step;
+  // one step from ping-pong buffer cur; its factors and checkpoint slot come
+  // from the device step table at the device step counter
+  auto enqueue_step = [&](int cur) {
     c.timed(PC_FILL, [&] { pmk::launch_fill_u32(c.count, c.L.n_keys, 0u, c.stream); });
-    pmk::ReadoutArgs a = c.readout_args(r.cur, np);
-    a.flags = pmk::RO_KICK | pmk::RO_DRIFT | pmk::RO_WRITE_SORTED | pmk::RO_KEYS;
-    a.kick_a = i ? (float)r.k2[i - 1] : 0.f;
-    a.kick_b = (float)r.k1[i];
-    a.drift = (float)r.dr[i];
-    if (r.ckpt) {
-      a.flags |= pmk::RO_CKPT;
-      a.ckpt_x = r.ckpt + (2 * (size_t)i) * ck;
-      a.ckpt_p = r.ckpt + (2 * (size_t)i + 1) * ck;
-    }
+    pmk::ReadoutArgs a = c.readout_args(cur, np);
+    a.flags = pmk::RO_KICK | pmk::RO_DRIFT | pmk::RO_WRITE_SORTED | pmk::RO_KEYS | (r.ckpt ? pmk::RO_CKPT : 0);
+    a.steps = c.step_tab;
+    a.step_i = c.step_ctr;
+    a.ckpt_base = c.ckpt_base_dev;
+    a.ckpt_stride = np * 3;
     c.readout(a);
-    c.finish_sort(c.pos_s[r.cur], c.mom_s[r.cur], c.id_s[r.cur], np, 1 - r.cur);
-    r.cur = 1 - r.cur;
-    c.paint(r.cur, np, c.mesh[0].r);
+    c.finish_sort(c.pos_s[cur], c.mom_s[cur], c.id_s[cur], np, 1 - cur);
+    c.paint(1 - cur, np, c.mesh[0].r);
     c.force_meshes();
+    pmk::launch_step_inc(c.step_ctr, c.stream);
+  };
+  const bool graphs = c.use_graphs && !c.prof.on;
+  if (graphs && (c.g_np != np || c.g_ckpt != (r.ckpt != nullptr))) {
+    c.drop_graphs();
+    c.g_np = np;
+    c.g_ckpt = r.ckpt != nullptr;
+  }
+  for (int k = 0; k < max_steps && r.step < r.ns; ++k) {
+    if (graphs) {
+      hipGraphExec_t& ge = c.gexec[r.cur];
+      if (!ge) {
+        if (hipStreamBeginCapture(c.stream, hipStreamCaptureModeRelaxed) != hipSuccess)
+          return c.fail(PM_EHIP, "pm_run_advance: stream capture could not start (graphs need a non-default stream)");
+        enqueue_step(r.cur);
+        hipGraph_t g = nullptr;
+        const hipError_t e1 = hipStreamEndCapture(c.stream, &g);
+        const hipError_t e2 = e1 == hipSuccess ? hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) : e1;
+        if (g) (void)hipGraphDestroy(g);   // the instantiated graph keeps what it needs
+        if (e2 != hipSuccess) {
+          ge = nullptr;
+          return c.fail(PM_EHIP, std::string("pm_run_advance: graph capture failed: ") + hipGetErrorString(e2));
+        }
+      }
+      if (hipGraphLaunch(ge, c.stream) != hipSuccess) return c.check("pm_run_advance");
+    } else {
+      enqueue_step(r.cur);
+    }
+    r.cur = 1 - r.cur;
     ++r.step;
   }
   if (h_remaining) *h_remaining = r.ns - r.step;
@@ -1054,6 +1113,13 @@ int pm_irfft(pm_ctx* ctx, const float* d_spec, float* d_real) {
   pmk::fft_c2r_yz(c.tm, &c.mesh[0], 1, c.stream);
   pmk::launch_relayout(c.mesh[0].r, d_real, c.ng, false, c.stream);
   return c.check("pm_irfft");
+}
+
+int pm_use_graphs(pm_ctx* ctx, int enable) {
+  if (!ctx) return PM_EINVAL;
+  ctx->use_graphs = enable != 0;
+  if (!ctx->use_graphs) ctx->drop_graphs();
+  return PM_OK;
 }
 
 int pm_profile(pm_ctx* ctx, int enable) {

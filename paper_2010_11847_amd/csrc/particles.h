@@ -76,6 +76,14 @@ struct ReadoutArgs {
   uint32_t* key_out = nullptr;
   uint32_t* rank_out = nullptr;
   uint32_t* count = nullptr;
+  // A run's step loop reads its factors from device memory, so that one
+  // captured graph serves every step: at i = *step_i, steps[i] = {kick_a,
+  // kick_b, drift, 0} and, with RO_CKPT, the checkpoint pair starts at
+  // *ckpt_base + 2 i ckpt_stride floats.  steps == null: the fields above.
+  const float4* steps = nullptr;
+  const uint32_t* step_i = nullptr;
+  float* const* ckpt_base = nullptr;
+  long ckpt_stride = 0;
 };
 
 struct PowerArgs {
@@ -106,6 +114,8 @@ void launch_scatter(const ScatterArgs& a, hipStream_t s);
 void launch_paint(const float* pos_sorted, const uint32_t* off, const TileGeom& g, float* out, float scale,
                   float offset, bool std_layout, hipStream_t s);
 void launch_readout(const ReadoutArgs& a, hipStream_t s);
+// *ctr += 1 (the step counter of a run's device-side step loop)
+void launch_step_inc(uint32_t* ctr, hipStream_t s);
 // *bits = bit pattern of max_i |v_i| over n floats
 void launch_absmax(const float* v, long n, uint32_t* bits, hipStream_t s);
 // x-blocked paint of signed masses wts[3 id + comp] * k (the adjoint's

@@ -366,6 +366,19 @@ __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
   const long j0 = chunk * (long)(kThreads * PPT);
   const bool keys = (a.flags & RO_KEYS) != 0;
   const int lane = threadIdx.x & 63;
+  float kick_a = a.kick_a, kick_b = a.kick_b, drift = a.drift;
+  float *ckpt_x = a.ckpt_x, *ckpt_p = a.ckpt_p;
+  if (a.steps) {   // uniform: the factors of step *step_i
+    const uint32_t si = *a.step_i;
+    const float4 f = a.steps[si];
+    kick_a = f.x;
+    kick_b = f.y;
+    drift = f.z;
+    if (a.flags & RO_CKPT) {
+      ckpt_x = *a.ckpt_base + 2 * (long)si * a.ckpt_stride;
+      ckpt_p = ckpt_x + a.ckpt_stride;
+    }
+  }
   uint32_t* cnt = slot_cnt[threadIdx.x >> 6];
   uint32_t* sbase = slot_base[threadIdx.x >> 6];
   if (keys)
@@ -434,22 +447,22 @@ __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
     }
     if (a.flags & RO_KICK) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) p[u][d] += F[u][d] * a.kick_a;
+      for (int d = 0; d < 3; ++d) p[u][d] += F[u][d] * kick_a;
     }
     if (valid[u] && (a.flags & RO_CKPT)) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        a.ckpt_x[3 * (long)id[u] + d] = x[u][d];
-        a.ckpt_p[3 * (long)id[u] + d] = p[u][d];
+        ckpt_x[3 * (long)id[u] + d] = x[u][d];
+        ckpt_p[3 * (long)id[u] + d] = p[u][d];
       }
     }
     if (a.flags & RO_KICK) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) p[u][d] += F[u][d] * a.kick_b;
+      for (int d = 0; d < 3; ++d) p[u][d] += F[u][d] * kick_b;
     }
     if (a.flags & RO_DRIFT) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) x[u][d] = wrap_pos(x[u][d] + p[u][d] * a.drift, nf);
+      for (int d = 0; d < 3; ++d) x[u][d] = wrap_pos(x[u][d] + p[u][d] * drift, nf);
     }
     if (!valid[u]) continue;
     if (a.flags & RO_WRITE_SORTED) {
@@ -511,6 +524,10 @@ __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
 #pragma unroll
   for (int u = 0; u < PPT; ++u)
     if (valid[u]) a.rank_out[jj[u]] = rank[u] + (slot[u] >= 0 ? sbase[slot[u]] : 0u);
+}
+
+__global__ void k_step_inc(uint32_t* ctr) {
+  if (threadIdx.x == 0) atomicAdd(ctr, 1u);
 }
 
 // elementwise kick + drift with a given per-particle force (first half of a
@@ -733,6 +750,10 @@ void launch_readout(const ReadoutArgs& a, hipStream_t s) {
   const long per = (long)kThreads * kReadoutPPT;
   const int grid = (int)((a.np + per - 1) / per);
   hipLaunchKernelGGL(k_readout, dim3(grid), dim3(kThreads), 0, s, a);
+}
+
+void launch_step_inc(uint32_t* ctr, hipStream_t s) {
+  hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(64), 0, s, ctr);
 }
 
 void launch_kick_drift(float* pos, float* mom, const float* f, long np, float kick, float drift, float nmesh,

@@ -177,7 +177,8 @@ class _Job:
 class GpuExecutor:
     """Runs requests with the HIP library, one context and stream per slot."""
 
-    def __init__(self, device="cuda", cosmo: Optional[Cosmology] = None, keep_results: bool = True):
+    def __init__(self, device="cuda", cosmo: Optional[Cosmology] = None, keep_results: bool = True,
+                 graphs: bool = True):
         import torch
         from .binding import PMContext
         self.torch = torch
@@ -186,6 +187,7 @@ class GpuExecutor:
         self.cosmo = cosmo or Cosmology()
         self.slots: Dict[tuple, List[_Slot]] = {}
         self.keep_results = keep_results
+        self.graphs = graphs   # each slot replays one captured graph per step
         self._ws_bytes: Dict[tuple, int] = {}
 
     def workspace_bytes(self, req: SimRequest) -> int:
@@ -208,6 +210,8 @@ class GpuExecutor:
         stream = self.torch.cuda.Stream(device=self.device)
         with self.torch.cuda.stream(stream):
             ctx = self.PMContext(req.workload(self.cosmo), device=self.device, stream=stream)
+        if self.graphs:
+            ctx.pm_use_graphs(True)
         s = _Slot(ctx, stream)
         s.busy = True
         pool.append(s)

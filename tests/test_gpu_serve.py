@@ -56,3 +56,37 @@ def test_tiny_budget_and_oversize_rejection(gpu):
     assert len(ok) == 4 and rep.max_active == 1
     bad = [c for c in rep.completions if c.rid == 99][0]
     assert not bad.ok and "exceeds the HBM budget" in bad.error
+
+
+@pytest.mark.gpu
+def test_graph_step_loop_equals_eager(gpu):
+    """One captured graph per step, replayed over the run, with eager work on
+    the same stream between replays: every replay's result equals the eager
+    loop's bit for bit, with and without checkpoints, run after run."""
+    import torch
+    from dataclasses import replace
+    from paper_2010_11847_amd import inputs
+    from paper_2010_11847_amd.binding import PMContext
+    w = inputs.scaled(inputs.MEDIUM, 64, 32, n_steps=6)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        eager = PMContext(w, stream=s)
+        graph = PMContext(w, stream=s)
+        graph.pm_use_graphs(True)
+        n = w.n_part ** 3
+        for rep, with_ckpt in enumerate((False, True, True)):
+            pos0, mom0 = eager.pm_init_lpt(w.seed + rep, w.a_list[0])
+            outs = []
+            for c in (eager, graph):
+                pos, mom = pos0.clone(), mom0.clone()
+                ck = torch.empty((len(w.a_list), 2, n, 3), device="cuda") if with_ckpt else None
+                d = torch.empty((64, 64, 64), device="cuda")
+                c.pm_run_begin(w.a_list, pos, mom, ckpt=ck)
+                while c.pm_run_advance(1) > 0:
+                    torch.zeros(1000, device="cuda").add_(1.0)   # eager work between replays
+                c.pm_run_end(delta_final=d)
+                outs.append((pos, mom, ck, d))
+            torch.cuda.synchronize()
+            for a, b in zip(outs[0], outs[1]):
+                if a is not None:
+                    assert torch.equal(a, b)
