@@ -761,11 +761,12 @@ int pm_run_begin(pm_ctx* ctx, const double* h_a, int n_a, float* d_pos, float* d
   r.cur = 0;
   r.step = 0;
   const long np = c.np3;
-  if (r.ns > 0 && (hipMemcpyAsync(c.step_tab, r.tab.data(), (size_t)r.ns * sizeof(float4), hipMemcpyHostToDevice,
-                                  c.stream) != hipSuccess ||
-                   hipMemcpyAsync(c.ckpt_base_dev, &r.ckpt, sizeof(float*), hipMemcpyHostToDevice, c.stream) !=
-                       hipSuccess))
-    return c.check("pm_run_begin");
+  if (r.ns > 0) {
+    hipError_t e = hipMemcpyAsync(c.step_tab, r.tab.data(), (size_t)r.ns * sizeof(float4), hipMemcpyHostToDevice,
+                                  c.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c.ckpt_base_dev, &r.ckpt, sizeof(float*), hipMemcpyHostToDevice, c.stream);
+    if (e != hipSuccess) return c.fail(PM_EHIP, std::string("pm_run_begin: ") + hipGetErrorString(e));
+  }
   pmk::launch_fill_u32(c.step_ctr, 1, 0u, c.stream);
   c.sort(d_pos, d_mom, nullptr, np, r.cur);
   c.paint(r.cur, np, c.mesh[0].r);
@@ -818,7 +819,8 @@ int pm_run_advance(pm_ctx* ctx, int max_steps, int* h_remaining) {
           return c.fail(PM_EHIP, std::string("pm_run_advance: graph capture failed: ") + hipGetErrorString(e2));
         }
       }
-      if (hipGraphLaunch(ge, c.stream) != hipSuccess) return c.check("pm_run_advance");
+      const hipError_t e = hipGraphLaunch(ge, c.stream);
+      if (e != hipSuccess) return c.fail(PM_EHIP, std::string("pm_run_advance: ") + hipGetErrorString(e));
     } else {
       enqueue_step(r.cur);
     }
@@ -1052,9 +1054,9 @@ int pm_recon_step(pm_ctx* ctx, const double* h_a, int n_a, const float* d_data, 
   pmk::launch_adam(d_noise, w.gnoise, d_adam_m, d_adam_v, c.np3, (float)lr, (float)beta1, (float)beta2, (float)eps,
                    (float)(1.0 / (1.0 - std::pow(beta1, t))), (float)(1.0 / (1.0 - std::pow(beta2, t))), w.partials,
                    w.out + 1, c.stream);
-  if (hipMemcpyAsync(h_loss2, w.out, 2 * sizeof(double), hipMemcpyDeviceToHost, c.stream) != hipSuccess ||
-      hipStreamSynchronize(c.stream) != hipSuccess)
-    return c.check("pm_recon_step");
+  hipError_t e = hipMemcpyAsync(h_loss2, w.out, 2 * sizeof(double), hipMemcpyDeviceToHost, c.stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+  if (e != hipSuccess) return c.fail(PM_EHIP, std::string("pm_recon_step: ") + hipGetErrorString(e));
   return c.check("pm_recon_step");
 }
 
