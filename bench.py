@@ -150,9 +150,18 @@ def adjoint_section(names=("adj128_mesh256_box400", "pm512_mesh1024_box1024"), r
         once()
         fw, bw = zip(*[once() for _ in range(reps)])
         f, b = min(fw), min(bw)
+        # the same with the forward's force meshes kept for the reverse sweep
+        c.pm_set_force_ckpt(len(w.a_list))
+        once()
+        fw2, bw2 = zip(*[once() for _ in range(reps)])
+        c.pm_set_force_ckpt(0)
+        f2, b2 = min(fw2), min(bw2)
         out[name] = {"n_part": n, "n_mesh": m, "steps": w.n_steps, "forward_ckpt_ms": round(f, 2),
                      "adjoint_ms": round(b, 2), "gradients_per_s": round(1e3 / (f + b), 3),
-                     "adjoint_over_forward": round(b / f, 2)}
+                     "adjoint_over_forward": round(b / f, 2),
+                     "with_force_ckpt": {"forward_ms": round(f2, 2), "adjoint_ms": round(b2, 2),
+                                         "gradients_per_s": round(1e3 / (f2 + b2), 3),
+                                         "extra_hbm_gb": round(len(w.a_list) * m ** 3 * 12 / 1e9, 1)}}
         print(f"[bench] adjoint {name} {out[name]}", file=sys.stderr, flush=True)
         del c, noise, gd, ckpt, delta
         torch.cuda.empty_cache()

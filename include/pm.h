@@ -243,6 +243,18 @@ int pm_rfft(pm_ctx* ctx, const float* d_real, float* d_spec);
  * inverse transforms are ignored. d_spec is left unchanged. */
 int pm_irfft(pm_ctx* ctx, const float* d_spec, float* d_real);
 
+/* Keep the force meshes of a run instead of recomputing them in the adjoint
+ * (the capacity of the device's memory traded for a paint and four FFT passes
+ * per step of the reverse sweep).  d_fckpt: caller-owned device memory of
+ * n_slots * n_mesh^3 * 3 floats (internal layout, opaque); NULL or n_slots = 0
+ * switches it off.  A pm_run / pm_run_begin with n_a <= n_slots then writes
+ * the force mesh at a[j] into slot j, and a later pm_run_adjoint over the
+ * same scale factors (n_a <= n_slots) reads them: the caller keeps d_fckpt
+ * unchanged in between.  Runs with force checkpoints do not use graphs.
+ * PM_EINVAL for n_slots < 0 or a buffer with no slots; PM_ESTATE during a
+ * resumable run. */
+int pm_set_force_ckpt(pm_ctx* ctx, float* d_fckpt, int64_t n_slots);
+
 /* Run the step loop of pm_run_advance (and so pm_run) as one captured HIP
  * graph per step (two graphs per context, one per ping-pong buffer, built on
  * first use and kept until the particle count or checkpointing changes):

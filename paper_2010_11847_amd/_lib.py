@@ -63,6 +63,7 @@ _SIGS = {
                                 C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
                                 C.c_void_p, C.c_size_t, C.POINTER(C.c_double)]),
     "pm_use_graphs": (C.c_int, [C.c_void_p, C.c_int]),
+    "pm_set_force_ckpt": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
     "pm_rfft": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "pm_irfft": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "pm_profile": (C.c_int, [C.c_void_p, C.c_int]),

@@ -195,6 +195,22 @@ class PMContext:
         self._check(self.lib.pm_irfft(self.ctx, _ptr(spec), _ptr(real)), "pm_irfft")
         return real
 
+    def pm_set_force_ckpt(self, n_slots: int, fckpt: Optional[torch.Tensor] = None):
+        """Keep the force meshes of runs of up to n_slots scale factors for the
+        adjoint (0 switches it off).  Returns the buffer (allocated here when
+        not given); it must stay alive while in use."""
+        if n_slots <= 0:
+            self._check(self.lib.pm_set_force_ckpt(self.ctx, None, 0), "pm_set_force_ckpt")
+            self._fck = None
+            return None
+        m = self.workload.n_mesh
+        if fckpt is None:
+            fckpt = torch.empty(n_slots * m ** 3 * 3, dtype=torch.float32, device=self.device)
+        self._dev(fckpt, (n_slots * m ** 3 * 3,), name="fckpt")
+        self._check(self.lib.pm_set_force_ckpt(self.ctx, _ptr(fckpt), n_slots), "pm_set_force_ckpt")
+        self._fck = fckpt
+        return fckpt
+
     def pm_use_graphs(self, enable: bool):
         self._check(self.lib.pm_use_graphs(self.ctx, int(enable)), "pm_use_graphs")
 

@@ -258,6 +258,13 @@ struct pm_ctx {
   FftTables tm, tl;
   Field mesh[3];
   float* force_i = nullptr;   // interleaved force mesh, x-blocked [n/8][n][n][8][3]
+  float* cur_force = nullptr; // the force mesh the next readout reads (force_i or a checkpoint slot)
+  // caller-owned force-mesh checkpoints of a run: slot j holds the force
+  // mesh at a[j] (layout of force_i), so that the adjoint reads instead of
+  // recomputing them
+  float* fck = nullptr;
+  long fck_slots = 0;
+  float* fck_slot(int j) const { return fck + (size_t)j * ng * ng * ng * 3; }
   // pyramid: coarse grid of nc = ng / 2^levels cells per side
   int nc = 0;
   FftTables tc;
@@ -297,6 +304,7 @@ struct pm_ctx {
     std::vector<double> k1, dr, k2;
     std::vector<float4> tab;   // host copy of the device step table
     float *pos = nullptr, *mom = nullptr, *ckpt = nullptr;
+    bool fck = false;          // force meshes go to the checkpoint slots
   } run;
 
   // run f (which enqueues one kernel class) between two events when profiling
@@ -423,11 +431,14 @@ struct pm_ctx {
       }
   }
 
-  // force meshes from the overdensity in mesh[0].r (overwritten) into force_i
-  void force_meshes() {
+  // force meshes from the overdensity in mesh[0].r (overwritten) into out
+  // (default force_i); the next readout reads them
+  void force_meshes(float* out = nullptr) {
+    out = out ? out : force_i;
+    cur_force = out;
     const double g = 1.5 * cfg.cosmo.omega_m;
     if (!nc) {
-      force_on(tm, mesh, force_i, ng, g / ((double)ng * ng * ng), cfg.deconv_order, cfg.split_mode, -1);
+      force_on(tm, mesh, out, ng, g / ((double)ng * ng * ng), cfg.deconv_order, cfg.split_mode, -1);
       return;
     }
     // Algorithm 3 with one device holding the periodic mesh:
@@ -446,12 +457,12 @@ struct pm_ctx {
     float* scr_d[1] = {mesh[1].r};
     timed(PC_PYR_REDUCE, [&] { pyr_chain(false, 1, fine1, coarse1, lv, scr_d, half, pmk::PYR_STORE, nullptr, 0.f); });
     force_on(tc, coarse, force_c, nc, g / ((double)nc * nc * nc) * (double)(1 << lv), 0, 0, PC_PYR_COARSE);
-    force_on(tm, mesh, force_i, ng, g / ((double)ng * ng * ng), 0, 0, -1);
+    force_on(tm, mesh, out, ng, g / ((double)ng * ng * ng), 0, 0, -1);
     // D = F_L - REDUCE(F_S) on the coarse grid (three channels in the now
     // idle coarse fields), then F_S += EXPAND(D)
     pmk::PyrField fs, dc;
     fs.kind = pmk::PYR_INTERLEAVED;
-    fs.p[0] = force_i;
+    fs.p[0] = out;
     fs.nx = fs.ny = fs.nz = (int)ng;
     dc.kind = pmk::PYR_SEPARATE;
     for (int c = 0; c < 3; ++c) dc.p[c] = coarse[c].r;
@@ -470,7 +481,7 @@ struct pm_ctx {
     a.pos = pos_s[cur];
     a.mom = mom_s[cur];
     a.id = id_s[cur];
-    a.fi = force_i;
+    a.fi = cur_force ? cur_force : force_i;
     a.key_out = key;
     a.rank_out = rank;
     a.count = count;
@@ -768,9 +779,10 @@ int pm_run_begin(pm_ctx* ctx, const double* h_a, int n_a, float* d_pos, float* d
     if (e != hipSuccess) return c.fail(PM_EHIP, std::string("pm_run_begin: ") + hipGetErrorString(e));
   }
   pmk::launch_fill_u32(c.step_ctr, 1, 0u, c.stream);
+  r.fck = c.fck && n_a <= c.fck_slots;
   c.sort(d_pos, d_mom, nullptr, np, r.cur);
   c.paint(r.cur, np, c.mesh[0].r);
-  c.force_meshes();
+  c.force_meshes(r.fck ? c.fck_slot(0) : nullptr);
   r.active = true;
   return c.check("pm_run_begin");
 }
@@ -783,7 +795,7 @@ int pm_run_advance(pm_ctx* ctx, int max_steps, int* h_remaining) {
   const long np = c.np3;
   // one step from ping-pong buffer cur; its factors and checkpoint slot come
   // from the device step table at the device step counter
-  auto enqueue_step = [&](int cur) {
+  auto enqueue_step = [&](int cur, int i) {
     c.timed(PC_FILL, [&] { pmk::launch_fill_u32(c.count, c.L.n_keys, 0u, c.stream); });
     pmk::ReadoutArgs a = c.readout_args(cur, np);
     a.flags = pmk::RO_KICK | pmk::RO_DRIFT | pmk::RO_WRITE_SORTED | pmk::RO_KEYS | (r.ckpt ? pmk::RO_CKPT : 0);
@@ -794,10 +806,11 @@ int pm_run_advance(pm_ctx* ctx, int max_steps, int* h_remaining) {
     c.readout(a);
     c.finish_sort(c.pos_s[cur], c.mom_s[cur], c.id_s[cur], np, 1 - cur);
     c.paint(1 - cur, np, c.mesh[0].r);
-    c.force_meshes();
+    c.force_meshes(r.fck ? c.fck_slot(i + 1) : nullptr);
     pmk::launch_step_inc(c.step_ctr, c.stream);
   };
-  const bool graphs = c.use_graphs && !c.prof.on;
+  // (force checkpoints move the output every step: launched eagerly)
+  const bool graphs = c.use_graphs && !c.prof.on && !r.fck;
   if (graphs && (c.g_np != np || c.g_ckpt != (r.ckpt != nullptr))) {
     c.drop_graphs();
     c.g_np = np;
@@ -809,7 +822,7 @@ int pm_run_advance(pm_ctx* ctx, int max_steps, int* h_remaining) {
       if (!ge) {
         if (hipStreamBeginCapture(c.stream, hipStreamCaptureModeRelaxed) != hipSuccess)
           return c.fail(PM_EHIP, "pm_run_advance: stream capture could not start (graphs need a non-default stream)");
-        enqueue_step(r.cur);
+        enqueue_step(r.cur, r.step);
         hipGraph_t g = nullptr;
         const hipError_t e1 = hipStreamEndCapture(c.stream, &g);
         const hipError_t e2 = e1 == hipSuccess ? hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) : e1;
@@ -822,7 +835,7 @@ int pm_run_advance(pm_ctx* ctx, int max_steps, int* h_remaining) {
       const hipError_t e = hipGraphLaunch(ge, c.stream);
       if (e != hipSuccess) return c.fail(PM_EHIP, std::string("pm_run_advance: ") + hipGetErrorString(e));
     } else {
-      enqueue_step(r.cur);
+      enqueue_step(r.cur, r.step);
     }
     r.cur = 1 - r.cur;
     ++r.step;
@@ -889,15 +902,22 @@ int pm_run_adjoint(pm_ctx* ctx, const double* h_a, int n_a, const float* d_ckpt,
     pmk::launch_readout_grad1(c.pos_s[0], c.id_s[0], np, c.ng, d_grad_delta_final, (float)s, xbar, true,
                               c.stream);
   }
-  // reverse sweep over the force evaluation points x_ns ... x_0
+  // reverse sweep over the force evaluation points x_ns ... x_0; the force
+  // meshes come from the forward's checkpoints when it kept them
+  const bool use_fck = c.fck && n_a <= c.fck_slots;
   for (int j = ns; j >= 0; --j) {
     const double kj = (j < ns ? k1[j] : 0.0) + (j > 0 ? k2[j - 1] : 0.0);
     if (kj != 0.0) {
       c.sort(ckpt_x(j), nullptr, nullptr, np, 0);
-      c.paint(0, np, c.mesh[0].r);
-      c.force_meshes();
+      const float* fmesh = c.force_i;
+      if (use_fck) {
+        fmesh = c.fck_slot(j);
+      } else {
+        c.paint(0, np, c.mesh[0].r);
+        c.force_meshes();
+      }
       // term A: positions at which the force meshes are read out
-      pmk::launch_readout_grad3(c.pos_s[0], c.id_s[0], np, c.ng, c.force_i, pbar, (float)kj, xbar, c.stream);
+      pmk::launch_readout_grad3(c.pos_s[0], c.id_s[0], np, c.ng, fmesh, pbar, (float)kj, xbar, c.stream);
       // term B: positions that paint the density, through G^T
       pmk::launch_absmax(pbar, 3 * np, c.misc, c.stream);
       for (int d = 0; d < 3; ++d)
@@ -1115,6 +1135,14 @@ int pm_irfft(pm_ctx* ctx, const float* d_spec, float* d_real) {
   pmk::fft_c2r_yz(c.tm, &c.mesh[0], 1, c.stream);
   pmk::launch_relayout(c.mesh[0].r, d_real, c.ng, false, c.stream);
   return c.check("pm_irfft");
+}
+
+int pm_set_force_ckpt(pm_ctx* ctx, float* d_fckpt, int64_t n_slots) {
+  if (!ctx || n_slots < 0 || (d_fckpt && n_slots < 1)) return PM_EINVAL;
+  if (ctx->run.active) return ctx->fail(PM_ESTATE, "a resumable run is in progress");
+  ctx->fck = n_slots ? d_fckpt : nullptr;
+  ctx->fck_slots = d_fckpt ? n_slots : 0;
+  return PM_OK;
 }
 
 int pm_use_graphs(pm_ctx* ctx, int enable) {

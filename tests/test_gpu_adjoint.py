@@ -123,3 +123,26 @@ def test_adjoint_vs_central_fd(gpu):
     record("fd_max_rel_to_rms", err)
     record("fd_rel_norm", rel(got, refs))
     assert rel(got, refs) < 1e-3
+
+
+def test_adjoint_with_force_checkpoints_is_identical(gpu):
+    """Reading the forward's force meshes instead of recomputing them changes
+    nothing: paint and FFTs are deterministic, so the gradients are equal bit
+    for bit."""
+    from paper_2010_11847_amd.binding import PMContext
+    banner("adjoint with force checkpoints 64/32 5 steps")
+    w = inputs.scaled(inputs.ADJ_SMALL, 64, 32, n_steps=5)
+    c = PMContext(w)
+    noise = to_dev(white_noise(w.seed, 32))
+    gd = to_dev(np.random.default_rng(3).normal(size=(64, 64, 64)))
+    outs = []
+    for fck in (False, True):
+        c.pm_set_force_ckpt(len(w.a_list) if fck else 0)
+        pos, mom = c.pm_init_lpt(0, w.a_list[0], noise=noise)
+        ck = torch.empty((len(w.a_list), 2, 32 ** 3, 3), device="cuda")
+        c.pm_run(w.a_list, pos, mom, ckpt=ck)
+        gx, gp, gn = c.pm_run_adjoint(w.a_list, ck, noise=noise, grad_delta=gd)
+        outs.append((pos, mom, gx, gp, gn))
+    c.pm_set_force_ckpt(0)
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
