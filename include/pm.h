@@ -214,7 +214,9 @@ int pm_run_adjoint(pm_ctx* ctx, const double* h_a, int n_a, const float* d_ckpt,
  * before t = 1.  d_work: 256-byte aligned scratch of at least
  * pm_recon_work_bytes(ctx, n_a) bytes (checkpoints, state, residual).
  * h_loss2: out, {chi^2, sum w^2} at the noise before the update; the call
- * synchronises the stream to return them.  PM_EINVAL for NULL pointers,
+ * synchronises the stream to return them.  The work buffer also holds the
+ * run's force meshes (n_a * n_mesh^3 * 12 bytes), read back by the adjoint
+ * instead of recomputed.  PM_EINVAL for NULL pointers,
  * n_a < 2, sigma <= 0, t < 1, lr <= 0, beta outside [0, 1) or eps < 0;
  * PM_ENOMEM if work_bytes is too small; PM_ESTATE during a resumable run. */
 size_t pm_recon_work_bytes(const pm_ctx* ctx, int n_a);

@@ -1016,7 +1016,7 @@ int pm_run_adjoint(pm_ctx* ctx, const double* h_a, int n_a, const float* d_ckpt,
 // ---- MAP reconstruction (section 7) --------------------------------------
 namespace {
 struct ReconWork {
-  float *ckpt, *pos, *mom, *resid, *gnoise;
+  float *ckpt, *fck, *pos, *mom, *resid, *gnoise;
   double *partials, *out;
   size_t total;
 };
@@ -1031,6 +1031,7 @@ ReconWork recon_work(const pm_ctx& c, int n_a, char* base) {
   };
   const size_t st = (size_t)c.np3 * 3 * sizeof(float);
   w.ckpt = reinterpret_cast<float*>(take((size_t)n_a * 2 * st));
+  w.fck = reinterpret_cast<float*>(take((size_t)n_a * c.ng * c.ng * c.ng * 3 * sizeof(float)));
   w.pos = reinterpret_cast<float*>(take(st));
   w.mom = reinterpret_cast<float*>(take(st));
   w.resid = reinterpret_cast<float*>(take((size_t)c.ng * c.ng * c.ng * sizeof(float)));
@@ -1062,6 +1063,20 @@ int pm_recon_step(pm_ctx* ctx, const double* h_a, int n_a, const float* d_data, 
   if (work_bytes < w.total) return c.fail(PM_ENOMEM, "reconstruction work buffer too small");
   int st = pm_init_lpt(ctx, 0, h_a[0], d_noise, nullptr, w.pos, w.mom);
   if (st != PM_OK) return st;
+  // the run keeps its force meshes in the work buffer for the adjoint
+  float* const user_fck = c.fck;
+  const long user_slots = c.fck_slots;
+  c.fck = w.fck;
+  c.fck_slots = n_a;
+  struct Restore {
+    pm_ctx& c;
+    float* f;
+    long n;
+    ~Restore() {
+      c.fck = f;
+      c.fck_slots = n;
+    }
+  } restore{c, user_fck, user_slots};
   st = pm_run(ctx, h_a, n_a, w.pos, w.mom, w.ckpt, w.resid);
   if (st != PM_OK) return st;
   const long ncell = (long)c.ng * c.ng * c.ng;
