@@ -202,6 +202,14 @@ int pm_run_adjoint(pm_ctx* ctx, const double* h_a, int n_a, const float* d_ckpt,
                    const float* d_grad_delta_final, float* d_grad_pos, float* d_grad_mom,
                    float* d_grad_noise);
 
+/* The chi^2 term of section 7's posterior for a model overdensity against
+ * data, sum ((delta - data) / sigma)^2, into the device double *d_chi2
+ * (float64 sum in a fixed order), and its derivative 2 (delta - data) /
+ * sigma^2 into d_grad (may equal d_delta), the grad_delta of
+ * pm_run_adjoint.  Asynchronous on the context's stream.  All meshes
+ * [n_mesh^3] float32, C order.  PM_EINVAL for NULL pointers or sigma <= 0. */
+int pm_chi2(pm_ctx* ctx, const float* d_delta, const float* d_data, double sigma, float* d_grad, double* d_chi2);
+
 /* MAP reconstruction of the initial conditions from the final dark-matter
  * overdensity (section 7): minimise
  *   loss(w) = sum_cells ((delta_m(w) - delta_e) / sigma)^2 + sum_lattice w^2

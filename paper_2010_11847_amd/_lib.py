@@ -58,6 +58,7 @@ _SIGS = {
     "pm_run_end": (C.c_int, [C.c_void_p, C.c_void_p]),
     "pm_run_adjoint": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int, C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pm_chi2": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]),
     "pm_recon_work_bytes": (C.c_size_t, [C.c_void_p, C.c_int]),
     "pm_recon_step": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int, C.c_void_p, C.c_double, C.c_void_p,
                                 C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,

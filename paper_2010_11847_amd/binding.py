@@ -258,6 +258,18 @@ class PMContext:
         return gx, gp, gn
 
     # ---- MAP reconstruction ----------------------------------------------------
+    def pm_chi2(self, delta, data, sigma: float, grad=None):
+        """(chi^2 as a device float64 scalar, d chi^2 / d delta) of a model
+        overdensity against data; asynchronous on the context's stream."""
+        m = self.workload.n_mesh
+        self._dev(delta, (m, m, m), name="delta")
+        self._dev(data, (m, m, m), name="data")
+        grad = torch.empty_like(delta) if grad is None else grad
+        self._dev(grad, (m, m, m), name="grad")
+        chi2 = torch.empty((), dtype=torch.float64, device=self.device)
+        self._check(self.lib.pm_chi2(self.ctx, _ptr(delta), _ptr(data), sigma, _ptr(grad), _ptr(chi2)), "pm_chi2")
+        return chi2, grad
+
     def pm_recon_work_bytes(self, n_a: int) -> int:
         return int(self.lib.pm_recon_work_bytes(self.ctx, n_a))
 

@@ -68,6 +68,7 @@ struct Layout {
   size_t pw_partial = 0, pw_out = 0;
   size_t misc = 0;   // small device words (the adjoint paint's max |weight|)
   size_t steps = 0;  // a run's step loop: counter, checkpoint base, factor table
+  size_t red = 0;    // float64 partial sums of the chi^2 reduction
   size_t tab_coarse = 0, coarse[3] = {0, 0, 0}, force_c = 0;   // pyramid coarse grid
   size_t lat0 = 0;   // LPT lattice fields alias the mesh + particle region
   size_t total = 0;
@@ -140,6 +141,7 @@ Layout make_layout(const pm_config* c) {
   L.pw_out = take((size_t)3 * L.n_bins_max * 8);
   L.misc = take(256);
   L.steps = take(256 + (size_t)kMaxSteps * 16);
+  L.red = take((size_t)(pmk::kReducePartials + 2) * 8);
   const long nc = c->pyramid_levels > 0 ? ng >> c->pyramid_levels : 0;
   if (nc) L.tab_coarse = take(fft_table_bytes(nc));
   const size_t region = o;
@@ -277,6 +279,7 @@ struct pm_ctx {
   uint32_t* step_ctr = nullptr;
   float** ckpt_base_dev = nullptr;
   float4* step_tab = nullptr;
+  double* red = nullptr;      // chi^2 partial sums (kReducePartials) + result
   bool use_graphs = false;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   long g_np = -1;
@@ -555,6 +558,7 @@ int pm_create(const pm_config* cfg, void* d_workspace, size_t bytes, void* strea
   c->step_ctr = reinterpret_cast<uint32_t*>(w + L.steps);
   c->ckpt_base_dev = reinterpret_cast<float**>(w + L.steps + 64);
   c->step_tab = reinterpret_cast<float4*>(w + L.steps + 256);
+  c->red = reinterpret_cast<double*>(w + L.red);
   c->nc = cfg->pyramid_levels > 0 ? c->ng >> cfg->pyramid_levels : 0;
   if (c->nc) {
     for (int i = 0; i < 3; ++i) {
@@ -1043,6 +1047,15 @@ ReconWork recon_work(const pm_ctx& c, int n_a, char* base) {
 }
 }  // namespace
 
+int pm_chi2(pm_ctx* ctx, const float* d_delta, const float* d_data, double sigma, float* d_grad, double* d_chi2) {
+  if (!ctx || !d_delta || !d_data || !d_grad || !d_chi2) return PM_EINVAL;
+  pm_ctx& c = *ctx;
+  if (!(sigma > 0)) return c.fail(PM_EINVAL, "sigma must be > 0");
+  const long ncell = (long)c.ng * c.ng * c.ng;
+  pmk::launch_residual(d_delta, d_data, d_grad, ncell, (float)(1.0 / sigma), c.red, d_chi2, c.stream);
+  return c.check("pm_chi2");
+}
+
 size_t pm_recon_work_bytes(const pm_ctx* ctx, int n_a) {
   if (!ctx || n_a < 2) return 0;
   return recon_work(*ctx, n_a, nullptr).total;
@@ -1080,7 +1093,7 @@ int pm_recon_step(pm_ctx* ctx, const double* h_a, int n_a, const float* d_data, 
   st = pm_run(ctx, h_a, n_a, w.pos, w.mom, w.ckpt, w.resid);
   if (st != PM_OK) return st;
   const long ncell = (long)c.ng * c.ng * c.ng;
-  pmk::launch_residual(w.resid, d_data, ncell, (float)(1.0 / sigma), w.partials, w.out, c.stream);
+  pmk::launch_residual(w.resid, d_data, w.resid, ncell, (float)(1.0 / sigma), w.partials, w.out, c.stream);
   // the state buffers become the zeroed cotangent accumulators of the adjoint
   pmk::launch_fill_u32(reinterpret_cast<uint32_t*>(w.pos), c.np3 * 3, 0u, c.stream);
   pmk::launch_fill_u32(reinterpret_cast<uint32_t*>(w.mom), c.np3 * 3, 0u, c.stream);

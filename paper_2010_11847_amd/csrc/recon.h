@@ -11,9 +11,9 @@ namespace pmk {
 // this many doubles).
 constexpr int kReducePartials = 1024;
 
-// g = 2 (delta - data) / sigma^2 (in place over delta) and
+// g = 2 (delta - data) / sigma^2 into grad (which may be delta itself) and
 // *out = sum ((delta - data) / sigma)^2.
-void launch_residual(float* delta_to_grad, const float* data, long n, float inv_sigma, double* partials,
+void launch_residual(const float* delta, const float* data, float* grad, long n, float inv_sigma, double* partials,
                      double* out, hipStream_t s);
 
 // Adam on w with gradient g_like + 2 w (the white-noise prior), step

@@ -29,15 +29,15 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return t;
 }
 
-__global__ __launch_bounds__(kThreads) void k_residual(float* __restrict__ d, const float* __restrict__ data, long n,
-                                                       float inv_sigma, double* __restrict__ partials) {
+__global__ __launch_bounds__(kThreads) void k_residual(const float* d, const float* __restrict__ data, float* g,
+                                                       long n, float inv_sigma, double* __restrict__ partials) {
   __shared__ double red[kThreads / 64];
   double acc = 0.0;
   const long stride = (long)gridDim.x * kThreads;
   for (long i = (long)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride) {
     const float r = (d[i] - data[i]) * inv_sigma;
     acc += (double)r * (double)r;
-    d[i] = 2.f * r * inv_sigma;
+    g[i] = 2.f * r * inv_sigma;
   }
   const double t = block_sum(acc, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
@@ -80,10 +80,10 @@ int blocks_for(long n) {
 
 }  // namespace
 
-void launch_residual(float* delta_to_grad, const float* data, long n, float inv_sigma, double* partials,
+void launch_residual(const float* delta, const float* data, float* grad, long n, float inv_sigma, double* partials,
                      double* out, hipStream_t s) {
   const int nb = blocks_for(n);
-  hipLaunchKernelGGL(k_residual, dim3(nb), dim3(kThreads), 0, s, delta_to_grad, data, n, inv_sigma, partials);
+  hipLaunchKernelGGL(k_residual, dim3(nb), dim3(kThreads), 0, s, delta, data, grad, n, inv_sigma, partials);
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(kThreads), 0, s, partials, nb, out);
 }
 

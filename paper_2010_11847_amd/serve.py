@@ -250,8 +250,7 @@ class GpuExecutor:
                 gen = torch.Generator(device=self.device)
                 gen.manual_seed(req.seed + 2000)
                 target = torch.randn((m, m, m), generator=gen, device=self.device) * req.sigma
-                gdelta = (2.0 / req.sigma ** 2) * (delta - target)
-                loss = (((delta - target) / req.sigma) ** 2).sum()
+                loss, gdelta = ctx.pm_chi2(delta, target, req.sigma)
                 _, _, gn = ctx.pm_run_adjoint(t["a"], t["ckpt"], noise=t["noise"], grad_delta=gdelta)
                 out.update(loss=loss, grad_noise=gn)
             ev = torch.cuda.Event()

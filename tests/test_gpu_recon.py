@@ -79,3 +79,19 @@ def test_recon_rejects_bad_arguments(gpu):
         c.pm_recon_step(w.a_list, d, SIGMA, z.clone(), z.clone(), z.clone(), 0, 0.01)
     with pytest.raises(PMError):
         c.pm_recon_step(w.a_list, d, -1.0, z.clone(), z.clone(), z.clone(), 1, 0.01)
+
+
+@pytest.mark.gpu
+def test_chi2_matches_oracle(gpu):
+    from oracle import adjoint as A
+    w, _, _ = problem(32, 16, 2)
+    c = PMContext(w)
+    rng = np.random.default_rng(9)
+    d = rng.normal(size=(32, 32, 32)).astype(np.float32)
+    t = rng.normal(size=(32, 32, 32)).astype(np.float32)
+    chi2, g = c.pm_chi2(to_dev(d), to_dev(t), SIGMA)
+    d64, t64 = d.astype(np.float64), t.astype(np.float64)
+    assert float(chi2.item()) == pytest.approx(A.chi2(d64, t64, SIGMA), rel=1e-6)
+    np.testing.assert_allclose(to_np(g), 2.0 * (d64 - t64) / SIGMA ** 2, rtol=1e-5, atol=1e-4)
+    with pytest.raises(PMError):
+        c.pm_chi2(to_dev(d), to_dev(t), 0.0)
