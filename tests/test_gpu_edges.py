@@ -37,7 +37,8 @@ def test_single_particle_paint_and_zero_self_force(gpu):
 
 
 def test_lattice_has_no_force(gpu):
-    # particles on every node of a B = 2 lattice: uniform density, zero force
+    # particles on every node of a B = 2 lattice: each sits at a centre of
+    # symmetry of the painted density, so the force read out there vanishes
     banner("unperturbed lattice")
     c = PMContext(wl(32, 16))
     q = np.stack(np.meshgrid(*(np.arange(16) * 2.0,) * 3, indexing="ij"), -1).reshape(-1, 3).astype(np.float32)
