@@ -941,7 +941,7 @@ int pm_run_adjoint(pm_ctx* ctx, const double* h_a, int n_a, const float* d_ckpt,
       }
       op.out_c[0] = c.mesh[0].c();
       op.out_q[0] = c.mesh[0].q;
-      pmk::fft_x_fused(c.tm, c.mesh[0], op, c.stream);
+      pmk::fft_x_force_t(c.tm, c.mesh, op, c.stream);
       pmk::fft_c2r_yz(c.tm, &c.mesh[0], 1, c.stream);
       pmk::launch_readout_grad1(c.pos_s[0], c.id_s[0], np, c.ng, c.mesh[0].r, 1.f, xbar, false, c.stream);
     }

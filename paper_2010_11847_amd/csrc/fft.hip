@@ -990,7 +990,14 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_fused(FusedArgs a) {
 // per basis) this does one forward transform instead of one per basis and
 // keeps each tile's compute short; it moves one more read and write of the
 // spectrum.  N >= 64 (two-stage columns).
-enum XOpMode { XOP_SCALE = 0, XOP_OUT = 1 };
+// The transpose of the force (the adjoint's fan-in, OP_FORCE_T) in the same
+// style, with Y_d the forward-(z, y) spectra of its three inputs:
+//   T0 : forward x of D(w_y) Y_y + D(w_z) Y_z (both factors are constant
+//        along x), stored over Y_y;
+//   T1 : forward x of Y_x, times D(w_x), plus T0's result, times -i g(k),
+//        stored over Y_x;
+//   then an OUT launch of the identity inverts x in place.
+enum XOpMode { XOP_SCALE = 0, XOP_OUT = 1, XOP_T0 = 2, XOP_T1 = 3 };
 
 template <int N, int M, int MODE>
 __global__ __launch_bounds__(kThreads) void k_fft_x_op(FusedArgs a) {
@@ -999,7 +1006,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_op(FusedArgs a) {
   constexpr int IA = (M * R2 + kThreads - 1) / kThreads;
   constexpr int IB = (M * R1 + kThreads - 1) / kThreads;
   constexpr int SA = ColLds<N, M>::SA;
-  constexpr int DIR = MODE == XOP_SCALE ? -1 : 1;
+  constexpr int DIR = MODE == XOP_OUT ? 1 : -1;
   __shared__ float2 lds[ColLds<N, M>::size];
   int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int mode = tile >= a.nb_main ? 1 : 0;
@@ -1043,6 +1050,19 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_op(FusedArgs a) {
 #pragma unroll
       for (int j1 = 0; j1 < R1; ++j1)
         v[j1] = ok ? src[row_off<true>(R2 * j1 + j2, g.sn) + m * 8] : make_float2(0.f, 0.f);
+      if constexpr (MODE == XOP_T0) {
+        // D(w_y) Y_y + D(w_z) Y_z: src is Y_y, the second input Y_z
+        const float2* src2 = (mode == 0 ? op.in_c[1] : op.in_q[1]) + off;
+        float2 u[R1];
+#pragma unroll
+        for (int j1 = 0; j1 < R1; ++j1)
+          u[j1] = ok ? src2[row_off<true>(R2 * j1 + j2, g.sn) + m * 8] : make_float2(0.f, 0.f);
+        int ky, kz;
+        freq(m, ky, kz);
+        const float dy = t.dxy[ky], dz = t.dz[kz];
+#pragma unroll
+        for (int j1 = 0; j1 < R1; ++j1) v[j1] = make_float2(dy * v[j1].x + dz * u[j1].x, dy * v[j1].y + dz * u[j1].y);
+      }
 #pragma unroll
       for (int l1 = 1; l1 < R1; ++l1) asm volatile("" : "+v"(tw[l1]));
       if (scale_in) {
@@ -1068,7 +1088,55 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_op(FusedArgs a) {
       if (c0 + m < g.ncols) {
         int ky, kz;
         freq(m, ky, kz);
-        if (MODE == XOP_SCALE) {
+        if constexpr (MODE == XOP_T0) {
+          float2* dst = (mode == 0 ? op.out_c[0] : op.out_q[0]) + off;
+#pragma unroll
+          for (int l2 = 0; l2 < R2; ++l2) dst[row_off<true>(l1 + R1 * l2, g.sn) + m * 8] = v[l2];
+        } else if constexpr (MODE == XOP_T1) {
+          // (D(w_x) X + Y) * (-i g): T0's result and every factor loaded
+          // before the first store
+          const float2* yh = (mode == 0 ? op.in_c[1] : op.in_q[1]) + off;
+          float2 yv[R2];
+          float fac[R2], dxv[R2];
+#pragma unroll
+          for (int l2 = 0; l2 < R2; ++l2) yv[l2] = yh[row_off<true>(l1 + R1 * l2, g.sn) + m * 8];
+#pragma unroll
+          for (int l2 = 0; l2 < R2; ++l2) {
+            fac[l2] = t.kxy[l1 + R1 * l2];
+            dxv[l2] = t.dxy[l1 + R1 * l2];
+          }
+#pragma unroll
+          for (int l2 = 0; l2 < R2; ++l2) asm volatile("" : "+v"(fac[l2]), "+v"(dxv[l2]), "+v"(yv[l2]));
+          const float kyz = t.kxy[ky] + t.kz[kz];
+#pragma unroll
+          for (int l2 = 0; l2 < R2; ++l2) {
+            const float kk = fac[l2] + kyz;
+            fac[l2] = kk > 0.f ? op.scale * __builtin_amdgcn_rcpf(kk) : 0.f;
+          }
+          if (op.deconv) {
+            const float wyz = t.wxy[ky] * t.wz[kz];
+#pragma unroll
+            for (int l2 = 0; l2 < R2; ++l2) {
+              const float wv = t.wxy[l1 + R1 * l2] * wyz;
+              fac[l2] *= __builtin_amdgcn_rcpf(op.deconv == 1 ? wv : wv * wv);
+            }
+          }
+          if (op.split) {
+            const float syz = t.sxy[ky] * t.sz[kz];
+#pragma unroll
+            for (int l2 = 0; l2 < R2; ++l2) {
+              const float sv = t.sxy[l1 + R1 * l2] * syz;
+              fac[l2] *= (op.split == 1 ? sv : 1.f - sv);
+            }
+          }
+          float2* dst = (mode == 0 ? op.out_c[0] : op.out_q[0]) + off;
+#pragma unroll
+          for (int l2 = 0; l2 < R2; ++l2) {
+            const float2 s = make_float2(dxv[l2] * v[l2].x + yv[l2].x, dxv[l2] * v[l2].y + yv[l2].y);
+            // times -i g: (a + i b)(-i g) = g b - i g a
+            dst[row_off<true>(l1 + R1 * l2, g.sn) + m * 8] = make_float2(fac[l2] * s.y, -fac[l2] * s.x);
+          }
+        } else if (MODE == XOP_SCALE) {
           // every factor before the first store: a table load issued after a
           // store through another pointer would wait for that store
           // the force's c(k) = scale W^-n S / K^2 with the per-kx table
@@ -1290,6 +1358,43 @@ void xforce(const FftTables& t, const Field& in, const SpecOp& op, int stage, hi
   }
 }
 
+// The transposed force's x pass (T0, T1, identity OUT) over f[0..2] = the
+// forward-(z, y) spectra of the x, y, z inputs; the result replaces f[0].
+template <int N>
+void xforce_t(const FftTables& t, Field* f, const SpecOp& op, hipStream_t s) {
+  if constexpr (Split<N>::R2 > 1) {
+    constexpr int M = Cols<N>::M;
+    FusedArgs a;
+    a.op = op;
+    a.t = t;
+    a.gm = ColGeom{4L * N, 4L * N * N, N / 2, cdiv(N / 2, M)};
+    a.gp = ColGeom{0, 8L * N, N, cdiv(N, M)};
+    a.nb_main = N * a.gm.ntc;
+    a.first = a.last = 1;
+    a.park_main = nullptr;
+    a.park_nyq = nullptr;
+    a.pbasis = 0;
+    const dim3 grid(a.nb_main + a.gp.ntc);
+    a.in_main = f[1].c();
+    a.in_nyq = f[1].q;
+    a.op.in_c[1] = f[2].c();
+    a.op.in_q[1] = f[2].q;
+    a.op.out_c[0] = f[1].c();
+    a.op.out_q[0] = f[1].q;
+    hipLaunchKernelGGL((k_fft_x_op<N, M, XOP_T0>), grid, dim3(kThreads), 0, s, a);
+    a.in_main = f[0].c();
+    a.in_nyq = f[0].q;
+    a.op.in_c[1] = f[1].c();
+    a.op.in_q[1] = f[1].q;
+    a.op.out_c[0] = f[0].c();
+    a.op.out_q[0] = f[0].q;
+    hipLaunchKernelGGL((k_fft_x_op<N, M, XOP_T1>), grid, dim3(kThreads), 0, s, a);
+    a.op.kind = OP_IDENTITY;
+    a.op.n_out = 1;
+    hipLaunchKernelGGL((k_fft_x_op<N, M, XOP_OUT>), grid, dim3(kThreads), 0, s, a);
+  }
+}
+
 template <int N>
 void yforce(const FftTables& t, Field* f, hipStream_t s) {
   if constexpr (Split<N>::R2 > 1) {
@@ -1386,6 +1491,16 @@ void fft_x_fused(const FftTables& t, const Field& in, const SpecOp& op, hipStrea
 
 void fft_x_force(const FftTables& t, const Field& in, const SpecOp& op, int stage, hipStream_t s) {
 #define CALL(N) xforce<N>(t, in, op, stage, s)
+  PM_FFT_SWITCH(t.n, CALL)
+#undef CALL
+}
+
+void fft_x_force_t(const FftTables& t, Field* f, const SpecOp& op, hipStream_t s) {
+  if (t.n < 64) {   // whole columns in registers: the fused fan-in pass
+    fft_x_fused(t, f[0], op, s);
+    return;
+  }
+#define CALL(N) xforce_t<N>(t, f, op, s)
   PM_FFT_SWITCH(t.n, CALL)
 #undef CALL
 }
