@@ -27,6 +27,7 @@ import numpy as np
 from . import cosmology as cosmo_mod
 from . import lpt as lpt_mod
 from . import pm
+from . import pyramid as pyramid_mod
 from .pm import omega_axes, laplace_symbol, gradient_symbol
 
 
@@ -75,22 +76,30 @@ def apply_multiplier(field, mult):
 
 
 def force_vjp(x, n_mesh, n_particles, omega_m, f_bar, **kw):
-    """x_bar of F = readout(G delta(x), x) for a cotangent f_bar [np, 3].
+    """x_bar of F = readout(G delta(x), x) for a cotangent f_bar [np, 3]
+    (G: the single-grid force, or with pyramid_levels = f the pyramid force).
 
     delta = paint(x) Ng^3/Np - 1, M_d = G_d delta, F_pd = readout(M_d, x_p).
     Two terms: the positions at which M is read out, and the positions that
     paint delta (through M_bar_d = paint(x, f_bar_d), delta_bar = sum G_d^T M_bar_d).
     """
+    levels = kw.pop("pyramid_levels", 0)
     delta = pm.density_contrast(x, n_mesh, n_particles)
-    mult = pm.force_multipliers(n_mesh, omega_m, **kw)
-    meshes = [apply_multiplier(delta, m) for m in mult]
+    if levels:
+        meshes = pyramid_mod.force_meshes(delta, omega_m, levels)
+    else:
+        mult = pm.force_multipliers(n_mesh, omega_m, **kw)
+        meshes = [apply_multiplier(delta, m) for m in mult]
     xb = np.zeros((len(x), 3))
     for d in range(3):
         xb += readout_position_grad(meshes[d], x) * f_bar[:, d:d + 1]
-    delta_bar = np.zeros((n_mesh,) * 3)
-    for d in range(3):
-        mbar = pm.paint(x, n_mesh, mass=f_bar[:, d])
-        delta_bar += apply_multiplier(mbar, np.conj(mult[d]))
+    mbar = [pm.paint(x, n_mesh, mass=f_bar[:, d]) for d in range(3)]
+    if levels:
+        delta_bar = pyramid_mod.force_meshes_T(mbar, omega_m, levels)
+    else:
+        delta_bar = np.zeros((n_mesh,) * 3)
+        for d in range(3):
+            delta_bar += apply_multiplier(mbar[d], np.conj(mult[d]))
     xb += paint_vjp(x, n_mesh, delta_bar * (n_mesh ** 3 / n_particles))
     return xb
 

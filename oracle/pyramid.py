@@ -96,3 +96,24 @@ def force(x, n_mesh, n_particles, omega_m, levels: int = 2, order: int = 6):
     delta = pm.density_contrast(x, n_mesh, n_particles)
     meshes = force_meshes(delta, omega_m, levels, order)
     return np.stack([pm.readout(m, x) for m in meshes], axis=1)
+
+
+def force_meshes_T(mbar, omega_m, levels: int = 2, order: int = 6):
+    """Transpose of force_meshes in the real-space inner product:
+    delta_bar = sum_d F_d^T mbar_d.  With R = REDUCE, E = EXPAND = 8^f R^T and
+    F_d = G_d delta - E R G_d delta + 2^f E G_c,d R delta, each term's
+    transpose gives
+        F_d^T m = G_d^T (m - E R m) + 2^f E G_c,d^T R m,
+    with G^T the conjugate multiplier (the FD force kernel is odd)."""
+    mbar = [np.asarray(m, dtype=np.float64) for m in mbar]
+    n = mbar[0].shape[0]
+    mult = pm.force_multipliers(n, omega_m)
+    mult_c = pm.force_multipliers(n >> levels, omega_m)
+    fine = np.zeros((n, n, n))
+    coarse = np.zeros((n >> levels,) * 3)
+    for d in range(3):
+        r = reduce_field(mbar[d], levels, order)
+        fine += np.fft.irfftn(np.conj(mult[d]) * np.fft.rfftn(mbar[d] - expand_field(r, levels, order)),
+                              s=(n, n, n), axes=(0, 1, 2))
+        coarse += np.fft.irfftn(np.conj(mult_c[d]) * np.fft.rfftn(r), s=r.shape, axes=(0, 1, 2))
+    return fine + 2.0 ** levels * expand_field(coarse, levels, order)

@@ -75,3 +75,28 @@ def test_pyramid_force_is_within_a_percent_of_single_grid():
     assert err < 1e-2
     # and it is not the single-grid force itself: the long-range part differs
     assert err > 1e-6
+
+
+@pytest.mark.parametrize("levels", [1, 2])
+def test_pyramid_force_transpose_dot_product(levels):
+    # sum_d <F_d(delta), m_d> = <delta, F^T(m)> for the pyramid force meshes
+    rng = np.random.default_rng(10 + levels)
+    n = 32
+    delta = rng.normal(size=(n, n, n))
+    m = [rng.normal(size=(n, n, n)) for _ in range(3)]
+    lhs = sum(np.sum(f * mm) for f, mm in zip(P.force_meshes(delta, OM, levels), m))
+    rhs = np.sum(delta * P.force_meshes_T(m, OM, levels))
+    assert lhs == pytest.approx(rhs, rel=1e-11)
+
+
+def test_pyramid_force_vjp_matches_fd():
+    from oracle import adjoint as A
+    n = 32
+    x = inputs.clustered_positions(300, n, seed=5).astype(np.float64)
+    rng = np.random.default_rng(5)
+    fb = rng.normal(size=x.shape)
+    v = rng.normal(size=x.shape)
+    lhs = np.sum(A.force_vjp(x, n, 300, OM, fb, pyramid_levels=2) * v)
+    f = lambda y: P.force(y, n, 300, OM, levels=2)
+    rhs = np.sum(fb * (f(x + 1e-7 * v) - f(x - 1e-7 * v)) / 2e-7)
+    assert lhs == pytest.approx(rhs, rel=1e-5)
