@@ -86,8 +86,8 @@ typedef struct {
     int64_t  max_particles; /* capacity for pm_paint/pm_force/pm_kdk_step; 0 = n_part^3 */
     int      pyramid_levels; /* 0: single-grid force; f >= 1: the multi-grid force of section 4.2
                                 (Algorithm 3) with a coarse grid n_mesh / 2^f >= 8 per side,
-                                order-6 B-spline REDUCE/EXPAND; needs deconv_order 0, no split,
-                                and has no adjoint (pm_run_adjoint, pm_recon_step: PM_EINVAL) */
+                                order-6 B-spline REDUCE/EXPAND; needs deconv_order 0 and no
+                                split; pm_run_adjoint differentiates it (its transpose) */
 } pm_config;
 
 typedef struct pm_ctx pm_ctx;   /* opaque; host memory only */

@@ -243,14 +243,15 @@ def loss_and_grad(noise, workload, target, sigma):
     return loss, lpt_vjp(noise, workload, x0b, p0b)
 
 
-def grad_along_trajectory(xs, noise, workload, target, sigma):
+def grad_along_trajectory(xs, noise, workload, target, sigma, **kw):
     """chi^2 gradient with respect to the noise, differentiating along a given
     trajectory xs (positions at every scale factor) instead of re-running the
-    forward pass: the same reverse sweep, at externally supplied points."""
+    forward pass: the same reverse sweep, at externally supplied points
+    (kw: force options, e.g. pyramid_levels)."""
     n, npart, om = workload.n_mesh, workload.n_particles, workload.cosmo.omega_m
     xs = [np.asarray(x, dtype=np.float64) for x in xs]
     delta = pm.density_contrast(xs[-1], n, npart)
     delta_bar = 2.0 * (delta - target) / sigma ** 2
     xb = paint_vjp(xs[-1], n, delta_bar * (n ** 3 / npart))
-    x0b, p0b = run_vjp(xs, workload.a_list, n, npart, om, xb, np.zeros_like(xb))
+    x0b, p0b = run_vjp(xs, workload.a_list, n, npart, om, xb, np.zeros_like(xb), **kw)
     return lpt_vjp(noise, workload, x0b, p0b)

@@ -271,6 +271,7 @@ struct pm_ctx {
   int nc = 0;
   FftTables tc;
   Field coarse[3];
+  const FftTables& tl_c() const { return tc; }
   float* force_c = nullptr;   // interleaved coarse force, fine-cell units
   uint32_t* misc = nullptr;   // small device words
   // the step loop of a run: step counter, checkpoint base and per-step
@@ -887,7 +888,6 @@ int pm_run_adjoint(pm_ctx* ctx, const double* h_a, int n_a, const float* d_ckpt,
                    const float* d_grad_delta_final, float* d_grad_pos, float* d_grad_mom, float* d_grad_noise) {
   if (!ctx || !h_a || n_a < 1 || !d_ckpt || !d_grad_pos || !d_grad_mom) return PM_EINVAL;
   pm_ctx& c = *ctx;
-  if (c.nc) return c.fail(PM_EINVAL, "the adjoint covers the single-grid force only");
   if (d_grad_noise && !d_noise) return c.fail(PM_EINVAL, "d_grad_noise needs d_noise");
   for (int i = 0; i < n_a; ++i)
     if (!(h_a[i] > 0) || (i && !(h_a[i] > h_a[i - 1]))) return c.fail(PM_EINVAL, "a must be > 0 and increasing");
@@ -927,6 +927,24 @@ int pm_run_adjoint(pm_ctx* ctx, const double* h_a, int n_a, const float* d_ckpt,
       for (int d = 0; d < 3; ++d)
         pmk::launch_paint_weighted(c.pos_s[0], c.id_s[0], c.off, c.tg, pbar, d, (float)kj, c.misc, c.mesh[d].r,
                                    c.stream);
+      // pyramid force: F_d^T m = G_d^T (m - E R m) + 2^f E G_c,d^T R m
+      // (R = REDUCE, E = EXPAND); the interleaved force mesh, read by term A
+      // above, is free scratch here
+      const size_t n3 = (size_t)c.ng * c.ng * c.ng;
+      float* scr3[3] = {c.force_i, c.force_i + n3, c.force_i + 2 * n3};
+      pmk::PyrField mf, cf;
+      if (c.nc) {
+        mf.kind = cf.kind = pmk::PYR_SEPARATE;
+        mf.nx = mf.ny = mf.nz = c.ng;
+        cf.nx = cf.ny = cf.nz = c.nc;
+        for (int d = 0; d < 3; ++d) {
+          mf.p[d] = c.mesh[d].r;
+          cf.p[d] = c.coarse[d].r;
+        }
+        const int lv = c.cfg.pyramid_levels;
+        c.pyr_chain(false, 3, mf, cf, lv, scr3, n3 / 2, pmk::PYR_STORE, nullptr, 0.f);   // R m
+        c.pyr_chain(true, 3, cf, mf, lv, scr3, n3 / 2, pmk::PYR_SUB, nullptr, 0.f);     // m - E R m
+      }
       pmk::fft_r2c_zy(c.tm, c.mesh, 3, c.stream);
       pmk::SpecOp op;
       op.kind = pmk::OP_FORCE_T;
@@ -943,6 +961,31 @@ int pm_run_adjoint(pm_ctx* ctx, const double* h_a, int n_a, const float* d_ckpt,
       op.out_q[0] = c.mesh[0].q;
       pmk::fft_x_force_t(c.tm, c.mesh, op, c.stream);
       pmk::fft_c2r_yz(c.tm, &c.mesh[0], 1, c.stream);
+      if (c.nc) {
+        // coarse part: G_c^T over R m with the coarse transform's 1/nc^3 and
+        // the coarse force's 2^f, then expanded onto the fine result
+        const int lv = c.cfg.pyramid_levels;
+        pmk::fft_r2c_zy(c.tl_c(), c.coarse, 3, c.stream);
+        pmk::SpecOp oc = op;
+        oc.deconv = 0;
+        oc.split = 0;
+        oc.scale = (float)(1.5 * c.cfg.cosmo.omega_m * s * (double)(1 << lv) / ((double)c.nc * c.nc * c.nc));
+        for (int d = 0; d < 3; ++d) {
+          oc.in_c[d] = c.coarse[d].c();
+          oc.in_q[d] = c.coarse[d].q;
+        }
+        oc.out_c[0] = c.coarse[0].c();
+        oc.out_q[0] = c.coarse[0].q;
+        pmk::fft_x_force_t(c.tl_c(), c.coarse, oc, c.stream);
+        pmk::fft_c2r_yz(c.tl_c(), &c.coarse[0], 1, c.stream);
+        pmk::PyrField c1, f1;
+        c1.kind = f1.kind = pmk::PYR_SEPARATE;
+        c1.nx = c1.ny = c1.nz = c.nc;
+        c1.p[0] = c.coarse[0].r;
+        f1.nx = f1.ny = f1.nz = c.ng;
+        f1.p[0] = c.mesh[0].r;
+        c.pyr_chain(true, 1, c1, f1, lv, scr3, n3 / 2, pmk::PYR_ADD, nullptr, 0.f);
+      }
       pmk::launch_readout_grad1(c.pos_s[0], c.id_s[0], np, c.ng, c.mesh[0].r, 1.f, xbar, false, c.stream);
     }
     if (j > 0) pmk::launch_axpy(pbar, xbar, (float)dr[j - 1], (long)ck, c.stream);
@@ -1071,7 +1114,6 @@ int pm_recon_step(pm_ctx* ctx, const double* h_a, int n_a, const float* d_data, 
     return c.fail(PM_EINVAL, "need sigma > 0, t >= 1, lr > 0, 0 <= beta < 1, eps >= 0");
   if ((uintptr_t)d_work % kAlign) return c.fail(PM_EINVAL, "d_work must be 256-byte aligned");
   if (c.run.active) return c.fail(PM_ESTATE, "a resumable run is in progress");
-  if (c.nc) return c.fail(PM_EINVAL, "the adjoint covers the single-grid force only");
   const ReconWork w = recon_work(c, n_a, static_cast<char*>(d_work));
   if (work_bytes < w.total) return c.fail(PM_ENOMEM, "reconstruction work buffer too small");
   int st = pm_init_lpt(ctx, 0, h_a[0], d_noise, nullptr, w.pos, w.mom);

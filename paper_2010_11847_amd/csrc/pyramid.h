@@ -24,6 +24,7 @@ enum PyrMode : int {
   PYR_STORE = 0,     // dst = v
   PYR_COMBINE = 1,   // dst = alpha * aux - v   (aux: interleaved, dst's cube)
   PYR_ADD = 2,       // dst += v
+  PYR_SUB = 3,       // dst -= v
 };
 
 // One separable pass along axis (0 = x, 1 = y, 2 = z) of REDUCE (centred

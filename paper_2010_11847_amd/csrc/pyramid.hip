@@ -92,8 +92,10 @@ __global__ __launch_bounds__(kThreads) void k_pyr_pass(PyrField src, PyrField ds
         *dp = acc[c];
       else if (mode == PYR_COMBINE)
         *dp = alpha * aux[3 * xoff(x, y, z, dst.ny, dst.nz) + c] - acc[c];
-      else
+      else if (mode == PYR_ADD)
         *dp += acc[c];
+      else
+        *dp -= acc[c];
     }
   }
 }

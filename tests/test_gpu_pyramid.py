@@ -1,7 +1,8 @@
 """Multi-grid (pyramid) force of section 4.2 on the GPU: the force against the
 oracle's Algorithm 3, a short KDK run against the oracle's run with the same
-force, the paper's sub-percent agreement with the single-grid force at a
-large mesh, and the configurations the library rejects."""
+force, its adjoint against the oracle's transpose along the same trajectory,
+the paper's sub-percent agreement with the single-grid force at a large
+mesh, and the configurations the library rejects."""
 from dataclasses import replace
 
 import numpy as np
@@ -61,10 +62,22 @@ def test_pyramid_rejections(gpu):
         PMContext(wl(32, 8, 3))                      # coarse grid of 4 cells
     with pytest.raises(PMError):
         PMContext(wl(64, 8, 2, deconv_order=2))      # no deconvolution with the pyramid
-    w = replace(inputs.scaled(inputs.MEDIUM, 32, 16, n_steps=2), pyramid_levels=1)
-    c = PMContext(w)
-    pos, mom = c.pm_init_lpt(w.seed, w.a_list[0])
-    ck = torch.empty((len(w.a_list), 2, 16 ** 3, 3), device="cuda")
-    c.pm_run(w.a_list, pos, mom, ckpt=ck)
     with pytest.raises(PMError):
-        c.pm_run_adjoint(w.a_list, ck, want_noise_grad=False)
+        PMContext(wl(64, 8, 2, split_mode=1, split_rs=2.0))   # nor a force split
+
+
+@pytest.mark.parametrize("n_mesh,n_part,levels", [(64, 32, 2), (128, 64, 1)])
+def test_pyramid_adjoint_matches_oracle_on_same_trajectory(gpu, n_mesh, n_part, levels):
+    from oracle import adjoint as A
+    from oracle.rng import white_noise
+    from tests.test_gpu_adjoint import SIGMA, gpu_run_and_grad
+    banner(f"pyramid adjoint n={n_mesh} np={n_part} levels={levels}")
+    w = replace(inputs.scaled(inputs.ADJ_SMALL, n_mesh, n_part, n_steps=3), pyramid_levels=levels)
+    noise = white_noise(w.seed, n_part)
+    xt = lpt.generate(w, noise=white_noise(w.seed + 1000, n_part))[0]
+    target = pm.density_contrast(xt, n_mesh, n_part ** 3)
+    target = target + np.random.default_rng(w.seed + 2000).normal(0.0, SIGMA, target.shape)
+    ck, g_g = gpu_run_and_grad(w, noise, target)
+    xs = [ck[i, 0] for i in range(len(w.a_list))]
+    g_o = A.grad_along_trajectory(xs, noise, w, target, SIGMA, pyramid_levels=levels)
+    assert rel(g_g, g_o) < 1e-4
