@@ -273,6 +273,18 @@ def serving_section(n_requests, rate=20.0, seed=5, budget_gb=64.0, slots=4):
             "burst": {"continuous": cb_sat, "continuous_no_graphs": cb_eager, "fifo": fifo_sat}}
 
 
+def optional(name, fn, *args):
+    """Run a secondary section; its failure (e.g. device memory) is reported
+    in the JSON line instead of losing the headline measurement."""
+    import torch
+    try:
+        return fn(*args)
+    except Exception as e:   # noqa: BLE001 - any failure of a side section
+        print(f"[bench] {name} section failed: {e!r}", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        return {"error": repr(e)[:300]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -367,16 +379,16 @@ def main():
 
     del ctx, pos, mom, pos0, mom0
     torch.cuda.empty_cache()
-    pyramid = None if args.no_adjoint else pyramid_section(w, args.steps)
-    adjoint = None if args.no_adjoint else adjoint_section()
-    reconstruction = None if args.no_adjoint else recon_section()
+    pyramid = None if args.no_adjoint else optional("pyramid", pyramid_section, w, args.steps)
+    adjoint = None if args.no_adjoint else optional("adjoint", adjoint_section)
+    reconstruction = None if args.no_adjoint else optional("reconstruction", recon_section)
     serving = None
     if args.serve > 0:
-        serving = serving_section(args.serve)
+        serving = optional("serving", serving_section, args.serve)
 
     base = None
     if not args.no_cpu:
-        base = cpu_baseline()
+        base = optional("cpu_baseline", cpu_baseline)
 
     out = {
         "metric": "particle-steps/s (PM KDK) at 512^3/1024^3",
