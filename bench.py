@@ -31,7 +31,7 @@ def kernel_bytes(w, np3):
 
     Mesh field F = N^3 reals = N^2 (N/2) complex, plus the Nyquist plane of
     N^2 complex values.  Particle state 24 B (x, p), id 4 B, key+rank 8 B.
-    The x_inv0 and y_inv figures are those of meshes from 64^3 up, where F_y
+    The x_force and y_inv figures are those of meshes from 64^3 up, where F_y
     and F_z share one inverse x transform.
     """
     n = w.n_mesh
@@ -40,9 +40,7 @@ def kernel_bytes(w, np3):
     return {
         "fft_z_r2c": real + spec,                       # 1 field
         "fft_y_fwd": 2 * spec,                          # 1 field, in place
-        "fft_x_scale": 2 * spec,                        # forward x times c(k), in place
-        "fft_x_inv0": 2 * spec,                         # inverse x, basis D^0: i g X shared by F_y, F_z
-        "fft_x_inv1": 2 * spec,                         # inverse x, basis D^1: F_x
+        "fft_x_force": 3 * spec,                        # spectrum in; F_x and i g X (shared by F_y, F_z) out
         "fft_y_inv": 2 * spec + 3 * spec,               # F_x and the shared factor in; F_x, F_y, F_z out
         "fft_z_c2r": 3 * (spec + real),                 # 3 fields
         "paint": 12.0 * np3 + real,                     # positions in, mesh out

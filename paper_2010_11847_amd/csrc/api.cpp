@@ -214,13 +214,13 @@ void build_fft_tables(long n, double rs, std::vector<char>& host, size_t base_of
 
 // Kernel classes timed by the optional event profiler.
 enum ProfCls : int {
-  PC_FILL, PC_KEYS, PC_SCAN, PC_SCATTER, PC_PAINT, PC_FFT_R2C_Z, PC_FFT_Y_FWD, PC_FFT_X_SCALE, PC_FFT_X_INV0,
-  PC_FFT_X_INV1, PC_FFT_Y_INV, PC_FFT_C2R_Z, PC_READOUT, PC_PYR_REDUCE, PC_PYR_COARSE, PC_PYR_EXPAND, PC_NCLS
+  PC_FILL, PC_KEYS, PC_SCAN, PC_SCATTER, PC_PAINT, PC_FFT_R2C_Z, PC_FFT_Y_FWD, PC_FFT_X_FORCE, PC_FFT_Y_INV,
+  PC_FFT_C2R_Z, PC_READOUT, PC_PYR_REDUCE, PC_PYR_COARSE, PC_PYR_EXPAND, PC_NCLS
 };
-const char* const kProfNames[PC_NCLS] = {"fill",        "keys",       "scan",        "scatter",    "paint",
-                                         "fft_z_r2c",   "fft_y_fwd",  "fft_x_scale", "fft_x_inv0", "fft_x_inv1",
-                                         "fft_y_inv",   "fft_z_c2r",  "readout_kdk", "pyr_reduce", "pyr_coarse_force",
-                                         "pyr_expand"};
+const char* const kProfNames[PC_NCLS] = {"fill",       "keys",      "scan",        "scatter",
+                                         "paint",      "fft_z_r2c", "fft_y_fwd",   "fft_x_force",
+                                         "fft_y_inv",  "fft_z_c2r", "readout_kdk", "pyr_reduce",
+                                         "pyr_coarse_force", "pyr_expand"};
 
 struct Profiler {
   bool on = false;
@@ -397,9 +397,7 @@ struct pm_ctx {
       op.out_c[i] = f[dst[i]].c();
       op.out_q[i] = f[dst[i]].q;
     }
-    tm_(PC_FFT_X_SCALE, [&] { pmk::fft_x_force(t, f[0], op, -1, stream); });
-    tm_(PC_FFT_X_INV0, [&] { pmk::fft_x_force(t, f[0], op, 0, stream); });
-    tm_(PC_FFT_X_INV1, [&] { pmk::fft_x_force(t, f[0], op, 1, stream); });
+    tm_(PC_FFT_X_FORCE, [&] { pmk::fft_x_force(t, f[0], op, stream); });
     if (xs)
       tm_(PC_FFT_Y_INV, [&] { pmk::fft_y_force(t, f, stream); });
     else

@@ -981,23 +981,60 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_fused(FusedArgs a) {
   }
 }
 
-// The force's x pass as three column passes over the x-blocked spectrum:
-//   SCALE : forward x transform, times the force's common factor
-//           c(k) = scale W(k)^-n S(k) / K^2(k), in place;
-//   OUT   : inverse x transform of D(w_x)^p times the scaled spectrum,
-//           stored with the coefficient of every output of power p.
-// Against the fused pass (forward, multiply and inverse in one tile, once
-// per basis) this does one forward transform instead of one per basis and
-// keeps each tile's compute short; it moves one more read and write of the
-// spectrum.  N >= 64 (two-stage columns).
-// The transpose of the force (the adjoint's fan-in, OP_FORCE_T) in the same
-// style, with Y_d the forward-(z, y) spectra of its three inputs:
-//   T0 : forward x of D(w_y) Y_y + D(w_z) Y_z (both factors are constant
-//        along x), stored over Y_y;
-//   T1 : forward x of Y_x, times D(w_x), plus T0's result, times -i g(k),
-//        stored over Y_x;
-//   then an OUT launch of the identity inverts x in place.
-enum XOpMode { XOP_SCALE = 0, XOP_OUT = 1, XOP_T0 = 2, XOP_T1 = 3 };
+
+// The force's common factor c(k) = scale W(k)^-n S(k) / K^2(k) at
+// kx = l1 + R1 l2 for every l2 of one stage-B item (column (ky, kz)).  The
+// per-kx table values are loaded together and pinned before use: a table
+// load issued after a store through another pointer would wait for that
+// store.  The reciprocal is the hardware one (<= 1 ulp); an IEEE divide per
+// element costs about ten instructions.
+template <int R1, int R2>
+__device__ __forceinline__ void force_factors(const FftTables& t, const SpecOp& op, int l1, int ky, int kz,
+                                              float (&fac)[R2]) {
+  float aux[R2];
+#pragma unroll
+  for (int l2 = 0; l2 < R2; ++l2) fac[l2] = t.kxy[l1 + R1 * l2];
+#pragma unroll
+  for (int l2 = 0; l2 < R2; ++l2) asm volatile("" : "+v"(fac[l2]));
+  const float kyz = t.kxy[ky] + t.kz[kz];
+#pragma unroll
+  for (int l2 = 0; l2 < R2; ++l2) {
+    const float kk = fac[l2] + kyz;
+    fac[l2] = kk > 0.f ? op.scale * __builtin_amdgcn_rcpf(kk) : 0.f;
+  }
+  if (op.deconv) {
+    const float wyz = t.wxy[ky] * t.wz[kz];
+#pragma unroll
+    for (int l2 = 0; l2 < R2; ++l2) aux[l2] = t.wxy[l1 + R1 * l2];
+#pragma unroll
+    for (int l2 = 0; l2 < R2; ++l2) {
+      const float wv = aux[l2] * wyz;
+      fac[l2] *= __builtin_amdgcn_rcpf(op.deconv == 1 ? wv : wv * wv);
+    }
+  }
+  if (op.split) {
+    const float syz = t.sxy[ky] * t.sz[kz];
+#pragma unroll
+    for (int l2 = 0; l2 < R2; ++l2) aux[l2] = t.sxy[l1 + R1 * l2];
+#pragma unroll
+    for (int l2 = 0; l2 < R2; ++l2) {
+      const float sv = aux[l2] * syz;
+      fac[l2] *= (op.split == 1 ? sv : 1.f - sv);
+    }
+  }
+}
+
+// Single-transform column passes over the x-blocked spectrum (N >= 64,
+// two-stage columns) for the transpose of the force (the adjoint's fan-in,
+// OP_FORCE_T), with Y_d the forward-(z, y) spectra of its three inputs:
+//   T0  : forward x of D(w_y) Y_y + D(w_z) Y_z (both factors are constant
+//         along x), stored over Y_y;
+//   T1  : forward x of Y_x, times D(w_x), plus T0's result, times -i g(k),
+//         stored over Y_x;
+//   OUT : inverse x transform of D(w_x)^p times the input, stored with the
+//         coefficient of every output of power p (the identity op inverts
+//         T1's result in place).
+enum XOpMode { XOP_OUT = 1, XOP_T0 = 2, XOP_T1 = 3 };
 
 template <int N, int M, int MODE>
 __global__ __launch_bounds__(kThreads) void k_fft_x_op(FusedArgs a) {
@@ -1136,47 +1173,6 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_op(FusedArgs a) {
             // times -i g: (a + i b)(-i g) = g b - i g a
             dst[row_off<true>(l1 + R1 * l2, g.sn) + m * 8] = make_float2(fac[l2] * s.y, -fac[l2] * s.x);
           }
-        } else if (MODE == XOP_SCALE) {
-          // every factor before the first store: a table load issued after a
-          // store through another pointer would wait for that store
-          // the force's c(k) = scale W^-n S / K^2 with the per-kx table
-          // values loaded together (uniform branches outside the loops)
-          float fac[R2], aux[R2];
-#pragma unroll
-          for (int l2 = 0; l2 < R2; ++l2) fac[l2] = t.kxy[l1 + R1 * l2];
-#pragma unroll
-          for (int l2 = 0; l2 < R2; ++l2) asm volatile("" : "+v"(fac[l2]));
-          const float kyz = t.kxy[ky] + t.kz[kz];
-          // hardware reciprocal (<= 1 ulp): an IEEE divide per element
-          // costs about ten instructions
-#pragma unroll
-          for (int l2 = 0; l2 < R2; ++l2) {
-            const float kk = fac[l2] + kyz;
-            fac[l2] = kk > 0.f ? op.scale * __builtin_amdgcn_rcpf(kk) : 0.f;
-          }
-          if (op.deconv) {
-            const float wyz = t.wxy[ky] * t.wz[kz];
-#pragma unroll
-            for (int l2 = 0; l2 < R2; ++l2) aux[l2] = t.wxy[l1 + R1 * l2];
-#pragma unroll
-            for (int l2 = 0; l2 < R2; ++l2) {
-              const float wv = aux[l2] * wyz;
-              fac[l2] *= __builtin_amdgcn_rcpf(op.deconv == 1 ? wv : wv * wv);
-            }
-          }
-          if (op.split) {
-            const float syz = t.sxy[ky] * t.sz[kz];
-#pragma unroll
-            for (int l2 = 0; l2 < R2; ++l2) aux[l2] = t.sxy[l1 + R1 * l2];
-#pragma unroll
-            for (int l2 = 0; l2 < R2; ++l2) {
-              const float sv = aux[l2] * syz;
-              fac[l2] *= (op.split == 1 ? sv : 1.f - sv);
-            }
-          }
-          float2* dst = (mode == 0 ? op.out_c[0] : op.out_q[0]) + off;
-#pragma unroll
-          for (int l2 = 0; l2 < R2; ++l2) dst[row_off<true>(l1 + R1 * l2, g.sn) + m * 8] = cscale(v[l2], fac[l2]);
         } else {
           const float dy = t.dxy[ky], dz = t.dz[kz];
 #pragma unroll 1
@@ -1192,6 +1188,139 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_op(FusedArgs a) {
       }
     }
   }
+}
+
+
+// The force's whole x pass in one tile (OP_FORCE_XS, N >= 64): the forward
+// x transform, times c(k), then two inverse x transforms, each output times
+// i: D(w_x) c X into out[0] (F_x, over the input) and c X into out[1] (the
+// factor F_y and F_z share).  The forward transform leaves item (m, l1)
+// holding kx = l1 + R1 l2 for every l2, which are exactly the inputs of the
+// inverse's first stage (an R2-point transform over l2, then R1 points over
+// l1): the scaled spectrum stays in registers between the transforms, and
+// the pass moves one read and two writes of the spectrum instead of three
+// of each.  The inverse twiddles come from an R1 x R2 table in LDS, filled
+// with the first loads, so no global load waits behind the stores of the
+// first output.
+template <int N, int M>
+__global__ __launch_bounds__(kThreads) void k_fft_x_force(FusedArgs a) {
+  constexpr int R1 = Split<N>::R1, R2 = Split<N>::R2;
+  static_assert(R2 > 1, "columns split over two stages");
+  constexpr int IA = (M * R2 + kThreads - 1) / kThreads;   // forward stage A, inverse stage B
+  constexpr int IB = (M * R1 + kThreads - 1) / kThreads;   // forward stage B, inverse stage A
+  constexpr int SA = ColLds<N, M>::SA, SB = ColLds<N, M>::SB;
+  __shared__ float2 lds[ColLds<N, M>::size];
+  __shared__ float2 tws[R1 * R2];   // exp(-2 pi i l j / N), l < R1, j < R2
+  int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int mode = tile >= a.nb_main ? 1 : 0;
+  if (mode) tile -= a.nb_main;
+  const ColGeom& g = mode ? a.gp : a.gm;
+  int b, c0;
+  tile_bc<true>(tile, mode ? ((int)gridDim.x - a.nb_main) / g.ntc : a.nb_main / g.ntc, g.ntc, M, b, c0);
+  const long off = b * g.sb + (long)c0 * 8;
+  const int tid = threadIdx.x;
+  const SpecOp& op = a.op;
+  const FftTables& t = a.t;
+  const float2* src = (mode == 0 ? a.in_main : a.in_nyq) + off;
+  // (ky, kz) of column m; masked columns map to the zero mode
+  auto freq = [&](int m, int& ky, int& kz) {
+    if (c0 + m >= g.ncols) { ky = 0; kz = 0; }
+    else if (mode == 0) { ky = b; kz = c0 + m; }
+    else { ky = c0 + m; kz = N / 2; }
+  };
+  constexpr int IT = (R1 * R2 + kThreads - 1) / kThreads;
+  float2 twv[IT];
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const int e = tid + k * kThreads;
+    if (e < R1 * R2) twv[k] = t.tw_n[(e / R2) * (e % R2)];
+  }
+  // forward stage A: rows x = R2 j1 + j2
+#pragma unroll
+  for (int i = 0; i < IA; ++i) {
+    const int it = tid + i * kThreads;
+    if (it < M * R2) {
+      const int m = it % M, j2 = it / M;
+      const bool ok = c0 + m < g.ncols;
+      float2 tw[R1];
+      float2 v[R1];
+#pragma unroll
+      for (int l1 = 1; l1 < R1; ++l1) tw[l1] = tw_get<-1>(t.tw_n, j2 * l1);
+#pragma unroll
+      for (int j1 = 0; j1 < R1; ++j1)
+        v[j1] = ok ? src[row_off<true>(R2 * j1 + j2, g.sn) + m * 8] : make_float2(0.f, 0.f);
+#pragma unroll
+      for (int l1 = 1; l1 < R1; ++l1) asm volatile("" : "+v"(tw[l1]));
+      dft<R1, -1>(v);
+#pragma unroll
+      for (int l1 = 0; l1 < R1; ++l1) lds[l1 * SA + j2 * M + m] = l1 == 0 ? v[l1] : cmul(v[l1], tw[l1]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const int e = tid + k * kThreads;
+    if (e < R1 * R2) tws[e] = twv[k];
+  }
+  __syncthreads();
+  // forward stage B: kx = l1 + R1 l2, times c(k) into X; D(w_x) of the same
+  // kx loaded now, before any store
+  float2 X[IB][R2];
+  float dxv[IB][R2];
+#pragma unroll
+  for (int i = 0; i < IB; ++i) {
+    const int it = tid + i * kThreads;
+    if (it < M * R1) {
+      const int m = it % M, l1 = it / M;
+#pragma unroll
+      for (int l2 = 0; l2 < R2; ++l2) X[i][l2] = lds[l1 * SA + l2 * M + m];
+      dft<R2, -1>(X[i]);
+      int ky, kz;
+      freq(m, ky, kz);
+      float fac[R2];
+      force_factors<R1, R2>(t, op, l1, ky, kz, fac);
+#pragma unroll
+      for (int l2 = 0; l2 < R2; ++l2) dxv[i][l2] = t.dxy[l1 + R1 * l2];
+#pragma unroll
+      for (int l2 = 0; l2 < R2; ++l2) X[i][l2] = cscale(X[i][l2], fac[l2]);
+    }
+  }
+  __syncthreads();
+  // inverse of D(w_x)^p c X; outputs x = lp + R2 l2p, stored times i
+  auto inverse = [&](int p, float2* dst) {
+#pragma unroll
+    for (int i = 0; i < IB; ++i) {
+      const int it = tid + i * kThreads;
+      if (it < M * R1) {
+        const int m = it % M, l1 = it / M;
+        float2 y[R2];
+#pragma unroll
+        for (int l2 = 0; l2 < R2; ++l2) y[l2] = p ? cscale(X[i][l2], dxv[i][l2]) : X[i][l2];
+        dft<R2, 1>(y);
+#pragma unroll
+        for (int lp = 0; lp < R2; ++lp)
+          lds[lp * SB + l1 * M + m] = lp == 0 ? y[0] : cmulc(y[lp], tws[l1 * R2 + lp]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < IA; ++i) {
+      const int it = tid + i * kThreads;
+      if (it < M * R2) {
+        const int m = it % M, lp = it / M;
+        float2 v[R1];
+#pragma unroll
+        for (int l1 = 0; l1 < R1; ++l1) v[l1] = lds[lp * SB + l1 * M + m];
+        dft<R1, 1>(v);
+        if (c0 + m < g.ncols) {
+#pragma unroll
+          for (int l2p = 0; l2p < R1; ++l2p) dst[row_off<true>(lp + R2 * l2p, g.sn) + m * 8] = cmul_i<1>(v[l2p]);
+        }
+      }
+    }
+  };
+  inverse(0, (mode == 0 ? op.out_c[1] : op.out_q[1]) + off);
+  __syncthreads();
+  inverse(1, (mode == 0 ? op.out_c[0] : op.out_q[0]) + off);
 }
 
 // ---------------------------------------------------------------------------
@@ -1291,22 +1420,6 @@ void xfused(const FftTables& t, const Field& in, const SpecOp& op, hipStream_t s
     return;
   }
   const int pfirst = __builtin_ctz(pmask), plast = 31 - __builtin_clz(pmask);
-  if constexpr (Split<N>::R2 > 1) {
-    if (op.kind == OP_FORCE) {
-      // scale in place (the spectrum buffer), then one inverse per basis in
-      // increasing p; the output that aliases the input has the highest p
-      FusedArgs sa = a;
-      sa.op.out_c[0] = const_cast<float2*>(a.in_main);
-      sa.op.out_q[0] = const_cast<float2*>(a.in_nyq);
-      hipLaunchKernelGGL((k_fft_x_op<N, M, XOP_SCALE>), grid, dim3(kThreads), 0, s, sa);
-      for (int p = pfirst; p <= plast; ++p) {
-        if (!(pmask >> p & 1)) continue;
-        a.pbasis = p;
-        hipLaunchKernelGGL((k_fft_x_op<N, M, XOP_OUT>), grid, dim3(kThreads), 0, s, a);
-      }
-      return;
-    }
-  }
   if (fan_in) {
     for (int o = 0; o < nterm && first_in < 0; ++o)
       if (op_term(op.kind, o).p == pfirst) first_in = o;
@@ -1325,14 +1438,14 @@ void xfused(const FftTables& t, const Field& in, const SpecOp& op, hipStream_t s
   }
 }
 
-// One stage of the force's x pass (OP_FORCE): stage -1 is the forward
-// transform times c(k) in place, stage p >= 0 the inverse of basis power p.
-// Meshes of N <= 32 run the whole pass in one fused launch at stage -1.
+// The force's x pass: for N >= 64 (OP_FORCE_XS) one launch of
+// k_fft_x_force, for N <= 32 (OP_FORCE, whole columns in registers) the
+// fused register pass.
 template <int N>
-void xforce(const FftTables& t, const Field& in, const SpecOp& op, int stage, hipStream_t s) {
+void xforce(const FftTables& t, const Field& in, const SpecOp& op, hipStream_t s) {
   constexpr int M = Cols<N>::M;
   if constexpr (Split<N>::R2 == 1) {
-    if (stage < 0) xfused<N>(t, in, op, s);
+    xfused<N>(t, in, op, s);
   } else {
     FusedArgs a;
     a.op = op;
@@ -1345,16 +1458,9 @@ void xforce(const FftTables& t, const Field& in, const SpecOp& op, int stage, hi
     a.first = a.last = 1;
     a.park_main = nullptr;
     a.park_nyq = nullptr;
+    a.pbasis = 0;
     const dim3 grid(a.nb_main + a.gp.ntc);
-    if (stage < 0) {
-      a.pbasis = 0;
-      a.op.out_c[0] = in.c();
-      a.op.out_q[0] = in.q;
-      hipLaunchKernelGGL((k_fft_x_op<N, M, XOP_SCALE>), grid, dim3(kThreads), 0, s, a);
-    } else {
-      a.pbasis = stage;
-      hipLaunchKernelGGL((k_fft_x_op<N, M, XOP_OUT>), grid, dim3(kThreads), 0, s, a);
-    }
+    hipLaunchKernelGGL((k_fft_x_force<N, M>), grid, dim3(kThreads), 0, s, a);
   }
 }
 
@@ -1489,8 +1595,8 @@ void fft_x_fused(const FftTables& t, const Field& in, const SpecOp& op, hipStrea
 #undef CALL
 }
 
-void fft_x_force(const FftTables& t, const Field& in, const SpecOp& op, int stage, hipStream_t s) {
-#define CALL(N) xforce<N>(t, in, op, stage, s)
+void fft_x_force(const FftTables& t, const Field& in, const SpecOp& op, hipStream_t s) {
+#define CALL(N) xforce<N>(t, in, op, s)
   PM_FFT_SWITCH(t.n, CALL)
 #undef CALL
 }

@@ -89,12 +89,11 @@ void fft_x_forward(const FftTables& t, Field* f, int nf, hipStream_t s);
 // Fused x pass: forward x transform of `in`, spectral op, inverse x
 // transforms written to op.out_*.  `in` may alias out[0].
 void fft_x_fused(const FftTables& t, const Field& in, const SpecOp& op, hipStream_t s);
-// The force's x pass (op.kind == OP_FORCE) one stage at a time: stage -1
-// transforms `in` forward and multiplies by the Green's function in place;
-// stage p (0, 1) inverse transforms D(w_x)^p times it into the outputs of
-// power p (p = 0: y and z components, p = 1: x, which may alias `in`, so
-// stage 1 runs last).  fft_x_fused(OP_FORCE) runs the three in order.
-void fft_x_force(const FftTables& t, const Field& in, const SpecOp& op, int stage, hipStream_t s);
+// The force's x pass in one launch: forward x transform of `in`, times the
+// Green's function, inverse x transforms into op.out_* (out[0] may alias
+// `in`).  N >= 64 takes OP_FORCE_XS (out[0] = F_x, out[1] = the factor F_y
+// and F_z share), smaller meshes OP_FORCE (three components).
+void fft_x_force(const FftTables& t, const Field& in, const SpecOp& op, hipStream_t s);
 // Inverse y pass of the three force meshes after an OP_FORCE_XS x pass:
 // f[0] holds F_x, f[2] the shared factor i g X.  f[2] becomes F_z times
 // D(w_z) in place and f[1] receives F_y = transform of D(w_y) i g X; one
