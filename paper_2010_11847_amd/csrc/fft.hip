@@ -258,11 +258,13 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(ColPass p, const float2* 
 
 // Inverse y pass of the force meshes after an OP_FORCE_XS x pass
 // (blockIdx.y = 0: F_x in place; 1: the shared factor i g X).  A shared-
-// factor tile is transformed twice: first times D(w_y), which varies along
-// y and so must come before the transform, stored to F_y; then, read again
-// (the tile was just read, so mostly from cache), plain and in place, its
-// output times D(w_z), constant along a column, as F_z.  p.main/p.plane
-// hold F_x, the shared factor (F_z) and F_y, in that order.
+// factor tile is loaded once and transformed twice from registers: first
+// times D(w_y), which varies along y and so must come before the
+// transform, stored to F_y; then plain, in place, its output times D(w_z),
+// constant along a column, as F_z.  The stage-A twiddles come from an
+// R1 x R2 table in LDS, filled with the first loads, so that the second
+// transform's stage A issues no global load behind the first one's stores.
+// p.main/p.plane hold F_x, the shared factor (F_z) and F_y, in that order.
 template <int N, int M>
 __global__ __launch_bounds__(kThreads) void k_fft_cols_force(ColPass p, const float2* __restrict__ tw,
                                                              const float* __restrict__ dy_tab,
@@ -272,7 +274,9 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols_force(ColPass p, const fl
   constexpr int IA = (M * R2 + kThreads - 1) / kThreads;
   constexpr int IB = (M * R1 + kThreads - 1) / kThreads;
   constexpr int SA = ColLds<N, M>::SA;
+  constexpr int IT = (R1 * R2 + kThreads - 1) / kThreads;
   __shared__ float2 lds[ColLds<N, M>::size];
+  __shared__ float2 tws[R1 * R2];   // exp(+2 pi i j l / N), j < R2, l < R1
   int tile = xcd_tile(blockIdx.x, gridDim.x);
   const bool is_plane = tile >= p.nb_main;
   if (is_plane) tile -= p.nb_main;
@@ -284,30 +288,49 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols_force(ColPass p, const fl
   float2* base = (is_plane ? p.plane[blockIdx.y] : p.main[blockIdx.y]) + off;
   const int tid = threadIdx.x;
 
-  // stage A: columns in (times D(w_y) of the row when row_factor), R1-point
-  // transforms, twiddles, into the exchange
+  // every global load of stage A first: the twiddle table, the row factors
+  // D(w_y) of a shared tile and the columns
+  float2 twv[IT];
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const int e = tid + k * kThreads;
+    if (e < R1 * R2) twv[k] = tw_get<1>(tw, (e / R1) * (e % R1));
+  }
+  float2 v0[IA][R1];
+  float d[IA][R1];
+#pragma unroll
+  for (int i = 0; i < IA; ++i) {
+    const int it = tid + i * kThreads;
+    const int m = it % M, j2 = it / M;
+    const bool ok = it < M * R2 && c0 + m < g.ncols;
+    if (shared) {
+#pragma unroll
+      for (int j1 = 0; j1 < R1; ++j1) d[i][j1] = it < M * R2 ? dy_tab[R2 * j1 + j2] : 0.f;
+    }
+#pragma unroll
+    for (int j1 = 0; j1 < R1; ++j1) v0[i][j1] = ok ? base[(long)(R2 * j1 + j2) * g.sn + m] : make_float2(0.f, 0.f);
+  }
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const int e = tid + k * kThreads;
+    if (e < R1 * R2) tws[e] = twv[k];
+  }
+  __syncthreads();
+
+  // stage A: the loaded columns (times D(w_y) of the row when row_factor),
+  // R1-point transforms, twiddles, into the exchange
   auto stage_a = [&](bool row_factor) {
 #pragma unroll
     for (int i = 0; i < IA; ++i) {
       const int it = tid + i * kThreads;
       if (it < M * R2) {
         const int m = it % M, j2 = it / M;
-        const bool ok = c0 + m < g.ncols;
         float2 v[R1];
-        float d[R1];
-        if (row_factor) {
 #pragma unroll
-          for (int j1 = 0; j1 < R1; ++j1) d[j1] = dy_tab[R2 * j1 + j2];
-        }
-#pragma unroll
-        for (int j1 = 0; j1 < R1; ++j1) v[j1] = ok ? base[(long)(R2 * j1 + j2) * g.sn + m] : make_float2(0.f, 0.f);
-        if (row_factor) {
-#pragma unroll
-          for (int j1 = 0; j1 < R1; ++j1) v[j1] = cscale(v[j1], d[j1]);
-        }
+        for (int j1 = 0; j1 < R1; ++j1) v[j1] = row_factor ? cscale(v0[i][j1], d[i][j1]) : v0[i][j1];
         dft<R1, 1>(v);
 #pragma unroll
-        for (int l1 = 0; l1 < R1; ++l1) lds[l1 * SA + j2 * M + m] = l1 == 0 ? v[l1] : cmul(v[l1], tw_get<1>(tw, j2 * l1));
+        for (int l1 = 0; l1 < R1; ++l1) lds[l1 * SA + j2 * M + m] = l1 == 0 ? v[l1] : cmul(v[l1], tws[j2 * R1 + l1]);
       }
     }
   };
