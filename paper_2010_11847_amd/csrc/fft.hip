@@ -1258,25 +1258,31 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_force(FusedArgs a) {
     const int e = tid + k * kThreads;
     if (e < R1 * R2) twv[k] = t.tw_n[(e / R2) * (e % R2)];
   }
-  // forward stage A: rows x = R2 j1 + j2
+  // forward stage A: rows x = R2 j1 + j2, all loads first; the twiddles
+  // come from the table once it is in LDS
+  float2 v[IA][R1];
 #pragma unroll
   for (int i = 0; i < IA; ++i) {
     const int it = tid + i * kThreads;
-    if (it < M * R2) {
-      const int m = it % M, j2 = it / M;
-      const bool ok = c0 + m < g.ncols;
-      float2 tw[R1];
-      float2 v[R1];
+    const int m = it % M, j2 = it / M;
+    const bool ok = it < M * R2 && c0 + m < g.ncols;
 #pragma unroll
-      for (int l1 = 1; l1 < R1; ++l1) tw[l1] = tw_get<-1>(t.tw_n, j2 * l1);
+    for (int j1 = 0; j1 < R1; ++j1)
+      v[i][j1] = ok ? src[row_off<true>(R2 * j1 + j2, g.sn) + m * 8] : make_float2(0.f, 0.f);
+  }
+  // c(k) and D(w_x) of the stage-B item (m, l1), kx = l1 + R1 l2, loaded
+  // behind the columns and before any store
+  float fac[IB][R2], dxv[IB][R2];
 #pragma unroll
-      for (int j1 = 0; j1 < R1; ++j1)
-        v[j1] = ok ? src[row_off<true>(R2 * j1 + j2, g.sn) + m * 8] : make_float2(0.f, 0.f);
+  for (int i = 0; i < IB; ++i) {
+    const int it = tid + i * kThreads;
+    if (it < M * R1) {
+      const int m = it % M, l1 = it / M;
+      int ky, kz;
+      freq(m, ky, kz);
+      force_factors<R1, R2>(t, op, l1, ky, kz, fac[i]);
 #pragma unroll
-      for (int l1 = 1; l1 < R1; ++l1) asm volatile("" : "+v"(tw[l1]));
-      dft<R1, -1>(v);
-#pragma unroll
-      for (int l1 = 0; l1 < R1; ++l1) lds[l1 * SA + j2 * M + m] = l1 == 0 ? v[l1] : cmul(v[l1], tw[l1]);
+      for (int l2 = 0; l2 < R2; ++l2) dxv[i][l2] = t.dxy[l1 + R1 * l2];
     }
   }
 #pragma unroll
@@ -1285,10 +1291,19 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_force(FusedArgs a) {
     if (e < R1 * R2) tws[e] = twv[k];
   }
   __syncthreads();
-  // forward stage B: kx = l1 + R1 l2, times c(k) into X; D(w_x) of the same
-  // kx loaded now, before any store
+#pragma unroll
+  for (int i = 0; i < IA; ++i) {
+    const int it = tid + i * kThreads;
+    if (it < M * R2) {
+      const int m = it % M, j2 = it / M;
+      dft<R1, -1>(v[i]);
+#pragma unroll
+      for (int l1 = 0; l1 < R1; ++l1) lds[l1 * SA + j2 * M + m] = l1 == 0 ? v[i][l1] : cmul(v[i][l1], tws[l1 * R2 + j2]);
+    }
+  }
+  __syncthreads();
+  // forward stage B: kx = l1 + R1 l2, times c(k) into X
   float2 X[IB][R2];
-  float dxv[IB][R2];
 #pragma unroll
   for (int i = 0; i < IB; ++i) {
     const int it = tid + i * kThreads;
@@ -1297,14 +1312,8 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_force(FusedArgs a) {
 #pragma unroll
       for (int l2 = 0; l2 < R2; ++l2) X[i][l2] = lds[l1 * SA + l2 * M + m];
       dft<R2, -1>(X[i]);
-      int ky, kz;
-      freq(m, ky, kz);
-      float fac[R2];
-      force_factors<R1, R2>(t, op, l1, ky, kz, fac);
 #pragma unroll
-      for (int l2 = 0; l2 < R2; ++l2) dxv[i][l2] = t.dxy[l1 + R1 * l2];
-#pragma unroll
-      for (int l2 = 0; l2 < R2; ++l2) X[i][l2] = cscale(X[i][l2], fac[l2]);
+      for (int l2 = 0; l2 < R2; ++l2) X[i][l2] = cscale(X[i][l2], fac[i][l2]);
     }
   }
   __syncthreads();
