@@ -219,8 +219,13 @@ struct PaintWeights {
   const uint32_t* maxbits = nullptr;   // bits of max |wts| (non-negative float)
 };
 
+// Threads per paint workgroup: the 64-bit tile accumulator (32 KB of LDS)
+// allows four workgroups per CU, and 512 threads each make that the full
+// eight waves per SIMD to hide the latency of the range and particle loads.
+constexpr int kPaintThreads = 512;
+
 template <bool STD, bool WT>
-__global__ __launch_bounds__(kThreads) void k_paint(const float* __restrict__ pos, const uint32_t* __restrict__ off,
+__global__ __launch_bounds__(kPaintThreads) void k_paint(const float* __restrict__ pos, const uint32_t* __restrict__ off,
                                                     TileGeom g, float* __restrict__ out, float scale, float offset,
                                                     PaintWeights pw) {
   __shared__ unsigned long long acc[kTileCells];
@@ -230,7 +235,7 @@ __global__ __launch_bounds__(kThreads) void k_paint(const float* __restrict__ po
   int tx, ty, tz;
   tile_coords(tile, g, tx, ty, tz);
   const int ox = tx * TX, oy = ty * TY, oz = tz * TZ;
-  for (int c = threadIdx.x; c < tile_cells(g); c += kThreads) acc[c] = 0ull;
+  for (int c = threadIdx.x; c < tile_cells(g); c += kPaintThreads) acc[c] = 0ull;
   float S = 1.f;   // WT: fixed-point scale, a power of two
   if (WT) {
     const float mx = __uint_as_float(*pw.maxbits) * fabsf(pw.k);
@@ -242,16 +247,15 @@ __global__ __launch_bounds__(kThreads) void k_paint(const float* __restrict__ po
   }
   build_ranges(rt, off, tx, ty, tz, g);
   const uint32_t total = rt.pre[27];
-  constexpr int kBatch = 4;   // particles whose loads are in flight together (4 measured
-                              // faster than 2 or 8 at 512 particles per tile)
-  for (uint32_t base = 0; base < total; base += kThreads * kBatch) {
+  constexpr int kBatch = 2;   // particles per thread whose loads are in flight together
+  for (uint32_t base = 0; base < total; base += kPaintThreads * kBatch) {
     // all range searches (LDS) first, then all loads, so that the kBatch
     // loads of a thread are in flight together; positions past the end are
     // clamped onto the last particle (a valid address) and skipped below
     uint32_t jj[kBatch];
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
-      const uint32_t idx = base + threadIdx.x + u * kThreads;
+      const uint32_t idx = base + threadIdx.x + u * kPaintThreads;
       jj[u] = range_particle(rt, idx < total ? idx : total - 1);
     }
     float px[kBatch][3];
@@ -277,7 +281,7 @@ __global__ __launch_bounds__(kThreads) void k_paint(const float* __restrict__ po
     }
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
-    if (base + threadIdx.x + u * kThreads >= total) continue;
+    if (base + threadIdx.x + u * kPaintThreads >= total) continue;
     int ix, iy, iz;
     float fx, fy, fz;
     cic_base(px[u][0], n, ix, fx);
@@ -316,7 +320,7 @@ __global__ __launch_bounds__(kThreads) void k_paint(const float* __restrict__ po
     }
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < store_walk_len(g); c += kThreads) {
+  for (int c = threadIdx.x; c < store_walk_len(g); c += kPaintThreads) {
     int cx, cy, cz;
     store_walk(c, g, cx, cy, cz);
     if (cx >= TX) continue;
@@ -734,10 +738,10 @@ void launch_paint(const float* pos_sorted, const uint32_t* off, const TileGeom& 
                   float offset, bool std_layout, hipStream_t s) {
   const PaintWeights pw;
   if (std_layout)
-    hipLaunchKernelGGL((k_paint<true, false>), dim3(g.ntiles), dim3(kThreads), 0, s, pos_sorted, off, g, out, scale,
+    hipLaunchKernelGGL((k_paint<true, false>), dim3(g.ntiles), dim3(kPaintThreads), 0, s, pos_sorted, off, g, out, scale,
                        offset, pw);
   else
-    hipLaunchKernelGGL((k_paint<false, false>), dim3(g.ntiles), dim3(kThreads), 0, s, pos_sorted, off, g, out,
+    hipLaunchKernelGGL((k_paint<false, false>), dim3(g.ntiles), dim3(kPaintThreads), 0, s, pos_sorted, off, g, out,
                        scale, offset, pw);
 }
 
@@ -754,7 +758,7 @@ void launch_paint_weighted(const float* pos_sorted, const uint32_t* id_sorted, c
   pw.comp = comp;
   pw.k = k;
   pw.maxbits = maxbits;
-  hipLaunchKernelGGL((k_paint<false, true>), dim3(g.ntiles), dim3(kThreads), 0, s, pos_sorted, off, g, out, 1.f,
+  hipLaunchKernelGGL((k_paint<false, true>), dim3(g.ntiles), dim3(kPaintThreads), 0, s, pos_sorted, off, g, out, 1.f,
                      0.f, pw);
 }
 
