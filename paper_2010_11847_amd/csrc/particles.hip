@@ -408,10 +408,14 @@ __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
     jj[u] = j0 + threadIdx.x + u * kThreads;
     valid[u] = jj[u] < a.np;
     const long jc = valid[u] ? jj[u] : a.np - 1;
+    // position and momentum as one 12-byte load each
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      x[u][d] = a.pos[3 * jc + d];
-      p[u][d] = a.mom ? a.mom[3 * jc + d] : 0.f;
+    for (int d = 0; d < 3; ++d) x[u][d] = a.pos[3 * jc + d];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) p[u][d] = 0.f;
+    if (a.mom) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) p[u][d] = a.mom[3 * jc + d];
     }
     // ids are needed only for writes by id (not on ordinary steps)
     id[u] = (a.id && (a.flags & (RO_FORCE_BYID | RO_XP_BYID | RO_CKPT))) ? a.id[jc] : (uint32_t)jc;
@@ -483,17 +487,17 @@ __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
     if (!valid[u]) continue;
     if (a.flags & RO_WRITE_SORTED) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        a.pos[3 * j + d] = x[u][d];
-        if (a.mom) a.mom[3 * j + d] = p[u][d];
+      for (int d = 0; d < 3; ++d) a.pos[3 * j + d] = x[u][d];
+      if (a.mom) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) a.mom[3 * j + d] = p[u][d];
       }
     }
     if (a.flags & RO_XP_BYID) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        a.pos_out[3 * (long)id[u] + d] = x[u][d];
-        a.mom_out[3 * (long)id[u] + d] = p[u][d];
-      }
+      for (int d = 0; d < 3; ++d) a.pos_out[3 * (long)id[u] + d] = x[u][d];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) a.mom_out[3 * (long)id[u] + d] = p[u][d];
     }
   }
   if (!keys) return;
