@@ -1086,7 +1086,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_op(FusedArgs a) {
     else if (mode == 0) { ky = b; kz = c0 + m; }
     else { ky = c0 + m; kz = N / 2; }
   };
-  // stage A: rows n = R2*j1 + j2 (kx for OUT, x for SCALE).  The symbol
+  // stage A: rows n = R2*j1 + j2 (kx for OUT, x for T0 and T1).  The symbol
   // factors of OUT are loaded before the data and pinned in registers.
 #pragma unroll
   for (int i = 0; i < IA; ++i) {
