@@ -36,16 +36,30 @@ __device__ __forceinline__ long xoff(int x, int y, int z, int ny, int nz) {
   return ((((long)(x >> 3) * ny + y) * nz + z) << 3) + (x & 7);
 }
 
-__device__ __forceinline__ long pf_off(const PyrField& f, int c, int x, int y, int z) {
+// Field kinds of a pass: PYR_SEPARATE or PYR_INTERLEAVED known at compile
+// time, so that the three adjacent channels of an interleaved cell move as
+// one 12-byte access; kAnyKind reads the kind at run time.
+constexpr int kAnyKind = -1;
+
+template <int KIND>
+__device__ __forceinline__ bool is_interleaved(const PyrField& f) {
+  return KIND == kAnyKind ? f.kind == PYR_INTERLEAVED : KIND == PYR_INTERLEAVED;
+}
+
+// the CH channel values of cell (x, y, z)
+template <int CH, int KIND>
+__device__ __forceinline__ void cell_load(const PyrField& f, int x, int y, int z, float (&v)[CH]) {
   const long e = xoff(x, y, z, f.ny, f.nz);
-  return f.kind == PYR_SEPARATE ? e : 3 * e + c;
+  if (is_interleaved<KIND>(f)) {
+#pragma unroll
+    for (int c = 0; c < CH; ++c) v[c] = f.p[0][3 * e + c];
+  } else {
+#pragma unroll
+    for (int c = 0; c < CH; ++c) v[c] = f.p[c][e];
+  }
 }
 
-__device__ __forceinline__ float pf_load(const PyrField& f, int c, int x, int y, int z) {
-  return (f.kind == PYR_INTERLEAVED ? f.p[0] : f.p[c])[pf_off(f, c, x, y, z)];
-}
-
-template <bool EXPAND, int AXIS, int CH>
+template <bool EXPAND, int AXIS, int CH, int SK, int DK>
 __global__ __launch_bounds__(kThreads) void k_pyr_pass(PyrField src, PyrField dst, Dims dd, int mode,
                                                         const float* __restrict__ aux, float alpha) {
   const long total = (long)dst.nx * dst.ny * dst.nz;
@@ -68,8 +82,10 @@ __global__ __launch_bounds__(kThreads) void k_pyr_pass(PyrField src, PyrField ds
       for (int t = -3; t <= 3; ++t) {
         const int i = (2 * o + t) & (nin - 1);
         const int sx = AXIS == 0 ? i : x, sy = AXIS == 1 ? i : y, sz = AXIS == 2 ? i : z;
+        float v[CH];
+        cell_load<CH, SK>(src, sx, sy, sz, v);
 #pragma unroll
-        for (int c = 0; c < CH; ++c) acc[c] += bw(t) * pf_load(src, c, sx, sy, sz);
+        for (int c = 0; c < CH; ++c) acc[c] += bw(t) * v[c];
       }
     } else {
       // out(j) = 2 sum_i b(j - 2 i) in(i): i = j/2 - 1 .. j/2 + 2
@@ -81,21 +97,32 @@ __global__ __launch_bounds__(kThreads) void k_pyr_pass(PyrField src, PyrField ds
         const float wgt = (!odd && u == 2) ? 0.f : 2.f * bw(t);
         const int i = (i0 + u) & (nin - 1);
         const int sx = AXIS == 0 ? i : x, sy = AXIS == 1 ? i : y, sz = AXIS == 2 ? i : z;
+        float v[CH];
+        cell_load<CH, SK>(src, sx, sy, sz, v);
 #pragma unroll
-        for (int c = 0; c < CH; ++c) acc[c] += wgt * pf_load(src, c, sx, sy, sz);
+        for (int c = 0; c < CH; ++c) acc[c] += wgt * v[c];
       }
     }
+    // one loop per mode, so that the channels of an interleaved cell merge
+    const long de = xoff(x, y, z, dst.ny, dst.nz);
+    const bool dil = is_interleaved<DK>(dst);
+    auto dptr = [&](int c) { return dil ? dst.p[0] + 3 * de + c : dst.p[c] + de; };
+    if (mode == PYR_STORE) {
 #pragma unroll
-    for (int c = 0; c < CH; ++c) {
-      float* dp = (dst.kind == PYR_INTERLEAVED ? dst.p[0] : dst.p[c]) + pf_off(dst, c, x, y, z);
-      if (mode == PYR_STORE)
-        *dp = acc[c];
-      else if (mode == PYR_COMBINE)
-        *dp = alpha * aux[3 * xoff(x, y, z, dst.ny, dst.nz) + c] - acc[c];
-      else if (mode == PYR_ADD)
-        *dp += acc[c];
-      else
-        *dp -= acc[c];
+      for (int c = 0; c < CH; ++c) *dptr(c) = acc[c];
+    } else if (mode == PYR_COMBINE) {
+      float av[CH];
+#pragma unroll
+      for (int c = 0; c < CH; ++c) av[c] = aux[3 * de + c];
+#pragma unroll
+      for (int c = 0; c < CH; ++c) *dptr(c) = alpha * av[c] - acc[c];
+    } else {
+      const float sg = mode == PYR_ADD ? 1.f : -1.f;
+      float dv[CH];
+#pragma unroll
+      for (int c = 0; c < CH; ++c) dv[c] = *dptr(c);
+#pragma unroll
+      for (int c = 0; c < CH; ++c) *dptr(c) = dv[c] + sg * acc[c];
     }
   }
 }
@@ -107,10 +134,23 @@ void launch_axis(int ch, const PyrField& src, const PyrField& dst, Dims dd, int 
   long blocks = (total + kThreads - 1) / kThreads;
   if (blocks > (1L << 20)) blocks = 1L << 20;
   const dim3 grid((unsigned)blocks);
+  constexpr int SEP = PYR_SEPARATE, IL = PYR_INTERLEAVED;
+  const int sk = src.kind, dk = dst.kind;
   if (ch == 1)
-    hipLaunchKernelGGL((k_pyr_pass<EXPAND, AXIS, 1>), grid, dim3(kThreads), 0, s, src, dst, dd, mode, aux, alpha);
+    hipLaunchKernelGGL((k_pyr_pass<EXPAND, AXIS, 1, kAnyKind, kAnyKind>), grid, dim3(kThreads), 0, s, src, dst, dd,
+                       mode, aux, alpha);
+  else if (sk == SEP && dk == SEP)
+    hipLaunchKernelGGL((k_pyr_pass<EXPAND, AXIS, 3, SEP, SEP>), grid, dim3(kThreads), 0, s, src, dst, dd, mode, aux,
+                       alpha);
+  else if (sk == IL && dk == SEP)
+    hipLaunchKernelGGL((k_pyr_pass<EXPAND, AXIS, 3, IL, SEP>), grid, dim3(kThreads), 0, s, src, dst, dd, mode, aux,
+                       alpha);
+  else if (sk == SEP && dk == IL)
+    hipLaunchKernelGGL((k_pyr_pass<EXPAND, AXIS, 3, SEP, IL>), grid, dim3(kThreads), 0, s, src, dst, dd, mode, aux,
+                       alpha);
   else
-    hipLaunchKernelGGL((k_pyr_pass<EXPAND, AXIS, 3>), grid, dim3(kThreads), 0, s, src, dst, dd, mode, aux, alpha);
+    hipLaunchKernelGGL((k_pyr_pass<EXPAND, AXIS, 3, kAnyKind, kAnyKind>), grid, dim3(kThreads), 0, s, src, dst, dd,
+                       mode, aux, alpha);
 }
 
 }  // namespace
