@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -407,10 +408,15 @@ struct pm_ctx {
 
   // REDUCE (expand = false) or EXPAND of ch channels over `levels` levels,
   // as three one-axis passes per level; intermediates alternate between the
-  // halves of each channel's scratch (scr[c], 2 * half floats).  The last
-  // pass writes `out` with `mode`.
+  // halves of each channel's scratch (scr[c], 2 * half floats).  When the
+  // three channel buffers are consecutive (scr[c] = scr[0] + c * stride,
+  // stride >= 2 * half), three-channel intermediates are interleaved instead,
+  // alternating between the two 3 * half-float halves of that region, so
+  // that every tap of a pass is one 12-byte access.  The last pass writes
+  // `out` with `mode`.
   void pyr_chain(bool expand, int ch, pmk::PyrField in, const pmk::PyrField& out, int levels, float* const* scr,
                  size_t half, int mode, const float* aux, float alpha) {
+    const bool il = ch == 3 && scr[1] - scr[0] >= (ptrdiff_t)(2 * half) && scr[2] - scr[1] == scr[1] - scr[0];
     int k = 0;
     for (int lv = 0; lv < levels; ++lv)
       for (int ax = 0; ax < 3; ++ax) {
@@ -419,13 +425,16 @@ struct pm_ctx {
         if (last) {
           nx = out;
         } else {
-          nx.kind = pmk::PYR_SEPARATE;
+          nx.kind = il ? pmk::PYR_INTERLEAVED : pmk::PYR_SEPARATE;
           nx.nx = in.nx;
           nx.ny = in.ny;
           nx.nz = in.nz;
           int* d = ax == 0 ? &nx.nx : (ax == 1 ? &nx.ny : &nx.nz);
           *d = expand ? *d * 2 : *d / 2;
-          for (int c = 0; c < ch; ++c) nx.p[c] = scr[c] + (k & 1) * half;
+          if (il)
+            nx.p[0] = scr[0] + (k & 1) * 3 * half;
+          else
+            for (int c = 0; c < ch; ++c) nx.p[c] = scr[c] + (k & 1) * half;
         }
         pmk::launch_pyr_pass(expand, ax, ch, in, nx, last ? mode : pmk::PYR_STORE, aux, alpha, stream);
         in = nx;

@@ -148,6 +148,9 @@ void launch_axis(int ch, const PyrField& src, const PyrField& dst, Dims dd, int 
   else if (sk == SEP && dk == IL)
     hipLaunchKernelGGL((k_pyr_pass<EXPAND, AXIS, 3, SEP, IL>), grid, dim3(kThreads), 0, s, src, dst, dd, mode, aux,
                        alpha);
+  else if (sk == IL && dk == IL)
+    hipLaunchKernelGGL((k_pyr_pass<EXPAND, AXIS, 3, IL, IL>), grid, dim3(kThreads), 0, s, src, dst, dd, mode, aux,
+                       alpha);
   else
     hipLaunchKernelGGL((k_pyr_pass<EXPAND, AXIS, 3, kAnyKind, kAnyKind>), grid, dim3(kThreads), 0, s, src, dst, dd,
                        mode, aux, alpha);
