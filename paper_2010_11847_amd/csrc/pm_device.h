@@ -77,25 +77,33 @@ static __device__ __forceinline__ void cell_coords(int c, const TileGeom& g, int
   cx = c >> (g.lz + g.ly);
 }
 
-// Rank of this lane's key among all keys counted so far: lanes of a wave
-// with equal keys share one atomic (particles arrive nearly sorted, so most
-// waves hold one or two distinct keys).  Must be called by the whole wave.
+// Rank of this lane's key among all keys counted so far.  Lanes of a wave
+// with equal keys share one atomic: the groups are found with ballots
+// first, then every group leader issues its atomic in the same instruction,
+// so the wave waits for one atomic round trip however many distinct keys it
+// holds (particles in lattice order span several tiles per wave).  Must be
+// called by the whole wave.
 static __device__ __forceinline__ uint32_t agg_rank(uint32_t* count, uint32_t key, bool valid) {
   uint64_t active = __ballot(valid);
   const int lane = __lane_id();
-  uint32_t mine = 0;
+  int my_leader = lane;
+  uint32_t my_prefix = 0, group = 0;
   while (active) {
     const int leader = __ffsll((unsigned long long)active) - 1;
     const uint32_t lk = __shfl(key, leader);
     const bool same = valid && key == lk;
     const uint64_t mask = __ballot(same) & active;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(&count[lk], (uint32_t)__popcll(mask));
-    base = __shfl(base, leader);
-    if (same) mine = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+    if (same) {
+      my_leader = leader;
+      my_prefix = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+    }
+    if (lane == leader) group = (uint32_t)__popcll(mask);
     active &= ~mask;
   }
-  return mine;
+  uint32_t base = 0;
+  if (group) base = atomicAdd(&count[key], group);
+  base = __shfl(base, my_leader);
+  return valid ? base + my_prefix : 0u;
 }
 
 // The 27 particle ranges a paint workgroup gathers: for every lower
