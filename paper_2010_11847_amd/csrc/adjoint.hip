@@ -37,11 +37,23 @@ __global__ __launch_bounds__(kThreads) void k_readout_grad(const float* __restri
   cic_base(pos[3 * j + 1], n, iy, fy);
   cic_base(pos[3 * j + 2], n, iz, fz);
   const long p = (long)id[j];
+  // the by-id loads (the cotangent and the running x-bar) go out together,
+  // before the corners; left in place, the x-bar load would follow the sum
+  // and add a round trip at the end
   float c0 = k, c1 = 0.f, c2 = 0.f;
   if constexpr (NCH == 3) {
-    c0 = pbar[3 * p + 0] * k;
-    c1 = pbar[3 * p + 1] * k;
-    c2 = pbar[3 * p + 2] * k;
+    c0 = pbar[3 * p + 0];
+    c1 = pbar[3 * p + 1];
+    c2 = pbar[3 * p + 2];
+  }
+  float xb[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) xb[d] = xbar[3 * p + d];
+  asm volatile("" : "+v"(c0), "+v"(c1), "+v"(c2), "+v"(xb[0]), "+v"(xb[1]), "+v"(xb[2]));
+  if constexpr (NCH == 3) {
+    c0 *= k;
+    c1 *= k;
+    c2 *= k;
   }
   const int jx = (ix + 1) & (n - 1), jy = (iy + 1) & (n - 1), jz = (iz + 1) & (n - 1);
   const int xs[2] = {ix, jx}, ys[2] = {iy, jy}, zs[2] = {iz, jz};
@@ -64,9 +76,9 @@ __global__ __launch_bounds__(kThreads) void k_readout_grad(const float* __restri
         gy += wx[a] * sb * wz[c] * val;
         gz += wx[a] * wy[b] * sc * val;
       }
-  xbar[3 * p + 0] += gx;
-  xbar[3 * p + 1] += gy;
-  xbar[3 * p + 2] += gz;
+  xbar[3 * p + 0] = xb[0] + gx;
+  xbar[3 * p + 1] = xb[1] + gy;
+  xbar[3 * p + 2] = xb[2] + gz;
 }
 
 // y += a x  (n floats)
