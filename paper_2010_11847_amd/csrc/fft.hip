@@ -1010,8 +1010,10 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_fused(FusedArgs a) {
 // per-kx table values are loaded together and pinned before use: a table
 // load issued after a store through another pointer would wait for that
 // store.  The reciprocal is the hardware one (<= 1 ulp); an IEEE divide per
-// element costs about ten instructions.
-template <int R1, int R2>
+// element costs about ten instructions.  FILT = false leaves out the
+// deconvolution and split branches (their registers included): callers
+// that take it are launched only for ops with neither.
+template <int R1, int R2, bool FILT = true>
 __device__ __forceinline__ void force_factors(const FftTables& t, const SpecOp& op, int l1, int ky, int kz,
                                               float (&fac)[R2]) {
   float aux[R2];
@@ -1025,7 +1027,7 @@ __device__ __forceinline__ void force_factors(const FftTables& t, const SpecOp& 
     const float kk = fac[l2] + kyz;
     fac[l2] = kk > 0.f ? op.scale * __builtin_amdgcn_rcpf(kk) : 0.f;
   }
-  if (op.deconv) {
+  if (FILT && op.deconv) {
     const float wyz = t.wxy[ky] * t.wz[kz];
 #pragma unroll
     for (int l2 = 0; l2 < R2; ++l2) aux[l2] = t.wxy[l1 + R1 * l2];
@@ -1035,7 +1037,7 @@ __device__ __forceinline__ void force_factors(const FftTables& t, const SpecOp& 
       fac[l2] *= __builtin_amdgcn_rcpf(op.deconv == 1 ? wv : wv * wv);
     }
   }
-  if (op.split) {
+  if (FILT && op.split) {
     const float syz = t.sxy[ky] * t.sz[kz];
 #pragma unroll
     for (int l2 = 0; l2 < R2; ++l2) aux[l2] = t.sxy[l1 + R1 * l2];
@@ -1355,6 +1357,157 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_force(FusedArgs a) {
   inverse(1, (mode == 0 ? op.out_c[0] : op.out_q[0]) + off);
 }
 
+
+// The second half of the transposed force's x pass (OP_FORCE_T, N >= 64,
+// no deconvolution or split) in one tile: the forward x transform of Y_x, then Z = (D(w_x) X + Y) (-i g)
+// with Y the T0 result (the forward x transform of D(w_y) Y_y + D(w_z) Y_z),
+// then the inverse x transform of Z from registers, stored over Y_x.  The
+// register hand-over is that of k_fft_x_force: the forward leaves item
+// (m, l1) holding kx = l1 + R1 l2, the inputs of the inverse's first stage,
+// so Z never goes back to HBM.
+template <int N, int M>
+__global__ __launch_bounds__(kThreads) void k_fft_x_force_t1(FusedArgs a) {
+  constexpr int R1 = Split<N>::R1, R2 = Split<N>::R2;
+  static_assert(R2 > 1, "columns split over two stages");
+  constexpr int IA = (M * R2 + kThreads - 1) / kThreads;   // forward stage A, inverse stage B
+  constexpr int IB = (M * R1 + kThreads - 1) / kThreads;   // forward stage B, inverse stage A
+  constexpr int SA = ColLds<N, M>::SA, SB = ColLds<N, M>::SB;
+  constexpr int IT = (R1 * R2 + kThreads - 1) / kThreads;
+  __shared__ float2 lds[ColLds<N, M>::size];
+  __shared__ float2 tws[R1 * R2];   // exp(-2 pi i l j / N), l < R1, j < R2
+  int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int mode = tile >= a.nb_main ? 1 : 0;
+  if (mode) tile -= a.nb_main;
+  const ColGeom& g = mode ? a.gp : a.gm;
+  int b, c0;
+  tile_bc<true>(tile, mode ? ((int)gridDim.x - a.nb_main) / g.ntc : a.nb_main / g.ntc, g.ntc, M, b, c0);
+  const long off = b * g.sb + (long)c0 * 8;
+  const int tid = threadIdx.x;
+  const SpecOp& op = a.op;
+  const FftTables& t = a.t;
+  const float2* src = (mode == 0 ? a.in_main : a.in_nyq) + off;
+  const float2* yh = (mode == 0 ? op.in_c[1] : op.in_q[1]) + off;
+  // (ky, kz) of column m; masked columns map to the zero mode
+  auto freq = [&](int m, int& ky, int& kz) {
+    if (c0 + m >= g.ncols) { ky = 0; kz = 0; }
+    else if (mode == 0) { ky = b; kz = c0 + m; }
+    else { ky = c0 + m; kz = N / 2; }
+  };
+  float2 twv[IT];
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const int e = tid + k * kThreads;
+    if (e < R1 * R2) twv[k] = t.tw_n[(e / R2) * (e % R2)];
+  }
+  // forward stage A: rows x = R2 j1 + j2 of Y_x
+  float2 v[IA][R1];
+#pragma unroll
+  for (int i = 0; i < IA; ++i) {
+    const int it = tid + i * kThreads;
+    const int m = it % M, j2 = it / M;
+    const bool ok = it < M * R2 && c0 + m < g.ncols;
+#pragma unroll
+    for (int j1 = 0; j1 < R1; ++j1)
+      v[i][j1] = ok ? src[row_off<true>(R2 * j1 + j2, g.sn) + m * 8] : make_float2(0.f, 0.f);
+  }
+  // c(k) of the stage-B item (m, l1), kx = l1 + R1 l2, computed while the
+  // columns load (later, beside the spectrum and T0's result, it would push
+  // the kernel past 256 registers)
+  float fac[IB][R2];
+#pragma unroll
+  for (int i = 0; i < IB; ++i) {
+    const int it = tid + i * kThreads;
+    if (it < M * R1) {
+      const int m = it % M, l1 = it / M;
+      int ky, kz;
+      freq(m, ky, kz);
+      force_factors<R1, R2, false>(t, op, l1, ky, kz, fac[i]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const int e = tid + k * kThreads;
+    if (e < R1 * R2) tws[e] = twv[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < IA; ++i) {
+    const int it = tid + i * kThreads;
+    if (it < M * R2) {
+      const int m = it % M, j2 = it / M;
+      dft<R1, -1>(v[i]);
+#pragma unroll
+      for (int l1 = 0; l1 < R1; ++l1) lds[l1 * SA + j2 * M + m] = l1 == 0 ? v[i][l1] : cmul(v[i][l1], tws[l1 * R2 + j2]);
+    }
+  }
+  __syncthreads();
+  // forward stage B (kx = l1 + R1 l2), then T0's result with D(w_x) in two
+  // halves of l2 (the compiler barrier keeps the second half's loads from
+  // being hoisted above the first half's use), combined into Z
+  float2 Z[IB][R2];
+#pragma unroll
+  for (int i = 0; i < IB; ++i) {
+    const int it = tid + i * kThreads;
+    if (it < M * R1) {
+      const int m = it % M, l1 = it / M;
+      const bool ok = c0 + m < g.ncols;
+#pragma unroll
+      for (int l2 = 0; l2 < R2; ++l2) Z[i][l2] = lds[l1 * SA + l2 * M + m];
+      dft<R2, -1>(Z[i]);
+      constexpr int H2 = R2 / 2;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        asm volatile("" ::: "memory");
+        float2 yv[H2];
+        float dxv[H2];
+#pragma unroll
+        for (int q = 0; q < H2; ++q) {
+          const int l2 = h * H2 + q;
+          yv[q] = ok ? yh[row_off<true>(l1 + R1 * l2, g.sn) + m * 8] : make_float2(0.f, 0.f);
+          dxv[q] = t.dxy[l1 + R1 * l2];
+        }
+#pragma unroll
+        for (int q = 0; q < H2; ++q) {
+          const int l2 = h * H2 + q;
+          const float2 sv = make_float2(dxv[q] * Z[i][l2].x + yv[q].x, dxv[q] * Z[i][l2].y + yv[q].y);
+          // times -i g: (a + i b)(-i g) = g b - i g a
+          Z[i][l2] = make_float2(fac[i][l2] * sv.y, -fac[i][l2] * sv.x);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // inverse x transform of Z; outputs x = lp + R2 l2p
+#pragma unroll
+  for (int i = 0; i < IB; ++i) {
+    const int it = tid + i * kThreads;
+    if (it < M * R1) {
+      const int m = it % M, l1 = it / M;
+      dft<R2, 1>(Z[i]);
+#pragma unroll
+      for (int lp = 0; lp < R2; ++lp)
+        lds[lp * SB + l1 * M + m] = lp == 0 ? Z[i][0] : cmulc(Z[i][lp], tws[l1 * R2 + lp]);
+    }
+  }
+  __syncthreads();
+  float2* dst = (mode == 0 ? op.out_c[0] : op.out_q[0]) + off;
+#pragma unroll
+  for (int i = 0; i < IA; ++i) {
+    const int it = tid + i * kThreads;
+    if (it < M * R2) {
+      const int m = it % M, lp = it / M;
+      float2 w[R1];
+#pragma unroll
+      for (int l1 = 0; l1 < R1; ++l1) w[l1] = lds[lp * SB + l1 * M + m];
+      dft<R1, 1>(w);
+      if (c0 + m < g.ncols) {
+#pragma unroll
+        for (int l2p = 0; l2p < R1; ++l2p) dst[row_off<true>(lp + R2 * l2p, g.sn) + m * 8] = w[l2p];
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // host-side launch helpers
 // ---------------------------------------------------------------------------
@@ -1526,10 +1679,16 @@ void xforce_t(const FftTables& t, Field* f, const SpecOp& op, hipStream_t s) {
     a.op.in_q[1] = f[1].q;
     a.op.out_c[0] = f[0].c();
     a.op.out_q[0] = f[0].q;
-    hipLaunchKernelGGL((k_fft_x_op<N, M, XOP_T1>), grid, dim3(kThreads), 0, s, a);
-    a.op.kind = OP_IDENTITY;
-    a.op.n_out = 1;
-    hipLaunchKernelGGL((k_fft_x_op<N, M, XOP_OUT>), grid, dim3(kThreads), 0, s, a);
+    if (!op.deconv && !op.split) {
+      hipLaunchKernelGGL((k_fft_x_force_t1<N, M>), grid, dim3(kThreads), 0, s, a);
+    } else {
+      // with the filters the fused kernel would exceed 256 registers: T1,
+      // then an OUT launch of the identity
+      hipLaunchKernelGGL((k_fft_x_op<N, M, XOP_T1>), grid, dim3(kThreads), 0, s, a);
+      a.op.kind = OP_IDENTITY;
+      a.op.n_out = 1;
+      hipLaunchKernelGGL((k_fft_x_op<N, M, XOP_OUT>), grid, dim3(kThreads), 0, s, a);
+    }
   }
 }
 

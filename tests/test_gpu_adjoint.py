@@ -72,6 +72,22 @@ def test_adjoint_matches_oracle_on_same_trajectory(gpu, n_mesh, n_part, steps):
     assert r < 1e-4
 
 
+@pytest.mark.parametrize("opts", [{"deconv_order": 2}, {"split_mode": 1, "split_rs": 2.0},
+                                  {"split_mode": 2, "split_rs": 2.0}])
+def test_adjoint_with_force_filters_on_same_trajectory(gpu, opts):
+    # the deconvolution and split filters are real and even in k, so the
+    # transposed force applies them unchanged
+    banner(f"adjoint same-trajectory with {opts}")
+    w = inputs.scaled(inputs.ADJ_SMALL, 64, 32, n_steps=3, **opts)
+    noise, target = setup(w)
+    ck, g_g = gpu_run_and_grad(w, noise, target)
+    xs = [ck[i, 0] for i in range(len(w.a_list))]
+    g_o = A.grad_along_trajectory(xs, noise, w, target, SIGMA, **opts)
+    r = rel(g_g, g_o)
+    record("same_traj_filters_" + "_".join(f"{k}{v}" for k, v in opts.items()), r)
+    assert r < 1e-4
+
+
 def test_autograd_function_matches_direct_call(gpu):
     banner("autograd")
     from paper_2010_11847_amd.autograd import simulate

@@ -39,14 +39,16 @@ def test_multiplier_transpose_dot_product():
         np.testing.assert_allclose(A.apply_multiplier(w, np.conj(m)), -A.apply_multiplier(w, m), atol=1e-12)
 
 
-def test_force_vjp_matches_fd():
+@pytest.mark.parametrize("opts", [{}, {"deconv_order": 2}, {"split_mode": 1, "split_rs": 1.5},
+                                  {"split_mode": 2, "split_rs": 1.5}])
+def test_force_vjp_matches_fd(opts):
     n = 16
     x = inputs.clustered_positions(300, n, seed=3).astype(np.float64)
     rng = np.random.default_rng(3)
     fb = rng.normal(size=x.shape)
     v = rng.normal(size=x.shape)
-    lhs = np.sum(A.force_vjp(x, n, 300, OM, fb) * v)
-    rhs = np.sum(fb * fd(lambda y: pm.force(y, n, 300, OM), x, v, 1e-7))
+    lhs = np.sum(A.force_vjp(x, n, 300, OM, fb, **opts) * v)
+    rhs = np.sum(fb * fd(lambda y: pm.force(y, n, 300, OM, **opts), x, v, 1e-7))
     assert lhs == pytest.approx(rhs, rel=1e-5)
 
 
