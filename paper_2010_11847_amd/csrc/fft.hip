@@ -1049,173 +1049,6 @@ __device__ __forceinline__ void force_factors(const FftTables& t, const SpecOp& 
   }
 }
 
-// Single-transform column passes over the x-blocked spectrum (N >= 64,
-// two-stage columns) for the transpose of the force (the adjoint's fan-in,
-// OP_FORCE_T), with Y_d the forward-(z, y) spectra of its three inputs:
-//   T0  : forward x of D(w_y) Y_y + D(w_z) Y_z (both factors are constant
-//         along x), stored over Y_y;
-//   T1  : forward x of Y_x, times D(w_x), plus T0's result, times -i g(k),
-//         stored over Y_x;
-//   OUT : inverse x transform of D(w_x)^p times the input, stored with the
-//         coefficient of every output of power p (the identity op inverts
-//         T1's result in place).
-enum XOpMode { XOP_OUT = 1, XOP_T0 = 2, XOP_T1 = 3 };
-
-template <int N, int M, int MODE>
-__global__ __launch_bounds__(kThreads) void k_fft_x_op(FusedArgs a) {
-  constexpr int R1 = Split<N>::R1, R2 = Split<N>::R2;
-  static_assert(R2 > 1, "columns split over two stages");
-  constexpr int IA = (M * R2 + kThreads - 1) / kThreads;
-  constexpr int IB = (M * R1 + kThreads - 1) / kThreads;
-  constexpr int SA = ColLds<N, M>::SA;
-  constexpr int DIR = MODE == XOP_OUT ? 1 : -1;
-  __shared__ float2 lds[ColLds<N, M>::size];
-  int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int mode = tile >= a.nb_main ? 1 : 0;
-  if (mode) tile -= a.nb_main;
-  const ColGeom& g = mode ? a.gp : a.gm;
-  int b, c0;
-  tile_bc<true>(tile, mode ? ((int)gridDim.x - a.nb_main) / g.ntc : a.nb_main / g.ntc, g.ntc, M, b, c0);
-  const long off = b * g.sb + (long)c0 * 8;
-  const int tid = threadIdx.x;
-  const SpecOp& op = a.op;
-  const FftTables& t = a.t;
-  const int p = a.pbasis;
-  const float2* src = (mode == 0 ? a.in_main : a.in_nyq) + off;
-  // (ky, kz) of column m; masked columns map to the zero mode
-  auto freq = [&](int m, int& ky, int& kz) {
-    if (c0 + m >= g.ncols) { ky = 0; kz = 0; }
-    else if (mode == 0) { ky = b; kz = c0 + m; }
-    else { ky = c0 + m; kz = N / 2; }
-  };
-  // stage A: rows n = R2*j1 + j2 (kx for OUT, x for T0 and T1).  The symbol
-  // factors of OUT are loaded before the data and pinned in registers.
-#pragma unroll
-  for (int i = 0; i < IA; ++i) {
-    const int it = tid + i * kThreads;
-    if (it < M * R2) {
-      const int m = it % M, j2 = it / M;
-      const bool ok = c0 + m < g.ncols;
-      // every global load of the item first (twiddles, symbol factors,
-      // data), then one pin: sunk to their uses, they would go out a few
-      // at a time with waits in between
-      float2 tw[R1];
-      float fac[R1];
-      float2 v[R1];
-      const bool scale_in = MODE == XOP_OUT && p > 0;   // uniform
-#pragma unroll
-      for (int l1 = 1; l1 < R1; ++l1) tw[l1] = tw_get<DIR>(t.tw_n, j2 * l1);
-      if (scale_in) {
-#pragma unroll
-        for (int j1 = 0; j1 < R1; ++j1) fac[j1] = t.dxy[R2 * j1 + j2];
-      }
-#pragma unroll
-      for (int j1 = 0; j1 < R1; ++j1)
-        v[j1] = ok ? src[row_off<true>(R2 * j1 + j2, g.sn) + m * 8] : make_float2(0.f, 0.f);
-      if constexpr (MODE == XOP_T0) {
-        // D(w_y) Y_y + D(w_z) Y_z: src is Y_y, the second input Y_z
-        const float2* src2 = (mode == 0 ? op.in_c[1] : op.in_q[1]) + off;
-        float2 u[R1];
-#pragma unroll
-        for (int j1 = 0; j1 < R1; ++j1)
-          u[j1] = ok ? src2[row_off<true>(R2 * j1 + j2, g.sn) + m * 8] : make_float2(0.f, 0.f);
-        int ky, kz;
-        freq(m, ky, kz);
-        const float dy = t.dxy[ky], dz = t.dz[kz];
-#pragma unroll
-        for (int j1 = 0; j1 < R1; ++j1) v[j1] = make_float2(dy * v[j1].x + dz * u[j1].x, dy * v[j1].y + dz * u[j1].y);
-      }
-#pragma unroll
-      for (int l1 = 1; l1 < R1; ++l1) asm volatile("" : "+v"(tw[l1]));
-      if (scale_in) {
-#pragma unroll
-        for (int j1 = 0; j1 < R1; ++j1) v[j1] = cscale(v[j1], powp(fac[j1], p));
-      }
-      dft<R1, DIR>(v);
-#pragma unroll
-      for (int l1 = 0; l1 < R1; ++l1) lds[l1 * SA + j2 * M + m] = l1 == 0 ? v[l1] : cmul(v[l1], tw[l1]);
-    }
-  }
-  __syncthreads();
-  // stage B: outputs n = l1 + R1*l2
-#pragma unroll
-  for (int i = 0; i < IB; ++i) {
-    const int it = tid + i * kThreads;
-    if (it < M * R1) {
-      const int m = it % M, l1 = it / M;
-      float2 v[R2];
-#pragma unroll
-      for (int j2 = 0; j2 < R2; ++j2) v[j2] = lds[l1 * SA + j2 * M + m];
-      dft<R2, DIR>(v);
-      if (c0 + m < g.ncols) {
-        int ky, kz;
-        freq(m, ky, kz);
-        if constexpr (MODE == XOP_T0) {
-          float2* dst = (mode == 0 ? op.out_c[0] : op.out_q[0]) + off;
-#pragma unroll
-          for (int l2 = 0; l2 < R2; ++l2) dst[row_off<true>(l1 + R1 * l2, g.sn) + m * 8] = v[l2];
-        } else if constexpr (MODE == XOP_T1) {
-          // (D(w_x) X + Y) * (-i g): T0's result and every factor loaded
-          // before the first store
-          const float2* yh = (mode == 0 ? op.in_c[1] : op.in_q[1]) + off;
-          float2 yv[R2];
-          float fac[R2], dxv[R2];
-#pragma unroll
-          for (int l2 = 0; l2 < R2; ++l2) yv[l2] = yh[row_off<true>(l1 + R1 * l2, g.sn) + m * 8];
-#pragma unroll
-          for (int l2 = 0; l2 < R2; ++l2) {
-            fac[l2] = t.kxy[l1 + R1 * l2];
-            dxv[l2] = t.dxy[l1 + R1 * l2];
-          }
-#pragma unroll
-          for (int l2 = 0; l2 < R2; ++l2) asm volatile("" : "+v"(fac[l2]), "+v"(dxv[l2]), "+v"(yv[l2]));
-          const float kyz = t.kxy[ky] + t.kz[kz];
-#pragma unroll
-          for (int l2 = 0; l2 < R2; ++l2) {
-            const float kk = fac[l2] + kyz;
-            fac[l2] = kk > 0.f ? op.scale * __builtin_amdgcn_rcpf(kk) : 0.f;
-          }
-          if (op.deconv) {
-            const float wyz = t.wxy[ky] * t.wz[kz];
-#pragma unroll
-            for (int l2 = 0; l2 < R2; ++l2) {
-              const float wv = t.wxy[l1 + R1 * l2] * wyz;
-              fac[l2] *= __builtin_amdgcn_rcpf(op.deconv == 1 ? wv : wv * wv);
-            }
-          }
-          if (op.split) {
-            const float syz = t.sxy[ky] * t.sz[kz];
-#pragma unroll
-            for (int l2 = 0; l2 < R2; ++l2) {
-              const float sv = t.sxy[l1 + R1 * l2] * syz;
-              fac[l2] *= (op.split == 1 ? sv : 1.f - sv);
-            }
-          }
-          float2* dst = (mode == 0 ? op.out_c[0] : op.out_q[0]) + off;
-#pragma unroll
-          for (int l2 = 0; l2 < R2; ++l2) {
-            const float2 s = make_float2(dxv[l2] * v[l2].x + yv[l2].x, dxv[l2] * v[l2].y + yv[l2].y);
-            // times -i g: (a + i b)(-i g) = g b - i g a
-            dst[row_off<true>(l1 + R1 * l2, g.sn) + m * 8] = make_float2(fac[l2] * s.y, -fac[l2] * s.x);
-          }
-        } else {
-          const float dy = t.dxy[ky], dz = t.dz[kz];
-#pragma unroll 1
-          for (int o = 0; o < op.n_out; ++o) {
-            const Term tm = op_term(op.kind, o);
-            if (tm.p != p) continue;
-            const float2 cf = coef_of(tm, dy, dz);
-            float2* dst = (mode == 0 ? op.out_c[o] : op.out_q[o]) + off;
-#pragma unroll
-            for (int l2 = 0; l2 < R2; ++l2) dst[row_off<true>(l1 + R1 * l2, g.sn) + m * 8] = cmul(v[l2], cf);
-          }
-        }
-      }
-    }
-  }
-}
-
-
 // The force's whole x pass in one tile (OP_FORCE_XS, N >= 64): the forward
 // x transform, times c(k), then two inverse x transforms, each output times
 // i: D(w_x) c X into out[0] (F_x, over the input) and c X into out[1] (the
@@ -1358,17 +1191,26 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_force(FusedArgs a) {
 }
 
 
-// The second half of the transposed force's x pass (OP_FORCE_T, N >= 64,
-// no deconvolution or split) in one tile: the forward x transform of Y_x, then Z = (D(w_x) X + Y) (-i g)
-// with Y the T0 result (the forward x transform of D(w_y) Y_y + D(w_z) Y_z),
-// then the inverse x transform of Z from registers, stored over Y_x.  The
-// register hand-over is that of k_fft_x_force: the forward leaves item
-// (m, l1) holding kx = l1 + R1 l2, the inputs of the inverse's first stage,
-// so Z never goes back to HBM.
-template <int N, int M>
-__global__ __launch_bounds__(kThreads) void k_fft_x_force_t1(FusedArgs a) {
+// The transposed force's whole x pass (OP_FORCE_T, N >= 64) in one tile:
+// with Y_d the forward-(z, y) spectra of the three painted channels, the
+// result is the inverse x transform of -i g(k) times the forward x
+// transform of
+//   w(x) = S[Y_x](x) + D(w_y) Y_y(x) + D(w_z) Y_z(x),
+// where S is the periodic five-point stencil whose discrete Fourier symbol
+// is exactly D(w_x) (shift theorem):
+//   S[Y](x) = [8 (Y(x+1) - Y(x-1)) - (Y(x+2) - Y(x-2))] / (12 i),
+// so one forward transform serves all three channels.  D(w_y) and D(w_z)
+// are constant along x.  A tile holds whole x columns, so the stencil reads
+// its neighbours from a staging copy of the Y_x tile in LDS.  The result
+// replaces Y_x; the register hand-over between the forward and the inverse
+// transform is that of k_fft_x_force.  (The stencil differences a painted
+// cotangent field, not a smooth potential, so it costs no precision that
+// the spectral product keeps.)
+template <int N, int M, bool FILT>
+__global__ __launch_bounds__(kThreads) void k_fft_x_force_t(FusedArgs a) {
   constexpr int R1 = Split<N>::R1, R2 = Split<N>::R2;
   static_assert(R2 > 1, "columns split over two stages");
+  static_assert(N * M <= ColLds<N, M>::size, "the staging copy fits the exchange buffer");
   constexpr int IA = (M * R2 + kThreads - 1) / kThreads;   // forward stage A, inverse stage B
   constexpr int IB = (M * R1 + kThreads - 1) / kThreads;   // forward stage B, inverse stage A
   constexpr int SA = ColLds<N, M>::SA, SB = ColLds<N, M>::SB;
@@ -1385,8 +1227,9 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_force_t1(FusedArgs a) {
   const int tid = threadIdx.x;
   const SpecOp& op = a.op;
   const FftTables& t = a.t;
-  const float2* src = (mode == 0 ? a.in_main : a.in_nyq) + off;
-  const float2* yh = (mode == 0 ? op.in_c[1] : op.in_q[1]) + off;
+  const float2* yx = (mode == 0 ? op.in_c[0] : op.in_q[0]) + off;
+  const float2* yy = (mode == 0 ? op.in_c[1] : op.in_q[1]) + off;
+  const float2* yz = (mode == 0 ? op.in_c[2] : op.in_q[2]) + off;
   // (ky, kz) of column m; masked columns map to the zero mode
   auto freq = [&](int m, int& ky, int& kz) {
     if (c0 + m >= g.ncols) { ky = 0; kz = 0; }
@@ -1399,20 +1242,32 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_force_t1(FusedArgs a) {
     const int e = tid + k * kThreads;
     if (e < R1 * R2) twv[k] = t.tw_n[(e / R2) * (e % R2)];
   }
-  // forward stage A: rows x = R2 j1 + j2 of Y_x
-  float2 v[IA][R1];
+  // rows x = R2 j1 + j2: Y_x to the staging copy, D(w_y) Y_y + D(w_z) Y_z
+  // into w
+  float2 w[IA][R1];
 #pragma unroll
   for (int i = 0; i < IA; ++i) {
     const int it = tid + i * kThreads;
     const int m = it % M, j2 = it / M;
     const bool ok = it < M * R2 && c0 + m < g.ncols;
+    int ky, kz;
+    freq(m, ky, kz);
+    const float dy = t.dxy[ky], dz = t.dz[kz];
+    float2 vx[R1];
 #pragma unroll
-    for (int j1 = 0; j1 < R1; ++j1)
-      v[i][j1] = ok ? src[row_off<true>(R2 * j1 + j2, g.sn) + m * 8] : make_float2(0.f, 0.f);
+    for (int j1 = 0; j1 < R1; ++j1) vx[j1] = ok ? yx[row_off<true>(R2 * j1 + j2, g.sn) + m * 8] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int j1 = 0; j1 < R1; ++j1) {
+      const float2 py = ok ? yy[row_off<true>(R2 * j1 + j2, g.sn) + m * 8] : make_float2(0.f, 0.f);
+      const float2 pz = ok ? yz[row_off<true>(R2 * j1 + j2, g.sn) + m * 8] : make_float2(0.f, 0.f);
+      w[i][j1] = make_float2(dy * py.x + dz * pz.x, dy * py.y + dz * pz.y);
+    }
+    if (it < M * R2) {
+#pragma unroll
+      for (int j1 = 0; j1 < R1; ++j1) lds[(R2 * j1 + j2) * M + m] = vx[j1];
+    }
   }
-  // c(k) of the stage-B item (m, l1), kx = l1 + R1 l2, computed while the
-  // columns load (later, beside the spectrum and T0's result, it would push
-  // the kernel past 256 registers)
+  // c(k) of the stage-B item (m, l1), kx = l1 + R1 l2
   float fac[IB][R2];
 #pragma unroll
   for (int i = 0; i < IB; ++i) {
@@ -1421,7 +1276,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_force_t1(FusedArgs a) {
       const int m = it % M, l1 = it / M;
       int ky, kz;
       freq(m, ky, kz);
-      force_factors<R1, R2, false>(t, op, l1, ky, kz, fac[i]);
+      force_factors<R1, R2, FILT>(t, op, l1, ky, kz, fac[i]);
     }
   }
 #pragma unroll
@@ -1430,50 +1285,48 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_force_t1(FusedArgs a) {
     if (e < R1 * R2) tws[e] = twv[k];
   }
   __syncthreads();
+  // w += S[Y_x]: d / (12 i) = (d.y, -d.x) / 12
 #pragma unroll
   for (int i = 0; i < IA; ++i) {
     const int it = tid + i * kThreads;
     if (it < M * R2) {
       const int m = it % M, j2 = it / M;
-      dft<R1, -1>(v[i]);
 #pragma unroll
-      for (int l1 = 0; l1 < R1; ++l1) lds[l1 * SA + j2 * M + m] = l1 == 0 ? v[i][l1] : cmul(v[i][l1], tws[l1 * R2 + j2]);
+      for (int j1 = 0; j1 < R1; ++j1) {
+        const int x = R2 * j1 + j2;
+        const float2 p1 = lds[((x + 1) & (N - 1)) * M + m], m1 = lds[((x - 1) & (N - 1)) * M + m];
+        const float2 p2 = lds[((x + 2) & (N - 1)) * M + m], m2 = lds[((x - 2) & (N - 1)) * M + m];
+        const float2 d = make_float2(8.f * (p1.x - m1.x) - (p2.x - m2.x), 8.f * (p1.y - m1.y) - (p2.y - m2.y));
+        constexpr float k12 = 1.f / 12.f;
+        w[i][j1] = make_float2(w[i][j1].x + k12 * d.y, w[i][j1].y - k12 * d.x);
+      }
+    }
+  }
+  __syncthreads();   // the staging copy is read before the exchange reuses it
+  // forward stage A
+#pragma unroll
+  for (int i = 0; i < IA; ++i) {
+    const int it = tid + i * kThreads;
+    if (it < M * R2) {
+      const int m = it % M, j2 = it / M;
+      dft<R1, -1>(w[i]);
+#pragma unroll
+      for (int l1 = 0; l1 < R1; ++l1) lds[l1 * SA + j2 * M + m] = l1 == 0 ? w[i][l1] : cmul(w[i][l1], tws[l1 * R2 + j2]);
     }
   }
   __syncthreads();
-  // forward stage B (kx = l1 + R1 l2), then T0's result with D(w_x) in two
-  // halves of l2 (the compiler barrier keeps the second half's loads from
-  // being hoisted above the first half's use), combined into Z
+  // forward stage B (kx = l1 + R1 l2), times -i g: (a + i b)(-i g) = g b - i g a
   float2 Z[IB][R2];
 #pragma unroll
   for (int i = 0; i < IB; ++i) {
     const int it = tid + i * kThreads;
     if (it < M * R1) {
       const int m = it % M, l1 = it / M;
-      const bool ok = c0 + m < g.ncols;
 #pragma unroll
       for (int l2 = 0; l2 < R2; ++l2) Z[i][l2] = lds[l1 * SA + l2 * M + m];
       dft<R2, -1>(Z[i]);
-      constexpr int H2 = R2 / 2;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        asm volatile("" ::: "memory");
-        float2 yv[H2];
-        float dxv[H2];
-#pragma unroll
-        for (int q = 0; q < H2; ++q) {
-          const int l2 = h * H2 + q;
-          yv[q] = ok ? yh[row_off<true>(l1 + R1 * l2, g.sn) + m * 8] : make_float2(0.f, 0.f);
-          dxv[q] = t.dxy[l1 + R1 * l2];
-        }
-#pragma unroll
-        for (int q = 0; q < H2; ++q) {
-          const int l2 = h * H2 + q;
-          const float2 sv = make_float2(dxv[q] * Z[i][l2].x + yv[q].x, dxv[q] * Z[i][l2].y + yv[q].y);
-          // times -i g: (a + i b)(-i g) = g b - i g a
-          Z[i][l2] = make_float2(fac[i][l2] * sv.y, -fac[i][l2] * sv.x);
-        }
-      }
+      for (int l2 = 0; l2 < R2; ++l2) Z[i][l2] = make_float2(fac[i][l2] * Z[i][l2].y, -fac[i][l2] * Z[i][l2].x);
     }
   }
   __syncthreads();
@@ -1496,13 +1349,13 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_force_t1(FusedArgs a) {
     const int it = tid + i * kThreads;
     if (it < M * R2) {
       const int m = it % M, lp = it / M;
-      float2 w[R1];
+      float2 v[R1];
 #pragma unroll
-      for (int l1 = 0; l1 < R1; ++l1) w[l1] = lds[lp * SB + l1 * M + m];
-      dft<R1, 1>(w);
+      for (int l1 = 0; l1 < R1; ++l1) v[l1] = lds[lp * SB + l1 * M + m];
+      dft<R1, 1>(v);
       if (c0 + m < g.ncols) {
 #pragma unroll
-        for (int l2p = 0; l2p < R1; ++l2p) dst[row_off<true>(lp + R2 * l2p, g.sn) + m * 8] = w[l2p];
+        for (int l2p = 0; l2p < R1; ++l2p) dst[row_off<true>(lp + R2 * l2p, g.sn) + m * 8] = v[l2p];
       }
     }
   }
@@ -1649,8 +1502,9 @@ void xforce(const FftTables& t, const Field& in, const SpecOp& op, hipStream_t s
   }
 }
 
-// The transposed force's x pass (T0, T1, identity OUT) over f[0..2] = the
-// forward-(z, y) spectra of the x, y, z inputs; the result replaces f[0].
+// The transposed force's x pass (one launch of k_fft_x_force_t) over
+// f[0..2] = the forward-(z, y) spectra of the x, y, z inputs; the result
+// replaces f[0], f[1] and f[2] are left as they were.
 template <int N>
 void xforce_t(const FftTables& t, Field* f, const SpecOp& op, hipStream_t s) {
   if constexpr (Split<N>::R2 > 1) {
@@ -1665,30 +1519,19 @@ void xforce_t(const FftTables& t, Field* f, const SpecOp& op, hipStream_t s) {
     a.park_main = nullptr;
     a.park_nyq = nullptr;
     a.pbasis = 0;
-    const dim3 grid(a.nb_main + a.gp.ntc);
-    a.in_main = f[1].c();
-    a.in_nyq = f[1].q;
-    a.op.in_c[1] = f[2].c();
-    a.op.in_q[1] = f[2].q;
-    a.op.out_c[0] = f[1].c();
-    a.op.out_q[0] = f[1].q;
-    hipLaunchKernelGGL((k_fft_x_op<N, M, XOP_T0>), grid, dim3(kThreads), 0, s, a);
-    a.in_main = f[0].c();
-    a.in_nyq = f[0].q;
-    a.op.in_c[1] = f[1].c();
-    a.op.in_q[1] = f[1].q;
+    for (int d = 0; d < 3; ++d) {
+      a.op.in_c[d] = f[d].c();
+      a.op.in_q[d] = f[d].q;
+    }
     a.op.out_c[0] = f[0].c();
     a.op.out_q[0] = f[0].q;
-    if (!op.deconv && !op.split) {
-      hipLaunchKernelGGL((k_fft_x_force_t1<N, M>), grid, dim3(kThreads), 0, s, a);
-    } else {
-      // with the filters the fused kernel would exceed 256 registers: T1,
-      // then an OUT launch of the identity
-      hipLaunchKernelGGL((k_fft_x_op<N, M, XOP_T1>), grid, dim3(kThreads), 0, s, a);
-      a.op.kind = OP_IDENTITY;
-      a.op.n_out = 1;
-      hipLaunchKernelGGL((k_fft_x_op<N, M, XOP_OUT>), grid, dim3(kThreads), 0, s, a);
-    }
+    a.in_main = f[0].c();
+    a.in_nyq = f[0].q;
+    const dim3 grid(a.nb_main + a.gp.ntc);
+    if (op.deconv || op.split)
+      hipLaunchKernelGGL((k_fft_x_force_t<N, M, true>), grid, dim3(kThreads), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_fft_x_force_t<N, M, false>), grid, dim3(kThreads), 0, s, a);
   }
 }
 
