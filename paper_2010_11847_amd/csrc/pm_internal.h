@@ -101,7 +101,8 @@ void fft_x_force(const FftTables& t, const Field& in, const SpecOp& op, hipStrea
 void fft_y_force(const FftTables& t, Field* f, hipStream_t s);
 // x pass of the transposed force (OP_FORCE_T: op.scale, deconv, split) over
 // the forward-(z, y) spectra f[0..2] of its x, y, z inputs; the result (the
-// fan-in, inverse-x transformed) replaces f[0]; f[1] is overwritten.
+// fan-in, inverse-x transformed) replaces f[0]; below 64^3 the other two
+// inputs may be overwritten as well.
 void fft_x_force_t(const FftTables& t, Field* f, const SpecOp& op, hipStream_t s);
 // Single passes (the composites above call these).
 void fft_z_r2c(const FftTables& t, Field* f, int nf, hipStream_t s);
