@@ -23,12 +23,15 @@ constexpr int kThreads = 256;
 //   NCH = 3: V(c) = k pbar[id] . F(c) with F the interleaved force mesh
 //            (x-blocked cells of 3 floats)
 //   NCH = 1: V(c) = k M(c) with M a real mesh, x-blocked (STD: [x][y][z])
-template <int NCH, bool STD>
+//   ADD1 (with NCH = 3): V(c) += M1(c), a real x-blocked mesh with weight 1,
+//            so that both terms of one force evaluation share one pass
+template <int NCH, bool STD, bool ADD1 = false>
 __global__ __launch_bounds__(kThreads) void k_readout_grad(const float* __restrict__ pos,
                                                            const uint32_t* __restrict__ id, long np, int n,
                                                            const float* __restrict__ mesh,
                                                            const float* __restrict__ pbar, float k,
-                                                           float* __restrict__ xbar) {
+                                                           float* __restrict__ xbar,
+                                                           const float* __restrict__ m1 = nullptr) {
   const long j = (long)xcd_tile(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
   if (j >= np) return;
   int ix, iy, iz;
@@ -71,6 +74,7 @@ __global__ __launch_bounds__(kThreads) void k_readout_grad(const float* __restri
           val = c0 * mesh[3 * cell] + c1 * mesh[3 * cell + 1] + c2 * mesh[3 * cell + 2];
         else
           val = c0 * mesh[cell];
+        if constexpr (ADD1) val += m1[cell];
         const float sa = a ? 1.f : -1.f, sb = b ? 1.f : -1.f, sc = c ? 1.f : -1.f;
         gx += sa * wy[b] * wz[c] * val;
         gy += wx[a] * sb * wz[c] * val;
@@ -140,6 +144,13 @@ void launch_readout_grad3(const float* pos, const uint32_t* id, long np, int n, 
   const int grid = (int)((np + kThreads - 1) / kThreads);
   hipLaunchKernelGGL((k_readout_grad<3, false>), dim3(grid), dim3(kThreads), 0, s, pos, id, np, n, fi, pbar, k,
                      xbar);
+}
+
+void launch_readout_grad31(const float* pos, const uint32_t* id, long np, int n, const float* fi, const float* pbar,
+                           float k, const float* m1, float* xbar, hipStream_t s) {
+  const int grid = (int)((np + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL((k_readout_grad<3, false, true>), dim3(grid), dim3(kThreads), 0, s, pos, id, np, n, fi, pbar, k,
+                     xbar, m1);
 }
 
 void launch_readout_grad1(const float* pos, const uint32_t* id, long np, int n, const float* m0, float k, float* xbar,

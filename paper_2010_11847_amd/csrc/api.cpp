@@ -927,8 +927,12 @@ int pm_run_adjoint(pm_ctx* ctx, const double* h_a, int n_a, const float* d_ckpt,
         c.paint(0, np, c.mesh[0].r);
         c.force_meshes();
       }
-      // term A: positions at which the force meshes are read out
-      pmk::launch_readout_grad3(c.pos_s[0], c.id_s[0], np, c.ng, fmesh, pbar, (float)kj, xbar, c.stream);
+      // term A: positions at which the force meshes are read out; it joins
+      // term B's pass at the end of the step unless the pyramid below uses
+      // the force mesh as scratch
+      const bool fuse_ab = !c.nc || use_fck;
+      if (!fuse_ab)
+        pmk::launch_readout_grad3(c.pos_s[0], c.id_s[0], np, c.ng, fmesh, pbar, (float)kj, xbar, c.stream);
       // term B: positions that paint the density, through G^T
       pmk::launch_absmax(pbar, 3 * np, c.misc, c.stream);
       for (int d = 0; d < 3; ++d)
@@ -993,7 +997,11 @@ int pm_run_adjoint(pm_ctx* ctx, const double* h_a, int n_a, const float* d_ckpt,
         f1.p[0] = c.mesh[0].r;
         c.pyr_chain(true, 1, c1, f1, lv, scr3, n3 / 2, pmk::PYR_ADD, nullptr, 0.f);
       }
-      pmk::launch_readout_grad1(c.pos_s[0], c.id_s[0], np, c.ng, c.mesh[0].r, 1.f, xbar, false, c.stream);
+      if (fuse_ab)
+        pmk::launch_readout_grad31(c.pos_s[0], c.id_s[0], np, c.ng, fmesh, pbar, (float)kj, c.mesh[0].r, xbar,
+                                   c.stream);
+      else
+        pmk::launch_readout_grad1(c.pos_s[0], c.id_s[0], np, c.ng, c.mesh[0].r, 1.f, xbar, false, c.stream);
     }
     if (j > 0) pmk::launch_axpy(pbar, xbar, (float)dr[j - 1], (long)ck, c.stream);
   }

@@ -130,6 +130,10 @@ void launch_scale(float* p, long n, float v, hipStream_t s);
 // adjoint kernels (adjoint.hip)
 void launch_readout_grad3(const float* pos, const uint32_t* id, long np, int n, const float* fi, const float* pbar,
                           float k, float* xbar, hipStream_t s);
+// Both readout terms of one force evaluation in one pass: the readout_grad3
+// term plus that of the real x-blocked mesh m1 with weight 1.
+void launch_readout_grad31(const float* pos, const uint32_t* id, long np, int n, const float* fi, const float* pbar,
+                           float k, const float* m1, float* xbar, hipStream_t s);
 // m0: real mesh, x-blocked (std_layout: plain [x][y][z])
 void launch_readout_grad1(const float* pos, const uint32_t* id, long np, int n, const float* m0, float k, float* xbar,
                           bool std_layout, hipStream_t s);
