@@ -59,21 +59,29 @@ __global__ void k_lpt_delta2(const float* __restrict__ xx, const float* __restri
 }
 
 // x = B q + shift + B (D1 s1 + D2 s2) (wrapped); p = B a0^2 E (f1 D1 s1 + f2 D2 s2)
+// np is a power of two: the lattice site comes from shifts (a 64-bit
+// division per particle costs more than the particle's memory traffic), and
+// position and momentum are stored as one 12-byte access each.
 __global__ void k_lpt_particles(LptParticleArgs a) {
-  const long n3 = (long)a.np * a.np * a.np;
+  const int ln = __builtin_ctz(a.np);
+  const long n3 = 1L << (3 * ln);
   const long stride = (long)gridDim.x * blockDim.x;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n3; i += stride) {
-    const int q[3] = {(int)(i / ((long)a.np * a.np)), (int)((i / a.np) % a.np), (int)(i % a.np)};
+    const int q[3] = {(int)(i >> (2 * ln)), (int)((i >> ln) & (a.np - 1)), (int)(i & (a.np - 1))};
     const long e = blk_real(q[0], q[1], q[2], a.np);   // lattice fields are x-blocked
+    float x[3], p[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const float s1 = a.s1[d][e];
       const float s2 = a.has_s2 ? a.s2[d][e] : 0.f;
       const float dx = a.cx1 * s1 + a.cx2 * s2;
-      const float x = (float)(a.ratio * q[d]) + a.shift + dx;
-      a.pos[3 * i + d] = wrap_pos(x, a.nmesh);
-      a.mom[3 * i + d] = a.cp1 * s1 + a.cp2 * s2;
+      x[d] = wrap_pos((float)(a.ratio * q[d]) + a.shift + dx, a.nmesh);
+      p[d] = a.cp1 * s1 + a.cp2 * s2;
     }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) a.pos[3 * i + d] = x[d];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) a.mom[3 * i + d] = p[d];
   }
 }
 
