@@ -176,12 +176,25 @@ def eh_nowiggle_transfer(k, cosmo):
     return L0 / (L0 + C0 * q * q)
 
 
+def table_power(k, table):
+    """A caller's tabulated P(k), interpolated linearly in (ln k, ln P); beyond
+    the first or last point the end segment's line continues."""
+    lk = np.log(np.asarray(table[0], dtype=np.float64))
+    lp = np.log(np.maximum(np.asarray(table[1], dtype=np.float64), 1e-300))
+    x = np.log(np.asarray(k, dtype=np.float64))
+    i = np.clip(np.searchsorted(lk, x, side="right"), 1, len(lk) - 1)
+    t = (x - lk[i - 1]) / (lk[i] - lk[i - 1])
+    return np.exp(lp[i - 1] + t * (lp[i] - lp[i - 1]))
+
+
 def _pk_shape(k, cosmo):
     k = np.asarray(k, dtype=np.float64)
     if cosmo.pk_kind == 0:
         return k ** cosmo.pk_index
     if cosmo.pk_kind == 1:
         return k ** cosmo.n_s * eh_nowiggle_transfer(k, cosmo) ** 2
+    if cosmo.pk_kind == 2:
+        return table_power(k, cosmo.pk_table)
     raise ValueError("unsupported pk_kind for the oracle")
 
 
@@ -210,6 +223,8 @@ def pk_amplitude(cosmo):
     """Amplitude A so that sigma8 of the linear P(k) at a = 1 matches cosmo.sigma8."""
     if cosmo.pk_amp > 0:
         return float(cosmo.pk_amp)
+    if cosmo.pk_kind == 2:   # a table is taken as given
+        return 1.0
     if cosmo.pk_kind == 0 and cosmo.pk_index == -2.0:
         return powerlaw_amplitude_sigma8(cosmo)
     s = sigma_r(lambda k: _pk_shape(k, cosmo), 8.0)

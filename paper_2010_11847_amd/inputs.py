@@ -42,8 +42,9 @@ class Cosmology:
     sigma8: float = 0.8
     t_cmb: float = 2.7255
     pk_kind: int = PK_EH_NOWIGGLE
-    pk_amp: float = 0.0      # 0: normalise to sigma8
+    pk_amp: float = 0.0      # 0: normalise to sigma8 (PK_TABLE: 0 means 1, the table as given)
     pk_index: float = -2.0   # power-law index (PK_POWERLAW)
+    pk_table: Tuple[Tuple[float, ...], Tuple[float, ...]] = ()   # PK_TABLE: (k in h/Mpc increasing, P)
 
 
 @dataclass(frozen=True)

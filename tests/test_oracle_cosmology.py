@@ -100,3 +100,21 @@ def test_eh_nowiggle_limits_and_normalisation():
     k = np.array([50.0, 100.0])
     tk = C.eh_nowiggle_transfer(k, cos)
     assert -2.3 < np.log(tk[1] / tk[0]) / np.log(2.0) < -1.6
+
+
+def test_table_power_is_exact_on_a_sampled_power_law():
+    # log-log interpolation reproduces a power law at any k, extrapolation
+    # beyond both ends included, so a sampled A k^-2 is the power law itself
+    ks = np.logspace(-3, 0, 20)
+    table = (tuple(ks), tuple(53.6 * ks ** -2.0))
+    k = np.array([2e-4, 1e-3, 3.3e-3, 0.047, 0.5, 1.0, 7.5])
+    np.testing.assert_allclose(C.table_power(k, table), 53.6 * k ** -2.0, rtol=1e-12)
+    cos = Cosmology(pk_kind=2, pk_table=table)
+    np.testing.assert_allclose(C.linear_power(k, cos), 53.6 * k ** -2.0, rtol=1e-12)   # amplitude 1
+    assert C.linear_power(np.array([0.0]), cos)[0] == 0.0
+
+
+def test_table_power_interpolates_between_points():
+    # a kink between two points: the midpoint in ln k gets the geometric mean
+    table = ((0.1, 1.0), (2.0, 8.0))
+    np.testing.assert_allclose(C.table_power(np.array([math.sqrt(0.1)]), table), [4.0], rtol=1e-12)
