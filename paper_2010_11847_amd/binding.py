@@ -23,10 +23,18 @@ class PMError(RuntimeError):
 
 def make_config(w: Workload, max_particles: int = 0) -> _lib.pm_config:
     c = w.cosmo
+    tk = tp = None
+    n_tab = 0
+    if c.pk_table:
+        n_tab = len(c.pk_table[0])
+        tk = (C.c_double * n_tab)(*c.pk_table[0])
+        tp = (C.c_double * n_tab)(*c.pk_table[1])
     cos = _lib.pm_cosmo(c.omega_m, c.omega_b, c.h, c.n_s, c.sigma8, c.t_cmb, c.pk_kind,
-                        c.pk_amp, c.pk_index, None, None, 0)
-    return _lib.pm_config(w.box_size, w.n_mesh, w.n_part, cos, w.lpt_order, w.deconv_order,
-                          w.split_rs, w.split_mode, w.lattice_shift, max_particles, w.pyramid_levels)
+                        c.pk_amp, c.pk_index, tk, tp, n_tab)
+    cfg = _lib.pm_config(w.box_size, w.n_mesh, w.n_part, cos, w.lpt_order, w.deconv_order,
+                         w.split_rs, w.split_mode, w.lattice_shift, max_particles, w.pyramid_levels)
+    cfg.keep_alive = (tk, tp)   # the library copies the table in pm_create
+    return cfg
 
 
 def _ptr(t: Optional[torch.Tensor]):
