@@ -168,7 +168,7 @@ def adjoint_section(names=("adj128_mesh256_box400", "pm512_mesh1024_box1024"), r
 
 
 def pyramid_section(w, steps):
-    """The same run with the two-level pyramid force (section 4.2, f = 2):
+    """The same run with the two-level pyramid force (section 5.2, f = 2):
     step time and the extra kernel classes (the paper's scheme targets
     distributed meshes; on one device it adds its passes to the full force)."""
     import torch

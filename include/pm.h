@@ -84,7 +84,7 @@ typedef struct {
     int      split_mode;    /* PM_SPLIT_* */
     double   lattice_shift; /* offset of the particle lattice from mesh nodes, cells, [0, 1) */
     int64_t  max_particles; /* capacity for pm_paint/pm_force/pm_kdk_step; 0 = n_part^3 */
-    int      pyramid_levels; /* 0: single-grid force; f >= 1: the multi-grid force of section 4.2
+    int      pyramid_levels; /* 0: single-grid force; f >= 1: the multi-grid force of section 5.2
                                 (Algorithm 3) with a coarse grid n_mesh / 2^f >= 8 per side,
                                 order-6 B-spline REDUCE/EXPAND; needs deconv_order 0 and no
                                 split; pm_run_adjoint differentiates it (its transpose) */
@@ -232,7 +232,7 @@ int pm_recon_step(pm_ctx* ctx, const double* h_a, int n_a, const float* d_data, 
                   float* d_adam_m, float* d_adam_v, int t, double lr, double beta1, double beta2, double eps,
                   void* d_work, size_t work_bytes, double* h_loss2);
 
-/* Binned power spectrum of a real mesh (section 5.1 two-point statistics):
+/* Binned power spectrum of a real mesh (section 6.1 two-point statistics):
  * P(k_j) = (L^3/N^6) sum_w |delta^|^2 / sum_w, mode weight 2 on interior
  * n_z planes and 1 on n_z = 0 and N/2, bins |n| in [j-1/2, j+1/2),
  * j = 1..n_bins (n_bins <= n_mesh/2).  Only modes with every |n_d| < n_max

@@ -2,7 +2,7 @@
 
 Test infrastructure: see the package docstring.
 
-Section 5.1 compares fields with the transfer function T_f = sqrt(P_a/P_b)
+Section 6.1 compares fields with the transfer function T_f = sqrt(P_a/P_b)
 and the cross-correlation r_c = P_ab / sqrt(P_a P_b).  Estimator (a reading):
 P(k_j) = (L^3/N^6) sum_w |delta^|^2 / sum_w over the half spectrum with mode
 weight 2 on interior planes (0 < n_z < N/2) and 1 on the n_z = 0 and N/2
@@ -61,7 +61,7 @@ def power_k(dk, box_size, n, n_bins=None, n_max=0):
 
 
 def transfer_and_correlation(a, b, box_size):
-    """T_f = sqrt(P_a/P_b), r_c = P_ab / sqrt(P_a P_b) (section 5.1)."""
+    """T_f = sqrt(P_a/P_b), r_c = P_ab / sqrt(P_a P_b) (section 6.1)."""
     n = a.shape[0]
     ak = np.fft.rfftn(np.asarray(a, dtype=np.float64))
     bk = np.fft.rfftn(np.asarray(b, dtype=np.float64))

@@ -1,9 +1,9 @@
-"""Multi-grid (pyramid) force of section 4.2 (float64).
+"""Multi-grid (pyramid) force of section 5.2 (float64).
 
 Test infrastructure: see the package docstring.
 
 The paper builds a two-level force from a multiresolution pyramid
-(section 3.3 and Algorithms 2 and 3):
+(section 3.1 and Algorithms 2 and 3):
   * REDUCE: f times, convolve with a 3-D B-spline kernel and subsample by a
     stride of 2 (a strided convolution);
   * EXPAND: f times, a transposed strided convolution with the same kernel

@@ -25,7 +25,7 @@ def make_config(w: Workload, max_particles: int = 0) -> _lib.pm_config:
     c = w.cosmo
     tk = tp = None
     n_tab = 0
-    if c.pk_table:
+    if len(c.pk_table):
         n_tab = len(c.pk_table[0])
         tk = (C.c_double * n_tab)(*c.pk_table[0])
         tp = (C.c_double * n_tab)(*c.pk_table[1])

@@ -38,25 +38,7 @@ size_t fft_table_bytes(long n) {
   return align_up(n * 8) + align_up(n / 2 * 8) + 4 * align_up(n * 4) + 4 * align_up((n / 2 + 1) * 4);
 }
 
-// Paint/sort tiles of 16 x 16 x 32 cells (x, y, z; 32 floats = 128-byte
-// rows along the contiguous axis), at least two tiles per side.
-pmk::TileGeom make_tiles(int n) {
-  pmk::TileGeom g;
-  g.n = n;
-  g.tx = g.ty = n / 2 < 16 ? n / 2 : 16;
-  g.tz = n / 2 < 16 ? n / 2 : 16;
-  g.ntx = n / g.tx;
-  g.nty = n / g.ty;
-  g.ntz = n / g.tz;
-  g.ntiles = g.ntx * g.nty * g.ntz;
-  g.lx = __builtin_ctz(g.tx);
-  g.ly = __builtin_ctz(g.ty);
-  g.lz = __builtin_ctz(g.tz);
-  g.lnx = __builtin_ctz(g.ntx);
-  g.lny = __builtin_ctz(g.nty);
-  g.lnz = __builtin_ctz(g.ntz);
-  return g;
-}
+pmk::TileGeom make_tiles(int n) { return pmk::make_tile_geom(n); }
 
 // Byte layout of the workspace (offsets from its base).
 struct Layout {
@@ -95,7 +77,9 @@ int validate(const pm_config* c, std::string* why) {
   if (c->cosmo.pk_kind == PM_PK_TABLE) {
     if (c->cosmo.pk_n < 2 || !c->cosmo.pk_k || !c->cosmo.pk_p) return bad("table P(k) needs pk_n >= 2 points");
     for (int i = 0; i < c->cosmo.pk_n; ++i) {
-      if (!(c->cosmo.pk_k[i] > 0) || !(c->cosmo.pk_p[i] >= 0)) return bad("table P(k) needs k > 0, P >= 0");
+      if (!(c->cosmo.pk_k[i] > 0) || !(c->cosmo.pk_p[i] >= 0) || !std::isfinite(c->cosmo.pk_k[i]) ||
+          !std::isfinite(c->cosmo.pk_p[i]))
+        return bad("table P(k) needs finite k > 0 and P >= 0");
       if (i && !(c->cosmo.pk_k[i] > c->cosmo.pk_k[i - 1])) return bad("table k must increase");
     }
   }

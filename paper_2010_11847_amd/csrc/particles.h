@@ -22,6 +22,11 @@ struct TileGeom {
   int lnx = 0, lny = 0, lnz = 0;     // log2 of ntx, nty, ntz
 };
 
+// Paint/sort tiles of the n^3 mesh: 16^3 cells, or n/2 per side below 32^3
+// (at least two tiles per side, so that a particle's 7 upper CIC neighbours
+// never wrap into its own tile).
+TileGeom make_tile_geom(int n);
+
 struct LptParticleArgs {
   int np = 0;             // particles per side
   int ratio = 1;          // B = n_mesh / n_part

@@ -699,6 +699,23 @@ inline int grid_for(long n, int per = kThreads, int cap = 65536) {
 
 }  // namespace
 
+TileGeom make_tile_geom(int n) {
+  TileGeom g;
+  g.n = n;
+  g.tx = g.ty = g.tz = n / 2 < 16 ? n / 2 : 16;
+  g.ntx = n / g.tx;
+  g.nty = n / g.ty;
+  g.ntz = n / g.tz;
+  g.ntiles = g.ntx * g.nty * g.ntz;
+  g.lx = __builtin_ctz(g.tx);
+  g.ly = __builtin_ctz(g.ty);
+  g.lz = __builtin_ctz(g.tz);
+  g.lnx = __builtin_ctz(g.ntx);
+  g.lny = __builtin_ctz(g.nty);
+  g.lnz = __builtin_ctz(g.ntz);
+  return g;
+}
+
 void launch_noise(uint64_t seed, int n_side, float* out, bool blocked, hipStream_t s) {
   const long n3 = (long)n_side * n_side * n_side;
   hipLaunchKernelGGL(k_noise, dim3(grid_for(n3)), dim3(kThreads), 0, s, seed, n3, __builtin_ctz(n_side),

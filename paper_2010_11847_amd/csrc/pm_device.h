@@ -26,10 +26,13 @@ static __device__ __forceinline__ void cic_base(float x, int n, int& i, float& t
   i = ((int)f) & (n - 1);
 }
 
+// Periodic wrap into [0, n): x - n floor(x / n) for any finite x (n is a
+// power of two, so x / n is exact); a result that rounds onto n becomes 0.
+// Non-finite positions (invalid input) become 0 so that every later index
+// stays inside the mesh.
 static __device__ __forceinline__ float wrap_pos(float x, float n) {
-  if (x < 0.f) x += n;
-  if (x >= n) x -= n;
-  if (!(x >= 0.f && x < n)) x = 0.f;    // rounding onto n, or non-finite
+  if (x < 0.f || x >= n) x -= n * floorf(x * (1.f / n));
+  if (!(x >= 0.f && x < n)) x = 0.f;
   return x;
 }
 

@@ -1,4 +1,4 @@
-// Multi-grid (pyramid) passes of the two-level force (section 4.2,
+// Multi-grid (pyramid) passes of the two-level force (section 5.2,
 // Algorithms 2 and 3).  REDUCE convolves with the 3-D B-spline of order 6
 // (the tensor product of the 1-D weights C(6, k) / 64, k = 0..6) and keeps
 // every second cell per axis; EXPAND is its transpose times 8, i.e. zeros

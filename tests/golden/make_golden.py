@@ -1,16 +1,47 @@
-"""Write stored expected values of full-size runs from the FP64 oracle only.
+"""Write stored expected values from the FP64 oracle only.
 
-Each golden file is produced by this script (oracle + seeded presets, no
-GPU code) and read by the GPU parity tests:
+Each golden file is produced by this script (oracle + seeded inputs, no GPU
+code) and read by the GPU parity tests.  Inputs that both sides need are
+drawn by the GPU tests again from the same seeded generators
+(paper_2010_11847_amd/inputs.py, no method arithmetic) or from the oracle's
+counter-based white noise.
 
-  pm128_mesh256_box256.json    : 128^3 particles / 256^3 mesh, 10 KDK steps
-  pm512_mesh1024_box1024.json  : 512^3 particles / 1024^3 mesh, 10 KDK steps
+  pm128_mesh256_box256.json    medium   128^3 particles / 256^3 mesh, 10 KDK
+                                        steps from the 2LPT start: P(k) of the
+                                        final density (full mesh and the 128^3
+                                        low-k subcube), 1024 sampled final
+                                        positions and momenta
+  pm512_mesh1024_box1024.json  large    the same at 512^3 / 1024^3 (P(k) over
+                                        the subcube only)
+  force_pm512_mesh1024.json    force1024  512^3 particles on the 1024^3 mesh:
+                                        overdensity at 4096 sampled cells and
+                                        the PM force at 1024 sampled particles,
+                                        for a perturbed lattice (the 2LPT
+                                        start's displacement scale) and a
+                                        clustered set (late-time halos)
+  adjoint_step_mesh512.json    adjoint512 one reverse KDK step on a 512^3 mesh
+                                        (256^3 particles) along a seeded
+                                        two-point trajectory: cotangents of
+                                        the initial positions and momenta at
+                                        1024 sampled particles
+  adjoint_adj128_mesh256.json  adjoint_c4b the whole reverse sweep of a 5-step
+                                        run at 128^3 particles / 256^3 mesh
+                                        along a seeded trajectory, with a
+                                        seeded final-density cotangent:
+                                        white-noise cotangent at 4096 cells,
+                                        position/momentum cotangents at 1024
+                                        particles
+  fd_adj64_mesh128_box200.json fd_c4a   central finite differences
+                                        (Richardson-extrapolated) of the chi^2
+                                        loss of the 64^3 / 128^3 5-step run
+                                        at 32 seeded white-noise cells, and
+                                        the oracle adjoint there
+  serve_classes.json           serve    final positions/momenta (1024 sampled
+                                        particles) of one request of each
+                                        serving class run by the oracle from
+                                        the same seed
 
-Contents: the final-overdensity power spectrum over the modes with every
-|n_d| < 64 (the 128^3 low-k subcube), the full-mesh spectrum of the 256^3
-run, and the final positions and momenta of 1024 fixed sampled particles
-(every 4th of a seeded 4096-particle draw, rounded to 1e-8).
-Usage: python tests/golden/make_golden.py [medium|large]
+Usage: python tests/golden/make_golden.py <name> [<name> ...]
 """
 import json
 import os
@@ -22,11 +53,76 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
+from oracle import adjoint as A  # noqa: E402
 from oracle import lpt, pm, power  # noqa: E402
+from oracle.rng import white_noise  # noqa: E402
 from paper_2010_11847_amd import inputs  # noqa: E402
 
 SAMPLE_SEED = 11
 
+# ---- seeded inputs shared with the GPU tests (tests/test_gpu_fullsize.py) ----
+FORCE_SETS = {
+    # 2LPT-start-like: lattice nodes with ~1-cell Gaussian displacements
+    "lattice": dict(kind="lattice", seed=21, amp=1.0),
+    # late-time-like: half the particles in 32768 Gaussian clumps of 2 cells
+    "clustered": dict(kind="clustered", seed=22, n_clumps=32768, width=2.0, frac=0.5),
+}
+ADJ512 = dict(n_mesh=512, n_part=256, a=(0.1, 0.3), x0_seed=31, x0_amp=0.7, x1_seed=32, x1_amp=1.5,
+              pbar_seed=33)
+ADJ_C4B = dict(traj_seed=40, dbar_seed=47, amp0=0.3, amp_step=0.4)
+SERVE_REQS = [  # (rid, n_part, n_mesh, box, steps, seed, with_grad)
+    (0, 64, 64, 128.0, 5, 1000, False),
+    (1, 128, 128, 256.0, 6, 1001, True),
+    (2, 256, 512, 512.0, 7, 1002, False),
+]
+
+
+def force_positions(name, n_part=512, n_mesh=1024):
+    s = FORCE_SETS[name]
+    if s["kind"] == "lattice":
+        return inputs.perturbed_lattice(n_part, n_mesh, seed=s["seed"], amp=s["amp"])
+    return inputs.clustered_positions(n_part ** 3, n_mesh, seed=s["seed"], n_clumps=s["n_clumps"],
+                                      width=s["width"], frac=s["frac"])
+
+
+def adj512_inputs():
+    c = ADJ512
+    x0 = inputs.perturbed_lattice(c["n_part"], c["n_mesh"], seed=c["x0_seed"], amp=c["x0_amp"])
+    x1 = inputs.perturbed_lattice(c["n_part"], c["n_mesh"], seed=c["x1_seed"], amp=c["x1_amp"])
+    pbar = inputs.normal_array((c["n_part"] ** 3, 3), seed=c["pbar_seed"])
+    return x0, x1, pbar
+
+
+def c4b_workload():
+    return inputs.ADJ_MEDIUM
+
+
+def c4b_inputs(w):
+    """A seeded trajectory (one perturbed lattice per scale factor, growing
+    displacements), the oracle's white noise of the preset's seed and a seeded
+    final-density cotangent."""
+    c = ADJ_C4B
+    xs = [inputs.perturbed_lattice(w.n_part, w.n_mesh, seed=c["traj_seed"] + i, amp=c["amp0"] + c["amp_step"] * i)
+          for i in range(len(w.a_list))]
+    noise = white_noise(w.seed, w.n_part).astype(np.float32)
+    dbar = inputs.normal_array((w.n_mesh,) * 3, seed=c["dbar_seed"])
+    return xs, noise, dbar
+
+
+def chi2_target(w, sigma=0.1):
+    """Target of the chi^2 loss: the oracle's final density of the run from
+    the white noise of seed + 1000, plus Gaussian noise of seed + 2000."""
+    xt, _, _ = pm.kdk_run(*lpt.generate(w, noise=white_noise(w.seed + 1000, w.n_part)), w.a_list, w.n_mesh,
+                          w.n_particles, w.cosmo.omega_m)
+    target = pm.density_contrast(xt, w.n_mesh, w.n_particles)
+    return target + np.random.default_rng(w.seed + 2000).normal(0.0, sigma, target.shape)
+
+
+def rnd(a):
+    return np.round(np.asarray(a, dtype=np.float64), 10).tolist()
+
+
+# ---- writers ------------------------------------------------------------------
 
 def run(w, n_sample, log):
     t0 = time.time()
@@ -51,15 +147,118 @@ def run(w, n_sample, log):
     return out
 
 
+def make_force1024(log):
+    w = inputs.LARGE
+    out = {"workload": w.name, "omega_m": w.cosmo.omega_m, "sets": {}}
+    cells = inputs.sample_indices(w.n_mesh ** 3, 4096, SAMPLE_SEED + 1)
+    parts = inputs.sample_indices(w.n_particles, 1024, SAMPLE_SEED + 2)
+    for name in FORCE_SETS:
+        t0 = time.time()
+        x = force_positions(name).astype(np.float64)
+        delta = pm.density_contrast(x, w.n_mesh, w.n_particles)
+        d_s = delta.reshape(-1)[cells]
+        del delta
+        log(f"{name}: paint {time.time() - t0:.0f}s")
+        f = pm.force(x, w.n_mesh, w.n_particles, w.cosmo.omega_m)
+        log(f"{name}: force {time.time() - t0:.0f}s")
+        out["sets"][name] = {"spec": FORCE_SETS[name], "cells": cells.tolist(), "delta": rnd(d_s),
+                             "particles": parts.tolist(), "force": rnd(f[parts])}
+        del x, f
+    return out
+
+
+def make_adjoint512(log):
+    c = ADJ512
+    t0 = time.time()
+    x0, x1, pbar = adj512_inputs()
+    npart = c["n_part"] ** 3
+    xb, pb = A.run_vjp([x0.astype(np.float64), x1.astype(np.float64)], c["a"], c["n_mesh"], npart, 0.3,
+                       np.zeros((npart, 3)), pbar.astype(np.float64))
+    log(f"reverse step {time.time() - t0:.0f}s")
+    parts = inputs.sample_indices(npart, 1024, SAMPLE_SEED + 3)
+    return {"spec": c, "omega_m": 0.3, "particles": parts.tolist(), "x0_bar": rnd(xb[parts]),
+            "p0_bar": rnd(pb[parts])}
+
+
+def make_adjoint_c4b(log):
+    w = c4b_workload()
+    t0 = time.time()
+    xs, noise, dbar = c4b_inputs(w)
+    xs = [x.astype(np.float64) for x in xs]
+    n, npart, om = w.n_mesh, w.n_particles, w.cosmo.omega_m
+    xb = A.paint_vjp(xs[-1], n, dbar.astype(np.float64) * (n ** 3 / npart))
+    x0b, p0b = A.run_vjp(xs, w.a_list, n, npart, om, xb, np.zeros_like(xb))
+    log(f"reverse sweep {time.time() - t0:.0f}s")
+    g = A.lpt_vjp(noise.astype(np.float64), w, x0b, p0b)
+    cells = inputs.sample_indices(w.n_part ** 3, 4096, SAMPLE_SEED + 4)
+    parts = inputs.sample_indices(npart, 1024, SAMPLE_SEED + 5)
+    return {"workload": w.name, "spec": ADJ_C4B, "cells": cells.tolist(), "grad_noise": rnd(g.reshape(-1)[cells]),
+            "grad_noise_rms": float(np.sqrt(np.mean(g ** 2))), "particles": parts.tolist(),
+            "x0_bar": rnd(x0b[parts]), "p0_bar": rnd(p0b[parts])}
+
+
+def make_fd_c4a(log, sigma=0.1, h=1e-4):
+    w = inputs.ADJ_SMALL
+    t0 = time.time()
+    noise = white_noise(w.seed, w.n_part)
+    target = chi2_target(w, sigma)
+    loss, g = A.loss_and_grad(noise, w, target, sigma)
+    log(f"oracle adjoint {time.time() - t0:.0f}s")
+    cells = inputs.sample_indices(noise.size, 32, seed=3)
+    flat = noise.reshape(-1)
+    fd = []
+    for i, c in enumerate(cells):
+        def f(e):
+            z = flat.copy()
+            z[c] += e
+            return A.forward_loss(z.reshape(noise.shape), w, target, sigma)[0]
+        d1 = (f(h) - f(-h)) / (2 * h)
+        d2 = (f(h / 2) - f(-h / 2)) / h
+        fd.append((4 * d2 - d1) / 3)
+        log(f"cell {i + 1}/32 {time.time() - t0:.0f}s")
+    fd = np.array(fd)
+    ga = g.reshape(-1)[cells]
+    return {"workload": w.name, "sigma": sigma, "h": h, "cells": cells.tolist(), "fd": fd.tolist(),
+            "oracle_adjoint": ga.tolist(), "grad_rms": float(np.sqrt(np.mean(g ** 2))), "loss": loss,
+            "oracle_adjoint_vs_fd_max_rel_to_rms": float(np.abs(ga - fd).max() / np.sqrt(np.mean(g ** 2)))}
+
+
+def make_serve(log):
+    from paper_2010_11847_amd.inputs import Workload, a_linear, Cosmology
+    out = {"requests": []}
+    for rid, npart, nmesh, box, steps, seed, grad in SERVE_REQS:
+        t0 = time.time()
+        w = Workload(f"req{rid}", box, nmesh, npart, seed, a_linear(0.1, 1.0, steps), Cosmology())
+        x, p = lpt.generate(w)
+        x, p, _ = pm.kdk_run(x, p, w.a_list, nmesh, w.n_particles, w.cosmo.omega_m)
+        parts = inputs.sample_indices(w.n_particles, 1024, SAMPLE_SEED + 6)
+        out["requests"].append({"rid": rid, "n_part": npart, "n_mesh": nmesh, "box": box, "steps": steps,
+                                "seed": seed, "with_grad": grad, "particles": parts.tolist(),
+                                "x": rnd(x[parts]), "p": rnd(p[parts])})
+        log(f"request {rid} ({npart}^3 / {nmesh}^3, {steps} steps) {time.time() - t0:.0f}s")
+    return out
+
+
+MAKERS = {
+    "medium": (inputs.MEDIUM.name, lambda log: run(inputs.MEDIUM, 4096, log)),
+    "large": (inputs.LARGE.name, lambda log: run(inputs.LARGE, 4096, log)),
+    "force1024": ("force_pm512_mesh1024", make_force1024),
+    "adjoint512": ("adjoint_step_mesh512", make_adjoint512),
+    "adjoint_c4b": ("adjoint_adj128_mesh256", make_adjoint_c4b),
+    "fd_c4a": ("fd_adj64_mesh128_box200", make_fd_c4a),
+    "serve": ("serve_classes", make_serve),
+}
+
+
 def main():
-    which = sys.argv[1] if len(sys.argv) > 1 else "medium"
-    w = {"medium": inputs.MEDIUM, "large": inputs.LARGE}[which]
-    log = lambda m: print(f"[golden {w.name}] {m}", flush=True)  # noqa: E731
-    out = run(w, 4096, log)
-    out["source"] = ("FP64 oracle (oracle/), same workload preset; "
-                     "written by tests/golden/make_golden.py")
-    with open(os.path.join(HERE, f"{w.name}.json"), "w") as fh:
-        json.dump(out, fh)
+    names = sys.argv[1:] or ["medium"]
+    for which in names:
+        fname, maker = MAKERS[which]
+        log = lambda m, f=fname: print(f"[golden {f}] {m}", flush=True)  # noqa: E731
+        out = maker(log)
+        out["source"] = "FP64 oracle (oracle/); written by tests/golden/make_golden.py " + which
+        with open(os.path.join(HERE, f"{fname}.json"), "w") as fh:
+            json.dump(out, fh)
 
 
 if __name__ == "__main__":

@@ -1,11 +1,21 @@
 """Shared helpers of the GPU parity tests."""
+import json
+import os
+
 import numpy as np
 import torch
 
+_METRICS = {}
+
 
 def rel(a, b):
-    a = np.asarray(a, dtype=np.float64)
-    b = np.asarray(b, dtype=np.float64)
+    """Norm-wise relative error ||a - b|| / ||b||; complex arrays keep their
+    imaginary parts."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    dt = np.complex128 if (np.iscomplexobj(a) or np.iscomplexobj(b)) else np.float64
+    a = a.astype(dt)
+    b = b.astype(dt)
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
@@ -18,5 +28,27 @@ def to_np(t):
     return t.detach().cpu().numpy()
 
 
+def f32(x):
+    """Round to float32 and back: the state both sides are fed."""
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
 def banner(msg):
     print(f"[gpu] {msg}", flush=True)
+
+
+def record(name, value):
+    """Keep a measured error; written to $PM_METRICS_DIR/parity_margins.json
+    when that variable is set (the committed margins come from such a run)."""
+    _METRICS[name] = float(value)
+    out = os.environ.get("PM_METRICS_DIR")
+    if out:
+        os.makedirs(out, exist_ok=True)
+        path = os.path.join(out, "parity_margins.json")
+        old = {}
+        if os.path.exists(path):
+            with open(path) as fh:
+                old = json.load(fh)
+        old.update(_METRICS)
+        with open(path, "w") as fh:
+            json.dump(old, fh, indent=1, sort_keys=True)

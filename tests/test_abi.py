@@ -61,6 +61,26 @@ def test_workspace_sizes_and_validation(lib):
     assert lib.pm_workspace_bytes(C.byref(cfg)) == 0
 
 
+def test_tabulated_power_spectrum_validation(lib):
+    """A caller's P(k) table must hold finite k > 0 (increasing) and finite
+    P >= 0; anything else is an invalid configuration (workspace size 0)."""
+    from paper_2010_11847_amd.binding import make_config
+    import numpy as np
+    ks = tuple(np.logspace(-3, 1, 8))
+    ps = tuple(np.linspace(1.0, 8.0, 8))
+
+    def cfg(k, p):
+        cos = replace(inputs.SMALL.cosmo, pk_kind=inputs.PK_TABLE, pk_table=(k, p))
+        return make_config(replace(inputs.SMALL, cosmo=cos))
+    assert lib.pm_workspace_bytes(C.byref(cfg(ks, ps))) > 0
+    # a numpy table is accepted too
+    assert lib.pm_workspace_bytes(C.byref(cfg(np.array(ks), np.array(ps)))) > 0
+    inf, nan = float("inf"), float("nan")
+    for k, p in [(ks[:-1] + (inf,), ps), (ks, ps[:-1] + (inf,)), (ks, (nan,) + ps[1:]),
+                 ((nan,) + ks[1:], ps), (ks, (-1.0,) + ps[1:]), (ks[::-1], ps), (ks[:1], ps[:1])]:
+        assert lib.pm_workspace_bytes(C.byref(cfg(k, p))) == 0, (k, p)
+
+
 def test_strerror(lib):
     assert lib.pm_strerror(0) == b"ok"
     assert lib.pm_strerror(-2) == b"workspace too small"

@@ -6,10 +6,10 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import pm
+from oracle import lpt, pm
 from paper_2010_11847_amd import inputs
 from paper_2010_11847_amd.binding import PMContext, PMError
-from tests.gpu_helpers import banner, rel, to_dev, to_np
+from tests.gpu_helpers import banner, f32, rel, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 OM = 0.3
@@ -62,8 +62,8 @@ def test_smallest_mesh_run(gpu):
     banner("8^3 mesh run")
     w = inputs.scaled(inputs.SMALL, 8, 8, n_steps=3)
     c = PMContext(w)
-    pos, mom = c.pm_init_lpt(w.seed, w.a_list[0])
-    x0, p0 = to_np(pos).astype(np.float64), to_np(mom).astype(np.float64)
+    x0, p0 = (f32(v) for v in lpt.generate(w))   # the oracle's start, fed to both sides
+    pos, mom = to_dev(x0), to_dev(p0)
     c.pm_run(w.a_list, pos, mom)
     xo, _, _ = pm.kdk_run(x0, p0, w.a_list, 8, 512, w.cosmo.omega_m)
     d = pm.min_image(to_np(pos).astype(np.float64) - xo, 8)

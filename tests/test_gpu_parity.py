@@ -14,7 +14,7 @@ from oracle import cosmology, lpt, pm, power
 from oracle.rng import white_noise
 from paper_2010_11847_amd import inputs
 from paper_2010_11847_amd.binding import PMError
-from tests.gpu_helpers import banner, rel, to_dev, to_np
+from tests.gpu_helpers import banner, f32, record, rel, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -37,6 +37,7 @@ def test_rfft_irfft_match_numpy(gpu, n):
     x = inputs.normal_array((n, n, n), seed=n)
     spec = to_np(c.pm_rfft(to_dev(x)))
     ref = np.fft.rfftn(x.astype(np.float64))
+    record(f"rfft_{n}_rel", rel(spec, ref))
     assert rel(spec, ref) < 2e-6
     back = to_np(c.pm_irfft(to_dev(ref.astype(np.complex64), torch.complex64)))
     assert rel(back, x) < 2e-6
@@ -62,6 +63,7 @@ def test_paint_matches_oracle(gpu, n_mesh, n_p, kind):
     x = (inputs.uniform_positions if kind == "uniform" else inputs.clustered_positions)(n_p, n_mesh, seed=n_mesh)
     g = to_np(c.pm_paint(to_dev(x)))
     o = pm.density_contrast(x.astype(np.float64), n_mesh, n_p)
+    record(f"paint_{n_mesh}_{n_p}_{kind}_rel", rel(g, o))
     assert rel(g, o) < 1e-5
     # mass conservation: sum(delta) = 0 <=> sum(rho) = np
     assert abs(g.astype(np.float64).sum()) < 1e-5 * n_mesh ** 3
@@ -94,6 +96,7 @@ def test_force_matches_oracle(gpu, n_mesh, n_p, opts):
     g = to_np(c.pm_force(to_dev(x)))
     o = pm.force(x.astype(np.float64), n_mesh, n_p, OM, deconv_order=w.deconv_order,
                  split_rs=w.split_rs, split_mode=w.split_mode)
+    record(f"force_{n_mesh}_{n_p}_" + "_".join(f"{k}{v}" for k, v in opts.items()) + "_rel", rel(g, o))
     assert rel(g, o) < 1e-5
     # momentum conservation of the force
     assert np.abs(g.astype(np.float64).sum(0)).max() < 1e-5 * np.abs(o).sum(0).max()
@@ -108,6 +111,7 @@ def test_init_lpt_matches_oracle(gpu, n_mesh, n_part, order):
     gx, gp = to_np(pos), to_np(mom)
     ox, op = lpt.generate(w)
     dx = pm.min_image(gx - ox, n_mesh)
+    record(f"lpt_{n_part}_{n_mesh}_order{order}_mom_rel", rel(gp, op))
     assert np.abs(dx).max() < 1e-4 * max(1.0, n_mesh / 64)
     assert rel(gp, op) < 1e-5
 
@@ -133,13 +137,22 @@ def test_init_lpt_with_tabulated_pk_matches_oracle(gpu):
     assert rel(gp, ap) < 5e-3
 
 
+def oracle_start(w):
+    """The 2LPT start of the oracle, rounded to float32: the state both sides
+    are fed (so that no oracle input comes from the GPU)."""
+    x0, p0 = lpt.generate(w)
+    return f32(x0), f32(p0)
+
+
 def test_kdk_step_matches_oracle(gpu):
     banner("kdk step")
     w = wl(64, 32)
     c = ctx_for(w)
-    pos, mom = c.pm_init_lpt(w.seed, 0.1)
+    x0, p0 = oracle_start(w)
+    pos, mom = to_dev(x0), to_dev(p0)
     force = c.pm_force(pos)
-    x0, p0, f0 = (to_np(t).astype(np.float64) for t in (pos, mom, force))
+    f0 = pm.force(x0, 64, 32 ** 3, OM)
+    assert rel(to_np(force), f0) < 1e-5
     c.pm_kdk_step(pos, mom, force, 0.1, 0.3)
     from oracle import cosmology as Cm
     ac = np.sqrt(0.1 * 0.3)
@@ -147,9 +160,14 @@ def test_kdk_step_matches_oracle(gpu):
     x = pm.wrap(x0 + p * Cm.drift_factor(0.1, 0.3, ac, OM), 64)
     f = pm.force(x, 64, 32 ** 3, OM)
     p = p + f * Cm.kick_factor(ac, 0.3, 0.3, OM)
-    assert np.abs(pm.min_image(to_np(pos) - x, 64)).max() < 1e-4
-    assert rel(to_np(force), f) < 1e-5
-    assert rel(to_np(mom), p) < 1e-5
+    dx = np.abs(pm.min_image(to_np(pos) - x, 64)).max()
+    r_f, r_p = rel(to_np(force), f), rel(to_np(mom), p)
+    record("kdk_step_pos_max_abs_cells", dx)
+    record("kdk_step_force_rel", r_f)
+    record("kdk_step_mom_rel", r_p)
+    assert dx < 1e-4
+    assert r_f < 1e-5
+    assert r_p < 1e-5
 
 
 @pytest.mark.parametrize("n_mesh,n_part", [(32, 32), (64, 32)])
@@ -158,14 +176,15 @@ def test_run_matches_oracle(gpu, n_mesh, n_part):
     base = inputs.SMALL if n_mesh == n_part else wl(n_mesh, n_part)
     w = replace(base, n_mesh=n_mesh, n_part=n_part)
     c = ctx_for(w)
-    pos, mom = c.pm_init_lpt(w.seed, w.a_list[0])
-    x0, p0 = to_np(pos).astype(np.float64), to_np(mom).astype(np.float64)
+    x0, p0 = oracle_start(w)
+    pos, mom = to_dev(x0), to_dev(p0)
     delta = torch.empty((n_mesh,) * 3, device="cuda")
     c.pm_run(w.a_list, pos, mom, delta_final=delta)
     ox, op, _ = pm.kdk_run(x0, p0, w.a_list, n_mesh, w.n_particles, OM)
     d = pm.min_image(to_np(pos) - ox, n_mesh)
     rms = float(np.sqrt((d ** 2).sum(1).mean()))
     banner(f"  rms position error {rms:.3e} cells")
+    record(f"run_{n_part}_{n_mesh}_pos_rms_cells", rms)
     assert rms < 1e-3
     assert rel(to_np(mom), op) < 1e-3
     od = pm.density_contrast(ox, n_mesh, w.n_particles)

@@ -1,4 +1,4 @@
-"""Multi-grid (pyramid) force of section 4.2 on the GPU: the force against the
+"""Multi-grid (pyramid) force of section 5.2 on the GPU: the force against the
 oracle's Algorithm 3, a short KDK run against the oracle's run with the same
 force, its adjoint against the oracle's transpose along the same trajectory,
 the paper's sub-percent agreement with the single-grid force at a large
@@ -12,7 +12,7 @@ import torch
 from oracle import lpt, pm, pyramid as P
 from paper_2010_11847_amd import inputs
 from paper_2010_11847_amd.binding import PMContext, PMError
-from tests.gpu_helpers import banner, rel, to_dev, to_np
+from tests.gpu_helpers import banner, f32, record, rel, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 OM = 0.3
@@ -29,6 +29,7 @@ def test_pyramid_force_matches_oracle(gpu, n_mesh, levels, n_p):
     x = inputs.clustered_positions(n_p, n_mesh, seed=21 + n_mesh + levels)
     g = to_np(c.pm_force(to_dev(x)))
     o = P.force(x.astype(np.float64), n_mesh, n_p, OM, levels=levels)
+    record(f"pyramid_force_{n_mesh}_f{levels}_rel", rel(g, o))
     assert rel(g, o) < 1e-5
 
 
@@ -36,8 +37,8 @@ def test_pyramid_run_matches_oracle(gpu):
     banner("pyramid run 64/32 5 steps")
     w = replace(inputs.scaled(inputs.MEDIUM, 64, 32, n_steps=5), pyramid_levels=2)
     c = PMContext(w)
-    pos, mom = c.pm_init_lpt(w.seed, w.a_list[0])
-    x0, p0 = to_np(pos).astype(np.float64), to_np(mom).astype(np.float64)
+    x0, p0 = (f32(v) for v in lpt.generate(w))   # the oracle's start, fed to both sides
+    pos, mom = to_dev(x0), to_dev(p0)
     c.pm_run(w.a_list, pos, mom)
     fn = lambda xx: P.force(xx, 64, 32 ** 3, OM, levels=2)
     xo, po, _ = pm.kdk_run(x0, p0, w.a_list, 64, 32 ** 3, OM, force_fn=fn)
@@ -70,14 +71,17 @@ def test_pyramid_rejections(gpu):
 def test_pyramid_adjoint_matches_oracle_on_same_trajectory(gpu, n_mesh, n_part, levels):
     from oracle import adjoint as A
     from oracle.rng import white_noise
-    from tests.test_gpu_adjoint import SIGMA, gpu_run_and_grad
+    from tests.test_gpu_adjoint import SIGMA, gpu_grad_along, oracle_trajectory
     banner(f"pyramid adjoint n={n_mesh} np={n_part} levels={levels}")
     w = replace(inputs.scaled(inputs.ADJ_SMALL, n_mesh, n_part, n_steps=3), pyramid_levels=levels)
     noise = white_noise(w.seed, n_part)
     xt = lpt.generate(w, noise=white_noise(w.seed + 1000, n_part))[0]
     target = pm.density_contrast(xt, n_mesh, n_part ** 3)
     target = target + np.random.default_rng(w.seed + 2000).normal(0.0, SIGMA, target.shape)
-    ck, g_g = gpu_run_and_grad(w, noise, target)
-    xs = [ck[i, 0] for i in range(len(w.a_list))]
+    fn = lambda xx: P.force(xx, n_mesh, n_part ** 3, OM, levels=levels)
+    xs = oracle_trajectory(w, noise, force_fn=fn)
+    g_g = gpu_grad_along(w, xs, noise, target)
     g_o = A.grad_along_trajectory(xs, noise, w, target, SIGMA, pyramid_levels=levels)
-    assert rel(g_g, g_o) < 1e-4
+    r = rel(g_g, g_o)
+    record(f"pyramid_adjoint_same_traj_{n_mesh}_{n_part}_f{levels}", r)
+    assert r < 1e-4

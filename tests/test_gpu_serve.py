@@ -1,12 +1,17 @@
 """Continuous batching on the GPU: every request's result in the mix equals
 its result when served alone (within the run tolerance), for forward and
 forward + gradient requests of different shapes."""
+import json
+import os
+
 import numpy as np
 import pytest
+import torch
 
 from oracle import pm as opm
 from paper_2010_11847_amd import serve
-from tests.gpu_helpers import banner, rel, to_np
+from tests.golden import make_golden as G
+from tests.gpu_helpers import banner, record, rel, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -43,6 +48,44 @@ def test_results_same_alone_and_in_mix(gpu):
         if req.with_grad:
             assert rel(to_np(m["grad_noise"]), to_np(a["grad_noise"])) < 1e-4
             assert float(m["loss"]) == pytest.approx(float(a["loss"]), rel=1e-5)
+
+
+def test_served_requests_match_the_oracle(gpu):
+    """One request of each serving class (64^3 forward, 128^3 forward +
+    gradient, 256^3 particles on a 512^3 mesh), served together with small
+    requests, against the FP64 oracle's run from the same seed (stored by
+    tests/golden/make_golden.py serve): final positions rms < 1e-3 cell and
+    momenta within 1e-2 at 1024 sampled particles (independent trajectories
+    from the seed on both sides)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "serve_classes.json")
+    if not os.path.exists(path):
+        pytest.skip("golden file serve_classes.json not generated")
+    with open(path) as fh:
+        g = json.load(fh)
+    banner("served requests vs the oracle")
+    trace = [serve.SimRequest(rid, npart, nmesh, box, steps, seed, grad, 0.0)
+             for rid, npart, nmesh, box, steps, seed, grad in G.SERVE_REQS]
+    trace += small_trace()[:4]
+    for i, r in enumerate(trace[3:]):
+        r.rid = 100 + i
+    results = {}
+    rep = serve.serve(trace, serve.GpuExecutor(), budget_bytes=64 << 30, slots_per_class=4, realtime=False,
+                      results=results)
+    assert rep.summary()["completed"] == len(trace)
+    for r in g["requests"]:
+        m = results[r["rid"]]
+        idx = torch.tensor(r["particles"], device="cuda", dtype=torch.long)
+        x = to_np(m["pos"][idx]).astype(np.float64)
+        p = to_np(m["mom"][idx]).astype(np.float64)
+        d = opm.min_image(x - np.array(r["x"]), r["n_mesh"])
+        rms = float(np.sqrt((d ** 2).sum(1).mean()))
+        rp = rel(p, np.array(r["p"]))
+        banner(f"  request {r['rid']} ({r['n_part']}^3 / {r['n_mesh']}^3): positions rms {rms:.2e} cells, "
+               f"momenta rel {rp:.2e}")
+        record(f"serve_class_{r['n_part']}_{r['n_mesh']}_pos_rms_cells", rms)
+        record(f"serve_class_{r['n_part']}_{r['n_mesh']}_mom_rel", rp)
+        assert rms < 1e-3
+        assert rp < 1e-2
 
 
 def test_tiny_budget_and_oversize_rejection(gpu):

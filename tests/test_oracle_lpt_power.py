@@ -131,3 +131,50 @@ def test_transfer_and_correlation_identities():
     _, tf, rc = power.transfer_and_correlation(2 * d, -d, 100.0)
     np.testing.assert_allclose(tf, 2, rtol=1e-12)
     np.testing.assert_allclose(rc, -1, rtol=1e-12)
+
+
+def test_power_subcube_and_weights_by_explicit_full_spectrum_loop():
+    """Brute force: every mode of the full complex spectrum (numpy's fftn, no
+    half-spectrum weights) counted once, selected by |n_d| < n_max and binned
+    by round(|n|), reproduces power()'s mode counts and band powers."""
+    n, box = 12, 30.0
+    d = np.random.default_rng(8).normal(size=(n, n, n))
+    full = np.fft.fftn(d)
+    freqs = [int(v) for v in np.fft.fftfreq(n, 1.0 / n)]
+    for n_max in (0, 3, 4, 6):
+        cnt = np.zeros(n // 2)
+        acc = np.zeros(n // 2)
+        for ix, fx in enumerate(freqs):
+            for iy, fy in enumerate(freqs):
+                for iz, fz in enumerate(freqs):
+                    if n_max and not (abs(fx) < n_max and abs(fy) < n_max and abs(fz) < n_max):
+                        continue
+                    j = int(math.floor(math.sqrt(fx * fx + fy * fy + fz * fz) + 0.5))
+                    if 1 <= j <= n // 2:
+                        cnt[j - 1] += 1
+                        acc[j - 1] += abs(full[ix, iy, iz]) ** 2
+        k, pk, nm = power.power(d, box, n_max=n_max)
+        np.testing.assert_array_equal(nm, cnt)
+        sel = cnt > 0
+        np.testing.assert_allclose(pk[sel], acc[sel] / cnt[sel] * box ** 3 / n ** 6, rtol=1e-12)
+        assert np.all(np.isnan(pk[~sel]))
+
+
+@pytest.mark.parametrize("m", [(3, 0, 0), (1, 2, 3), (5, 0, 6)])
+def test_power_deconvolution_divides_a_plane_wave_by_the_window_squared(m):
+    """A single plane wave: the CIC-deconvolved band power is the plain one
+    divided by W^2, W = prod_d (sin(w_d/2)/(w_d/2))^2 at the wave's mode."""
+    n, box = 16, 40.0
+    g = np.arange(n)
+    ph = 2 * np.pi * (m[0] * g[:, None, None] + m[1] * g[None, :, None] + m[2] * g[None, None, :]) / n
+    d = 0.3 * np.cos(ph)
+    _, p0, nm0 = power.power(d, box)
+    _, p1, nm1 = power.power(d, box, deconvolve_cic=True)
+    np.testing.assert_array_equal(nm0, nm1)
+    j = int(math.floor(math.sqrt(sum(v * v for v in m)) + 0.5))
+    win = 1.0
+    for v in m:
+        h = math.pi * v / n
+        win *= (math.sin(h) / h) ** 2 if v else 1.0
+    assert p1[j - 1] == pytest.approx(p0[j - 1] / win ** 2, rel=1e-12)
+    assert p0[j - 1] > 0
