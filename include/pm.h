@@ -286,6 +286,27 @@ int pm_profile(pm_ctx* ctx, int enable);
  * (launches).  Returns the number of classes seen, or a negative status. */
 int pm_profile_read(pm_ctx* ctx, int max, char* h_names, double* h_total_ms, int* h_count);
 
+/* ---- allocation-free force ----------------------------------------------
+ * For callers that cannot allocate device memory or create a workspace
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * allocation).  The same computation as pm_force on a context created from
+ * cfg, with the workspace taken from a fixed device array of
+ * PM_STATIC_SCRATCH_BYTES bytes inside the library: every GPU the library
+ * runs on holds one such array until the process ends.  The call allocates
+ * no device memory; it builds a host-side context, uploads the static tables
+ * into the array on `stream` (a hipStream_t as void*, NULL = default stream)
+ * and waits for that upload, then enqueues the force asynchronously on
+ * `stream`.  d_pos: [np][3] positions in [0, n_mesh); d_force: [np][3]
+ * output; np in [1, max_particles].  All calls on one GPU share its array
+ * and it keeps the last call's contents: calls that overlap on one GPU (two
+ * host threads, or two streams with work still in flight) race and give
+ * undefined results.  Returns PM_EINVAL for NULL pointers or an invalid cfg,
+ * PM_ENOMEM if pm_workspace_bytes(cfg) exceeds PM_STATIC_SCRATCH_BYTES
+ * (with a message on stderr; meshes up to 64^3 with up to 64^3 particles
+ * fit), PM_EHIP for a runtime error. */
+#define PM_STATIC_SCRATCH_BYTES (64u * 1024u * 1024u)
+int pm_force_static(const pm_config* cfg, const float* d_pos, int64_t np, float* d_force, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -324,3 +324,26 @@ class PMContext:
         refs = getattr(self, "_run_refs", None)
         self._run_refs = None
         return refs
+
+
+def pm_force_static(workload: Workload, pos: torch.Tensor, out: Optional[torch.Tensor] = None,
+                    max_particles: int = 0, stream=None) -> torch.Tensor:
+    """PM force through the library's allocation-free entry point (its
+    scratch is a fixed device array inside the library, so no workspace is
+    created).  pos: (np, 3) float32 on the current GPU; out: the same shape,
+    allocated here when not given (pass it to keep the call allocation-free)."""
+    lib = _lib.load()
+    if not isinstance(pos, torch.Tensor) or pos.device.type != "cuda" or pos.dtype != torch.float32:
+        raise PMError("pos must be a float32 tensor on a GPU")
+    if pos.ndim != 2 or pos.shape[1] != 3 or not pos.is_contiguous():
+        raise PMError("pos must be a contiguous (np, 3) tensor")
+    out = torch.empty_like(pos) if out is None else out
+    if out.shape != pos.shape or out.dtype != torch.float32 or out.device != pos.device or not out.is_contiguous():
+        raise PMError("out must be a contiguous float32 tensor shaped like pos on its device")
+    cfg = make_config(workload, max_particles)
+    s = stream if stream is not None else torch.cuda.current_stream(pos.device)
+    with torch.cuda.device(pos.device):
+        rc = lib.pm_force_static(C.byref(cfg), _ptr(pos), pos.shape[0], _ptr(out), C.c_void_p(s.cuda_stream))
+    if rc != _lib.PM_OK:
+        raise PMError(f"pm_force_static failed ({rc}): {lib.pm_strerror(rc).decode()}")
+    return out

@@ -18,7 +18,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpm.so")
 ARCH = os.environ.get("PM_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["fft.hip", "particles.hip", "adjoint.hip", "recon.hip", "pyramid.hip", "api.cpp", "cosmo.cpp"]
+SOURCES = ["fft.hip", "particles.hip", "adjoint.hip", "recon.hip", "pyramid.hip", "api.cpp", "cosmo.cpp",
+           "static_scratch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{INCLUDE}", f"-I{CSRC}"]
