@@ -97,24 +97,49 @@ def measured_traffic(workload, kernel_class):
     return rows[kernel_class]
 
 
-def cpu_baseline(seconds_hint=20.0):
-    """The oracle (FP64 NumPy, unmodified) on a bounded sample: the same
-    recipe (B = 2, 1 Mpc/h cells, no-wiggle P(k), 2LPT at a = 0.1) at
-    128^3 particles on a 256^3 mesh, 8 KDK steps (10-20 s on 16 host
-    threads); reported in particle-steps/s."""
+def cpu_baseline():
+    """The oracle (FP64 NumPy/SciPy, unmodified) timed on this host at the
+    small configurations, about 30 s of CPU work in all:
+      - 32^3 particles on 32^3 (100 Mpc/h, power law), 10 KDK steps;
+      - 128^3 particles on 256^3 (256 Mpc/h, no-wiggle), 10 KDK steps: the
+        headline figure, in particle-steps/s (same B = 2 and 1 Mpc/h cells as
+        the 512^3 / 1024^3 workload);
+      - 64^3 particles on 128^3 (200 Mpc/h), 5 steps: forward run plus the
+        adjoint (gradient of the chi^2 loss w.r.t. the white noise).
+    Each run starts from the oracle's own 2LPT initial conditions (not
+    timed)."""
     import numpy as np
+    from oracle import adjoint as A
     from oracle import lpt, pm
+    from oracle.rng import white_noise
     from paper_2010_11847_amd import inputs
-    w = inputs.scaled(inputs.LARGE, 256, 128, n_steps=8)
-    x, p = lpt.generate(w)
+    out = {}
+
+    def run(w):
+        x, p = lpt.generate(w)
+        t0 = time.perf_counter()
+        pm.kdk_run(x, p, w.a_list, w.n_mesh, w.n_particles, w.cosmo.omega_m)
+        dt = time.perf_counter() - t0
+        return {"particle_steps_per_s": w.n_particles * w.n_steps / dt, "s": round(dt, 2)}
+    out["pm32_box100_powerlaw"] = run(inputs.SMALL)
+    out["pm128_mesh256_box256"] = run(inputs.MEDIUM)
+    w = inputs.ADJ_SMALL
+    noise = white_noise(w.seed, w.n_part)
+    target = np.zeros((w.n_mesh,) * 3)
     t0 = time.perf_counter()
-    pm.kdk_run(x, p, w.a_list, w.n_mesh, w.n_particles, w.cosmo.omega_m)
+    A.loss_and_grad(noise, w, target, 0.1)
     dt = time.perf_counter() - t0
-    return {"value": w.n_particles * w.n_steps / dt, "unit": "particle-steps/s", "cores": pm._WORKERS,
+    out["adj64_mesh128_box200"] = {"gradients_per_s": 1.0 / dt, "s": round(dt, 2),
+                                   "what": "2LPT + 5-step forward run + adjoint to the white noise"}
+    med = out["pm128_mesh256_box256"]
+    cores = len(os.sched_getaffinity(0))
+    return {"value": med["particle_steps_per_s"], "unit": "particle-steps/s", "cores": pm._WORKERS,
             "kind": "oracle",
-            "sample": f"{w.n_part}^3 particles on {w.n_mesh}^3 mesh, box {w.box_size:g} Mpc/h "
-                      f"(same B=2, 1 Mpc/h cell, no-wiggle P(k)), {w.n_steps} KDK steps incl. first force, "
-                      f"{dt:.1f} s wall; DFTs on {pm._WORKERS} threads (scipy.fft), paint/readout 1 thread"}
+            "sample": f"128^3 particles on 256^3 mesh, 256 Mpc/h, 10 KDK steps incl. first force, {med['s']} s wall "
+                      f"(same B=2, 1 Mpc/h cell, no-wiggle P(k) as the headline workload); DFTs on {pm._WORKERS} "
+                      f"threads (scipy.fft), paint/readout 1 thread; host cpu_count {os.cpu_count()}, "
+                      f"affinity {cores}",
+            "configs": out}
 
 
 def adjoint_section(names=("adj128_mesh256_box400", "pm512_mesh1024_box1024"), reps=2):
@@ -240,36 +265,46 @@ def recon_section(n_iter=10):
 
 
 def serving_section(n_requests, rate=20.0, seed=5, budget_gb=64.0, slots=4):
-    """Continuous batching vs one-at-a-time on the same Poisson trace."""
+    """Continuous batching (batch plans, batched steps) vs one request at a
+    time on the same Poisson trace, then the same requests arriving at once
+    (throughput), and the forward+gradient requests alone."""
     from paper_2010_11847_amd import serve
     trace = serve.poisson_trace(n_requests, rate, seed)
     warm = serve.poisson_trace(24, 1000.0, seed + 1)
-    ex = serve.GpuExecutor(keep_results=False)
     budget = int(budget_gb * (1 << 30))
-    serve.serve(warm, ex, budget, slots, realtime=False)          # builds the slot contexts
+    ex = serve.BatchedExecutor(slots_per_class=slots, keep_results=False)
+    fifo_ex = serve.GpuExecutor(keep_results=False)
+    serve.serve(warm, ex, budget, slots, realtime=False)          # builds the plans and their graphs
+    serve.serve_fifo(warm, fifo_ex, realtime=False)               # builds the per-class contexts
+    print(f"[bench] serving: Poisson trace of {n_requests} requests at {rate}/s, continuous batching",
+          file=sys.stderr, flush=True)
     cb = serve.serve(trace, ex, budget, slots, realtime=True).summary()
     print(f"[bench] serving continuous {cb}", file=sys.stderr, flush=True)
-    fifo = serve.serve_fifo(trace, ex, realtime=True).summary()
+    fifo = serve.serve_fifo(trace, fifo_ex, realtime=True).summary()
     print(f"[bench] serving fifo {fifo}", file=sys.stderr, flush=True)
     # saturated: the same requests all arriving at once (maximum throughput)
     burst = [serve.SimRequest(r.rid, r.n_part, r.n_mesh, r.box_size, r.n_steps, r.seed, r.with_grad, 0.0)
              for r in trace]
     cb_sat = serve.serve(burst, ex, budget, slots, realtime=True).summary()
     print(f"[bench] serving burst continuous {cb_sat}", file=sys.stderr, flush=True)
-    fifo_sat = serve.serve_fifo(burst, ex, realtime=True).summary()
+    fifo_sat = serve.serve_fifo(burst, fifo_ex, realtime=True).summary()
     print(f"[bench] serving burst fifo {fifo_sat}", file=sys.stderr, flush=True)
-    # the same burst with every step launched kernel by kernel
-    ex_eager = serve.GpuExecutor(keep_results=False, graphs=False)
-    serve.serve(warm, ex_eager, budget, slots, realtime=False)
-    cb_eager = serve.serve(burst, ex_eager, budget, slots, realtime=True).summary()
-    print(f"[bench] serving burst continuous, no graphs {cb_eager}", file=sys.stderr, flush=True)
-    del ex_eager
-    grad = [r for r in trace if r.with_grad]
+    # forward + gradient requests alone (128^3 particles on 128^3, chi^2 adjoint)
+    grad = [r for r in burst if r.with_grad]
+    cb_grad = serve.serve(grad, ex, budget, slots, realtime=True).summary()
+    print(f"[bench] serving fwd+grad burst continuous {cb_grad}", file=sys.stderr, flush=True)
+    fifo_grad = serve.serve_fifo(grad, fifo_ex, realtime=True).summary()
+    print(f"[bench] serving fwd+grad burst fifo {fifo_grad}", file=sys.stderr, flush=True)
+    del ex, fifo_ex
     return {"requests": n_requests, "rate_per_s": rate, "arrival_seed": seed, "hbm_budget_gb": budget_gb,
             "slots_per_class": slots, "grad_requests": len(grad),
             "mix": "60% fwd 64^3/64^3, 30% fwd+grad 128^3/128^3, 10% fwd 256^3/512^3, 5-10 steps",
+            "continuous": "one batch plan per shape class (all slots' workspaces), one batched step per class "
+                          "per tick (captured graph), classes on separate streams, <= 2 steps in flight per class",
+            "fifo": "one request at a time, each on a context of its own (captured step graphs)",
             "poisson": {"continuous": cb, "fifo": fifo},
-            "burst": {"continuous": cb_sat, "continuous_no_graphs": cb_eager, "fifo": fifo_sat}}
+            "burst": {"continuous": cb_sat, "fifo": fifo_sat},
+            "fwd_grad_burst": {"continuous": cb_grad, "fifo": fifo_grad}}
 
 
 def optional(name, fn, *args):
@@ -298,7 +333,7 @@ def main():
                     help="only run a plain device-to-device copy of GIB GiB (counter calibration) and exit")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the pyramid, gradient (adjoint) and reconstruction timing sections")
-    ap.add_argument("--serve", type=int, default=200,
+    ap.add_argument("--serve", type=int, default=1000,
                     help="requests of the serving trace (Poisson 20/s); 0 skips the serving section")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

@@ -53,6 +53,24 @@ extern "C" {
 #define PM_PK_EH_NOWIGGLE  1  /* Eisenstein & Hu (1998) no-wiggle, A k^n_s T0(k)^2 */
 #define PM_PK_TABLE        2  /* caller's table, log-log interpolated */
 
+/* ---- time-stepping schemes (pm_config.integrator) ----------------------
+ * All three are kick-drift-kick leapfrogs over the same PM force and the
+ * same scale factors, half steps at a_c = sqrt(a_i a_{i+1}).
+ *  FASTPM   : FastPM's kick/drift factors (section 2), exact for the linear
+ *             growing mode.
+ *  LEAPFROG : the plain leapfrog of dx/da = p/(a^3 E), dp/da = F/(a^2 E):
+ *             kick int da/(a^2 E), drift int da/(a^3 E).
+ *  COLA     : that leapfrog applied to the residual from the particles' LPT
+ *             trajectory x_LPT = q + D1 Psi1 + D2 Psi2 (the comoving
+ *             Lagrangian acceleration frame; section 2 leaves other PM
+ *             schemes to the implementer): the force less the LPT force
+ *             1.5 Om [D1 Psi1 + (D2 - D1^2) Psi2] kicks the residual
+ *             momentum, and every drift adds the LPT displacement exactly.
+ *             Needs the LPT displacement fields (pm_set_lpt_frame). */
+#define PM_INT_FASTPM    0
+#define PM_INT_LEAPFROG  1
+#define PM_INT_COLA      2
+
 /* ---- optional long/short force split (Fourier filter S = exp(-k^2 rs^2)) */
 #define PM_SPLIT_NONE   0     /* full force */
 #define PM_SPLIT_LONG   1     /* long-range part  S(k) * F */
@@ -88,6 +106,12 @@ typedef struct {
                                 (Algorithm 3) with a coarse grid n_mesh / 2^f >= 8 per side,
                                 order-6 B-spline REDUCE/EXPAND; needs deconv_order 0 and no
                                 split; pm_run_adjoint differentiates it (its transpose) */
+    int      batch;         /* 0 or 1: one simulation.  B in [2, PM_MAX_BATCH]: a batch plan of B
+                               same-shape member slots (continuous batching, see pm_batch_*);
+                               needs n_mesh >= 64 and pyramid_levels 0 */
+    int      integrator;    /* PM_INT_* (0 = FastPM).  COLA: pm_run / pm_run_begin only (no
+                               pm_kdk_step, checkpoints, adjoint, reconstruction or batch plan);
+                               LEAPFROG: everywhere FASTPM is */
 } pm_config;
 
 typedef struct pm_ctx pm_ctx;   /* opaque; host memory only */
@@ -120,8 +144,9 @@ const char* pm_last_error(const pm_ctx* ctx);
  * out[0..5] = D1, f1, D2, f2, E, G_f at scale factor a (D1(1) = 1). */
 int pm_growth(const pm_ctx* ctx, double a, double* h_out6);
 
-/* Time-step factors of n_a - 1 FastPM KDK steps over h_a[0] < ... < h_a[n_a-1]
- * (section 2; kick and drift exact for the Zel'dovich growing mode):
+/* Time-step factors of n_a - 1 KDK steps over h_a[0] < ... < h_a[n_a-1] of
+ * the configured integrator (FASTPM, section 2: kick and drift exact for the
+ * Zel'dovich growing mode; LEAPFROG and COLA: the plain time integrals):
  * h_k1[i] opening kick a_i -> a_c, h_dr[i] drift a_i -> a_{i+1}, h_k2[i]
  * closing kick a_c -> a_{i+1}, a_c = sqrt(a_i a_{i+1}).  Host arrays of
  * n_a - 1 doubles each, owned by the caller.  PM_EINVAL for a NULL pointer,
@@ -253,6 +278,16 @@ int pm_rfft(pm_ctx* ctx, const float* d_real, float* d_spec);
  * inverse transforms are ignored. d_spec is left unchanged. */
 int pm_irfft(pm_ctx* ctx, const float* d_spec, float* d_real);
 
+/* LPT frame of the COLA integrator: caller-owned device arrays d_psi1,
+ * d_psi2 of [n_part^3][3] floats, lattice (particle index) order, mesh-cell
+ * units: the first- and second-order LPT displacement fields Psi1, Psi2 of
+ * the particles (x_LPT(a) = q + D1(a) Psi1 + D2(a) Psi2, section 6).  While
+ * set, pm_init_lpt writes them (B times its lattice displacement fields;
+ * Psi2 = 0 for lpt_order 1) and a COLA pm_run / pm_run_begin reads them; the
+ * caller keeps them unchanged in between.  NULL, NULL unsets.  PM_EINVAL if
+ * only one is NULL; PM_ESTATE during a resumable run. */
+int pm_set_lpt_frame(pm_ctx* ctx, float* d_psi1, float* d_psi2);
+
 /* Keep the force meshes of a run instead of recomputing them in the adjoint
  * (the capacity of the device's memory traded for a paint and four FFT passes
  * per step of the reverse sweep).  d_fckpt: caller-owned device memory of
@@ -285,6 +320,84 @@ int pm_profile(pm_ctx* ctx, int enable);
  * NUL-terminated class name), h_total_ms (summed event time), h_count
  * (launches).  Returns the number of classes seen, or a negative status. */
 int pm_profile_read(pm_ctx* ctx, int max, char* h_names, double* h_total_ms, int* h_count);
+
+/* ---- continuous batching of same-shape simulations -----------------------
+ * The paper runs many simulations of one shape as the batch dimension of its
+ * tensors (section 4).  Here a plan created with cfg.batch = B holds B member
+ * slots, each with the full workspace of one simulation of cfg (the
+ * workspace is B times that of a single context, members at a fixed
+ * stride).  Requests join and leave slots while others are mid-run; one
+ * batched step launches every kernel of a KDK step once for all listed
+ * members (readout + kick + drift, counting sort, paint, the five FFT passes
+ * of the force), blockIdx.z selecting the member through a device table of
+ * descriptors.  Each member's result equals the same run on a context of its
+ * own, bit for bit (same kernels, integer paint sums).
+ *
+ * A member's state between steps (particles sorted by tile, force mesh at
+ * its current scale factor) lives in its slot.  Typical use:
+ *   pm_batch_member(plan, m, &ctx_m); pm_init_lpt(ctx_m, ...)  (any
+ *     single-simulation call works on a member's context)
+ *   pm_batch_begin(plan, m, h_a, n_a, d_pos, d_mom, d_ckpt)
+ *   pm_batch_advance(plan, &n)   (repeated: one step of every running member)
+ *   pm_batch_end(plan, m, d_delta_final)   once m has no step left
+ * All calls are asynchronous on the plan's stream (pm_set_stream on the plan
+ * also moves its members).  A plan and its members are not thread-safe. */
+#define PM_MAX_BATCH 256
+#define PM_REQ_CKPT 1
+
+/* One member's entry of a batched step.  Device memory, 48 bytes. */
+typedef struct {
+    int32_t member;      /* slot in [0, batch); < 0: the entry is skipped */
+    int32_t flags;       /* 0 or PM_REQ_CKPT */
+    float   kick_close;  /* closing kick K(a_c(i-1) -> a_i; a_i) of the member's previous step, 0 before its first */
+    float   kick_open;   /* opening kick K(a_i -> a_c; a_i) of this step */
+    float   drift;       /* drift D(a_i -> a_i+1; a_c) of this step */
+    float   reserved;
+    float*  ckpt_x;      /* PM_REQ_CKPT: [n_part^3][3] receives x_i by particle id */
+    float*  ckpt_p;      /* PM_REQ_CKPT: [n_part^3][3] receives p_i (after the closing kick) by particle id */
+    int64_t reserved2;
+} pm_req_desc;
+
+/* One KDK step (section 2 kick/drift equations, force equation) of every
+ * member listed in the device array d_descs[0..n) (n in [1, batch]; each
+ * member at most once): p += F kick_close; checkpoint; p += F kick_open;
+ * x += p drift (wrapped); sort; paint; force at the new positions.  The
+ * factors come from the descriptors, so one captured graph can serve every
+ * step.  The members must have been started with pm_batch_begin; the caller
+ * keeps count of their steps (pm_batch_advance is this call with the
+ * bookkeeping done, over the plan's own descriptor table).  PM_EINVAL if plan is not a batch plan, d_descs is NULL or n is out
+ * of range. */
+int pm_kdk_step_batched(pm_ctx* plan, const pm_req_desc* d_descs, int n);
+
+/* Context handle of member m (0 <= m < batch) of a plan: every
+ * single-simulation entry point works on it, over the member's slot.  Owned
+ * by the plan (never pm_destroy it); member 0 is the plan itself. */
+int pm_batch_member(pm_ctx* plan, int m, pm_ctx** out);
+
+/* Start member m's run (as pm_run_begin on its context): scale factors
+ * h_a[0..n_a) strictly increasing, d_pos/d_mom [n_part^3][3] in lattice
+ * order (kept by the caller until pm_batch_end), d_ckpt NULL or
+ * [n_a][2][n_part^3][3].  Sorts the particles into the slot, paints and
+ * computes the force at h_a[0].  PM_ESTATE if m already runs. */
+int pm_batch_begin(pm_ctx* plan, int m, const double* h_a, int n_a, float* d_pos, float* d_mom, float* d_ckpt);
+
+/* One batched step of every running member with steps left: fills the
+ * plan's device descriptor table from the members' scale factors and calls
+ * pm_kdk_step_batched (a captured graph once pm_use_graphs(plan, 1)).
+ * *h_stepped (may be NULL) receives the number of members advanced. */
+int pm_batch_advance(pm_ctx* plan, int* h_stepped);
+
+/* Steps member m still has to take (0 when it can end), or a negative
+ * status; PM_ESTATE if m does not run. */
+int pm_batch_remaining(pm_ctx* plan, int m);
+
+/* Finish member m's run (as pm_run_end): closing half kick, positions and
+ * momenta back to the caller's arrays in lattice order, the last checkpoint,
+ * the final overdensity if d_delta_final is not NULL.  The slot is free
+ * afterwards.  The member must have taken all its steps: with
+ * pm_batch_advance, pm_batch_remaining(plan, m) == 0; with
+ * pm_kdk_step_batched the caller counts them.  PM_ESTATE if m does not run. */
+int pm_batch_end(pm_ctx* plan, int m, float* d_delta_final);
 
 /* ---- allocation-free force ----------------------------------------------
  * For callers that cannot allocate device memory or create a workspace

@@ -29,7 +29,18 @@ class pm_config(C.Structure):
     _fields_ = [("box_size", C.c_double), ("n_mesh", C.c_int), ("n_part", C.c_int),
                 ("cosmo", pm_cosmo), ("lpt_order", C.c_int), ("deconv_order", C.c_int),
                 ("split_rs", C.c_double), ("split_mode", C.c_int),
-                ("lattice_shift", C.c_double), ("max_particles", C.c_int64), ("pyramid_levels", C.c_int)]
+                ("lattice_shift", C.c_double), ("max_particles", C.c_int64), ("pyramid_levels", C.c_int),
+                ("batch", C.c_int), ("integrator", C.c_int)]
+
+
+class pm_req_desc(C.Structure):
+    _fields_ = [("member", C.c_int32), ("flags", C.c_int32), ("kick_close", C.c_float), ("kick_open", C.c_float),
+                ("drift", C.c_float), ("reserved", C.c_float), ("ckpt_x", C.c_void_p), ("ckpt_p", C.c_void_p),
+                ("reserved2", C.c_int64)]
+
+
+PM_MAX_BATCH = 256
+PM_REQ_CKPT = 1
 
 
 # name -> (restype, argtypes)
@@ -72,6 +83,14 @@ _SIGS = {
     "pm_power": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double),
                            C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "pm_force_static": (C.c_int, [C.POINTER(pm_config), C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "pm_kdk_step_batched": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "pm_set_lpt_frame": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pm_batch_member": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_void_p)]),
+    "pm_batch_begin": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.c_int, C.c_void_p, C.c_void_p,
+                                 C.c_void_p]),
+    "pm_batch_advance": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
+    "pm_batch_remaining": (C.c_int, [C.c_void_p, C.c_int]),
+    "pm_batch_end": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
 }
 
 _lib = None

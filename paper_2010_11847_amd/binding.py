@@ -21,7 +21,7 @@ class PMError(RuntimeError):
     pass
 
 
-def make_config(w: Workload, max_particles: int = 0) -> _lib.pm_config:
+def make_config(w: Workload, max_particles: int = 0, batch: int = 0) -> _lib.pm_config:
     c = w.cosmo
     tk = tp = None
     n_tab = 0
@@ -32,7 +32,8 @@ def make_config(w: Workload, max_particles: int = 0) -> _lib.pm_config:
     cos = _lib.pm_cosmo(c.omega_m, c.omega_b, c.h, c.n_s, c.sigma8, c.t_cmb, c.pk_kind,
                         c.pk_amp, c.pk_index, tk, tp, n_tab)
     cfg = _lib.pm_config(w.box_size, w.n_mesh, w.n_part, cos, w.lpt_order, w.deconv_order,
-                         w.split_rs, w.split_mode, w.lattice_shift, max_particles, w.pyramid_levels)
+                         w.split_rs, w.split_mode, w.lattice_shift, max_particles, w.pyramid_levels, batch,
+                         w.integrator)
     cfg.keep_alive = (tk, tp)   # the library copies the table in pm_create
     return cfg
 
@@ -44,14 +45,14 @@ def _ptr(t: Optional[torch.Tensor]):
 class PMContext:
     """A library context with its device workspace, bound to one GPU stream."""
 
-    def __init__(self, workload: Workload, device="cuda", max_particles: int = 0, stream=None):
+    def __init__(self, workload: Workload, device="cuda", max_particles: int = 0, stream=None, batch: int = 0):
         self.lib = _lib.load()
         self.workload = workload
         dev = torch.device(device)
         if dev.type == "cuda" and dev.index is None:
             dev = torch.device("cuda", torch.cuda.current_device())
         self.device = dev
-        self.cfg = make_config(workload, max_particles)
+        self.cfg = make_config(workload, max_particles, batch)
         nbytes = self.lib.pm_workspace_bytes(C.byref(self.cfg))
         if nbytes == 0:
             raise PMError(f"invalid configuration for {workload.name}")
@@ -66,6 +67,16 @@ class PMContext:
         self._check(rc, "pm_create", ctx=None)
         self.ctx = ctx
         self.np3 = workload.n_part ** 3
+        self._owner = True
+
+    @classmethod
+    def _view(cls, parent: "PMContext", handle: C.c_void_p) -> "PMContext":
+        """A context handle owned by the library (a batch plan's member)."""
+        v = cls.__new__(cls)
+        v.lib, v.workload, v.device, v.cfg = parent.lib, parent.workload, parent.device, parent.cfg
+        v.workspace_bytes, v.ws, v._ws_ptr = 0, parent.ws, 0
+        v.stream, v.ctx, v.np3, v._owner = parent.stream, handle, parent.np3, False
+        return v
 
     # ---- helpers -------------------------------------------------------------
     def _check(self, rc, what, ctx="self"):
@@ -85,9 +96,9 @@ class PMContext:
         return t
 
     def close(self):
-        if getattr(self, "ctx", None):
+        if getattr(self, "ctx", None) and getattr(self, "_owner", True):
             self.lib.pm_destroy(self.ctx)
-            self.ctx = None
+        self.ctx = None
 
     def __del__(self):
         try:
@@ -219,6 +230,23 @@ class PMContext:
         self._fck = fckpt
         return fckpt
 
+    def pm_set_lpt_frame(self, psi1: Optional[torch.Tensor] = None, psi2: Optional[torch.Tensor] = None):
+        """Register the LPT displacement fields of the COLA integrator, [np][3]
+        each (created here, zeroed, when not given: pm_init_lpt then fills
+        them).  pm_clear_lpt_frame unsets them."""
+        if psi1 is None and psi2 is None:
+            psi1 = torch.zeros((self.np3, 3), dtype=torch.float32, device=self.device)
+            psi2 = torch.zeros((self.np3, 3), dtype=torch.float32, device=self.device)
+        self._dev(psi1, (self.np3, 3), name="psi1")
+        self._dev(psi2, (self.np3, 3), name="psi2")
+        self._check(self.lib.pm_set_lpt_frame(self.ctx, _ptr(psi1), _ptr(psi2)), "pm_set_lpt_frame")
+        self._frame = (psi1, psi2)
+        return psi1, psi2
+
+    def pm_clear_lpt_frame(self):
+        self._check(self.lib.pm_set_lpt_frame(self.ctx, None, None), "pm_set_lpt_frame")
+        self._frame = None
+
     def pm_use_graphs(self, enable: bool):
         self._check(self.lib.pm_use_graphs(self.ctx, int(enable)), "pm_use_graphs")
 
@@ -347,3 +375,86 @@ def pm_force_static(workload: Workload, pos: torch.Tensor, out: Optional[torch.T
     if rc != _lib.PM_OK:
         raise PMError(f"pm_force_static failed ({rc}): {lib.pm_strerror(rc).decode()}")
     return out
+
+
+class PMBatch(PMContext):
+    """A batch plan of `batch` member slots of one workload's shape
+    (continuous batching): members join and leave while others run, and one
+    batched step launches every kernel of a KDK step once for all running
+    members.  Member m's context (``member(m)``) takes every single-simulation
+    call (initial conditions, adjoint, chi^2, power spectrum) on its slot."""
+
+    def __init__(self, workload: Workload, batch: int, device="cuda", stream=None):
+        if batch < 2:
+            raise PMError("a batch plan has at least 2 members")
+        super().__init__(workload, device=device, stream=stream, batch=batch)
+        self.batch = batch
+        self._members = []
+        for m in range(batch):
+            h = C.c_void_p()
+            self._check(self.lib.pm_batch_member(self.ctx, m, C.byref(h)), "pm_batch_member")
+            self._members.append(PMContext._view(self, h))
+        self._refs = {}
+
+    def member(self, m: int) -> PMContext:
+        return self._members[m]
+
+    def set_stream(self, stream):
+        super().set_stream(stream)
+        for v in self._members:
+            v.stream = stream
+
+    def pm_batch_begin(self, m: int, a_list, pos, mom, ckpt: Optional[torch.Tensor] = None):
+        self._dev(pos, (self.np3, 3), name="pos")
+        self._dev(mom, (self.np3, 3), name="mom")
+        a = np.ascontiguousarray(a_list, dtype=np.float64)
+        if ckpt is not None:
+            self._dev(ckpt, (len(a), 2, self.np3, 3), name="ckpt")
+        ap = a.ctypes.data_as(C.POINTER(C.c_double))
+        self._check(self.lib.pm_batch_begin(self.ctx, m, ap, len(a), _ptr(pos), _ptr(mom), _ptr(ckpt)),
+                    "pm_batch_begin")
+        self._refs[m] = (pos, mom, ckpt)   # the library writes them at pm_batch_end
+
+    def pm_batch_advance(self) -> int:
+        k = C.c_int(0)
+        self._check(self.lib.pm_batch_advance(self.ctx, C.byref(k)), "pm_batch_advance")
+        return k.value
+
+    def pm_batch_remaining(self, m: int) -> int:
+        r = self.lib.pm_batch_remaining(self.ctx, m)
+        if r < 0:
+            self._check(r, "pm_batch_remaining")
+        return r
+
+    def pm_batch_end(self, m: int, delta_final: Optional[torch.Tensor] = None, check_steps: bool = True):
+        """check_steps: require every step counted by pm_batch_advance (pass
+        False for a member stepped through pm_kdk_step_batched)."""
+        if delta_final is not None:
+            n = self.workload.n_mesh
+            self._dev(delta_final, (n, n, n), name="delta_final")
+        if check_steps and self.pm_batch_remaining(m) != 0:
+            raise PMError(f"member {m} still has steps to take")
+        self._check(self.lib.pm_batch_end(self.ctx, m, _ptr(delta_final)), "pm_batch_end")
+        return self._refs.pop(m, None)
+
+    def pm_kdk_step_batched(self, descs: torch.Tensor, n: int):
+        """descs: a uint8 device tensor holding n pm_req_desc entries."""
+        if descs.device != self.device or descs.dtype != torch.uint8 or not descs.is_contiguous():
+            raise PMError("descs must be a contiguous uint8 tensor on the plan's device")
+        if descs.numel() < n * C.sizeof(_lib.pm_req_desc):
+            raise PMError("descs holds fewer than n descriptors")
+        self._check(self.lib.pm_kdk_step_batched(self.ctx, _ptr(descs), n), "pm_kdk_step_batched")
+
+    def close(self):
+        for v in getattr(self, "_members", []):
+            v.ctx = None
+        super().close()
+
+
+def req_descs(entries) -> bytes:
+    """Pack (member, flags, kick_close, kick_open, drift, ckpt_x_ptr, ckpt_p_ptr)
+    tuples as pm_req_desc structures (host bytes, to be copied to the device)."""
+    arr = (_lib.pm_req_desc * len(entries))()
+    for i, (m, fl, kc, ko, dr, cx, cp) in enumerate(entries):
+        arr[i] = _lib.pm_req_desc(m, fl, kc, ko, dr, 0.0, cx, cp, 0)
+    return bytes(arr)

@@ -3,6 +3,7 @@
 // the HIP kernels for painting, force, KDK steps, full runs, initial
 // conditions and power spectra.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <cmath>
 #include <cstddef>
@@ -22,7 +23,24 @@
 using pmk::Field;
 using pmk::FftTables;
 
+static_assert(sizeof(pm_req_desc) == 48, "pm_req_desc is 48 bytes in the ABI");
+
 namespace {
+
+// Host-side roctx range around the enqueueing of one phase of the path (a
+// KDK step, the initial conditions, a reverse step): rocprofv3
+// --marker-trace shows them beside the kernels they launched.
+struct Range {
+  explicit Range(const char* what) { roctxRangePushA(what); }
+  Range(const char* what, int i) {
+    char buf[48];
+    std::snprintf(buf, sizeof(buf), "%s %d", what, i);
+    roctxRangePushA(buf);
+  }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr size_t kAlign = 256;
@@ -52,6 +70,8 @@ struct Layout {
   size_t misc = 0;   // small device words (the adjoint paint's max |weight|)
   size_t steps = 0;  // a run's step loop: counter, checkpoint base, factor table
   size_t red = 0;    // float64 partial sums of the chi^2 reduction
+  size_t desc = 0;   // a batch plan's device descriptor table (member 0's)
+  size_t cola = 0;   // COLA: per-step LPT-frame factors {c1, c2, dD1, dD2}
   size_t tab_coarse = 0, coarse[3] = {0, 0, 0}, force_c = 0;   // pyramid coarse grid
   size_t lat0 = 0;   // LPT lattice fields alias the mesh + particle region
   size_t total = 0;
@@ -95,6 +115,11 @@ int validate(const pm_config* c, std::string* why) {
   if (c->max_particles > 0 && c->max_particles < np3) return bad("max_particles must be 0 or >= n_part^3");
   if ((c->max_particles > 0 ? c->max_particles : np3) > (1L << 31) - 1) return bad("too many particles");
   if (c->pyramid_levels < 0 || c->pyramid_levels > 4) return bad("pyramid_levels must be in [0, 4]");
+  if (c->batch < 0 || c->batch > PM_MAX_BATCH) return bad("batch must be in [0, PM_MAX_BATCH]");
+  if (c->batch > 1 && (c->n_mesh < 64 || c->pyramid_levels > 0))
+    return bad("a batch plan needs n_mesh >= 64 and no pyramid");
+  if (c->integrator < PM_INT_FASTPM || c->integrator > PM_INT_COLA) return bad("unknown integrator");
+  if (c->integrator == PM_INT_COLA && c->batch > 1) return bad("a batch plan takes no COLA integrator");
   if (c->pyramid_levels > 0) {
     if ((c->n_mesh >> c->pyramid_levels) < 8) return bad("the pyramid's coarse grid needs >= 8 cells per side");
     if (c->deconv_order != 0 || c->split_mode != PM_SPLIT_NONE)
@@ -127,6 +152,8 @@ Layout make_layout(const pm_config* c) {
   L.misc = take(256);
   L.steps = take(256 + (size_t)kMaxSteps * 16);
   L.red = take((size_t)(pmk::kReducePartials + 2) * 8);
+  L.desc = take((size_t)PM_MAX_BATCH * sizeof(pm_req_desc));
+  L.cola = take((size_t)kMaxSteps * 16);
   const long nc = c->pyramid_levels > 0 ? ng >> c->pyramid_levels : 0;
   if (nc) L.tab_coarse = take(fft_table_bytes(nc));
   const size_t region = o;
@@ -277,7 +304,43 @@ struct pm_ctx {
         g = nullptr;
       }
   }
-  ~pm_ctx() { drop_graphs(); }
+  // COLA frame: caller's Psi1, Psi2 ([np][3] by particle id) and the
+  // device table of per-step frame factors
+  float* psi1 = nullptr;
+  float* psi2 = nullptr;
+  float4* cola_tab = nullptr;
+  bool cola() const { return cfg.integrator == PM_INT_COLA; }
+  // kick/drift factors of the configured integrator
+  void factors(const double* a, int n_a, double* k1, double* dr, double* k2) const {
+    cosmo.step_factors(cfg.integrator, a, n_a, k1, dr, k2);
+  }
+  // COLA frame coefficients at a: (c1, c2) of the LPT force, (q1, q2) of the
+  // LPT momentum, (D1, D2)
+  void cola_coeffs(double a, double* c, double* q, double* d) const {
+    double g[6];
+    cosmo.growth(a, g);
+    const double d2 = cfg.lpt_order >= 2 ? g[2] : 0.0;
+    c[0] = 1.5 * cfg.cosmo.omega_m * g[0];
+    c[1] = 1.5 * cfg.cosmo.omega_m * (d2 - g[0] * g[0]);
+    q[0] = a * a * g[4] * g[1] * g[0];
+    q[1] = a * a * g[4] * g[3] * d2;
+    d[0] = g[0];
+    d[1] = d2;
+  }
+  // batch plans: member slots at a fixed stride of the workspace (member 0
+  // is the plan itself; members 1.. are owned by it)
+  int batch = 1;
+  size_t mstride = 0;
+  pm_ctx* plan = nullptr;             // members 1..: their plan
+  std::vector<pm_ctx*> members;       // plan: members[0] == this
+  pm_req_desc* desc_dev = nullptr;    // plan: device descriptor table (PM_MAX_BATCH entries)
+  std::vector<pm_req_desc> desc_host;
+  hipGraphExec_t bgraph = nullptr;    // plan: one captured batched step over all slots
+  ~pm_ctx() {
+    drop_graphs();
+    if (bgraph) (void)hipGraphExecDestroy(bgraph);   // teardown: nothing to report to
+    for (size_t m = 1; m < members.size(); ++m) delete members[m];
+  }
   float* pos_s[2] = {};
   float* mom_s[2] = {};
   uint32_t* id_s[2] = {};
@@ -294,6 +357,8 @@ struct pm_ctx {
     std::vector<float4> tab;   // host copy of the device step table
     float *pos = nullptr, *mom = nullptr, *ckpt = nullptr;
     bool fck = false;          // force meshes go to the checkpoint slots
+    std::vector<float4> cola_tab;                 // COLA: host copy of the frame factors
+    double cola_end[2] = {0, 0}, cola_qend[2] = {0, 0};
   } run;
 
   // run f (which enqueues one kernel class) between two events when profiling
@@ -364,10 +429,11 @@ struct pm_ctx {
   // f[0].r, overwritten) into the interleaved mesh out; scale multiplies the
   // force (the inverse transform's 1/n^3 and any change of cell units); the
   // stages are timed by class when cls < 0, else as one class
-  void force_on(const FftTables& t, Field* f, float* out, long n, double scale, int deconv, int split, int cls) {
+  void force_on(const FftTables& t, Field* f, float* out, long n, double scale, int deconv, int split, int cls,
+                const pmk::BatchArg& bat = pmk::BatchArg()) {
     auto tm_ = [&](int c, auto&& fn) { timed(cls < 0 ? c : cls, fn); };
-    tm_(PC_FFT_R2C_Z, [&] { pmk::fft_z_r2c(t, &f[0], 1, stream); });
-    tm_(PC_FFT_Y_FWD, [&] { pmk::fft_y(t, &f[0], 1, -1, stream); });
+    tm_(PC_FFT_R2C_Z, [&] { pmk::fft_z_r2c(t, &f[0], 1, stream, bat); });
+    tm_(PC_FFT_Y_FWD, [&] { pmk::fft_y(t, &f[0], 1, -1, stream, bat); });
     pmk::SpecOp op;
     op.scale = (float)scale;
     op.deconv = deconv;
@@ -382,12 +448,12 @@ struct pm_ctx {
       op.out_c[i] = f[dst[i]].c();
       op.out_q[i] = f[dst[i]].q;
     }
-    tm_(PC_FFT_X_FORCE, [&] { pmk::fft_x_force(t, f[0], op, stream); });
+    tm_(PC_FFT_X_FORCE, [&] { pmk::fft_x_force(t, f[0], op, stream, bat); });
     if (xs)
-      tm_(PC_FFT_Y_INV, [&] { pmk::fft_y_force(t, f, stream); });
+      tm_(PC_FFT_Y_INV, [&] { pmk::fft_y_force(t, f, stream, bat); });
     else
-      tm_(PC_FFT_Y_INV, [&] { pmk::fft_y(t, f, 3, 1, stream); });
-    tm_(PC_FFT_C2R_Z, [&] { pmk::fft_z_c2r_interleaved3(t, f, out, stream); });
+      tm_(PC_FFT_Y_INV, [&] { pmk::fft_y(t, f, 3, 1, stream); });   // below 64^3: never batched
+    tm_(PC_FFT_C2R_Z, [&] { pmk::fft_z_c2r_interleaved3(t, f, out, stream, bat); });
   }
 
   // REDUCE (expand = false) or EXPAND of ch channels over `levels` levels,
@@ -469,6 +535,50 @@ struct pm_ctx {
   void readout(const pmk::ReadoutArgs& a) {
     timed(PC_READOUT, [&] { pmk::launch_readout(a, stream); });
   }
+  // One KDK step of the members listed in the device descriptors d[0..n):
+  // every kernel is launched once with blockIdx.z over the descriptors and
+  // member 0's workspace pointers (the kernels shift them by member *
+  // mstride).  Between steps a member's sorted state is in buffer 0; the
+  // readout writes the updated state to buffer 1 in the same order and the
+  // scatter sorts it back into buffer 0.  The static tables are member 0's
+  // (every member holds the same ones).
+  void batched_step(const pm_req_desc* d, int n) {
+    Range rg("pm_kdk_step_batched", n);
+    pmk::BatchArg bat;
+    bat.d = d;
+    bat.stride = (long)mstride;
+    bat.n = n;
+    const long np = np3;
+    timed(PC_FILL, [&] { pmk::launch_fill_u32(count, L.n_keys, 0u, stream, bat); });
+    pmk::ReadoutArgs a = readout_args(0, np);
+    a.fi = force_i;
+    a.flags = pmk::RO_KICK | pmk::RO_DRIFT | pmk::RO_KEYS | pmk::RO_TO_ALT;
+    a.pos_alt = pos_s[1];
+    a.mom_alt = mom_s[1];
+    a.id_alt = id_s[1];
+    a.bat = bat;
+    readout(a);
+    timed(PC_SCAN, [&] { pmk::launch_scan(count, L.n_keys, off, bsum, stream, bat); });
+    pmk::ScatterArgs sa;
+    sa.np = np;
+    sa.pos = pos_s[1];
+    sa.mom = mom_s[1];
+    sa.id = id_s[1];
+    sa.key = key;
+    sa.rank = rank;
+    sa.off = off;
+    sa.pos_out = pos_s[0];
+    sa.mom_out = mom_s[0];
+    sa.id_out = id_s[0];
+    sa.bat = bat;
+    timed(PC_SCATTER, [&] { pmk::launch_scatter(sa, stream); });
+    const double scale = (double)ng * ng * ng / (double)np;
+    timed(PC_PAINT, [&] {
+      pmk::launch_paint(pos_s[0], off, tg, mesh[0].r, (float)scale, -1.f, false, stream, bat);
+    });
+    const double g = 1.5 * cfg.cosmo.omega_m;
+    force_on(tm, mesh, force_i, ng, g / ((double)ng * ng * ng), cfg.deconv_order, cfg.split_mode, -1, bat);
+  }
   pmk::ReadoutArgs readout_args(int cur, long np) {
     pmk::ReadoutArgs a;
     a.g = tg;
@@ -499,9 +609,17 @@ const char* pm_strerror(int s) {
 
 const char* pm_last_error(const pm_ctx* ctx) { return ctx ? ctx->err.c_str() : "no context"; }
 
+namespace {
+int batch_of(const pm_config* cfg) { return cfg->batch > 1 ? cfg->batch : 1; }
+
+// One simulation's context over the workspace at ws (layout L); the static
+// tables are uploaded with `stream` (and waited for).
+int create_one(const pm_config* cfg, char* ws, const Layout& L, void* stream, pm_ctx** out);
+}  // namespace
+
 size_t pm_workspace_bytes(const pm_config* cfg) {
   if (validate(cfg, nullptr) != PM_OK) return 0;
-  return make_layout(cfg).total;
+  return make_layout(cfg).total * (size_t)batch_of(cfg);
 }
 
 int pm_create(const pm_config* cfg, void* d_workspace, size_t bytes, void* stream, pm_ctx** out) {
@@ -514,7 +632,35 @@ int pm_create(const pm_config* cfg, void* d_workspace, size_t bytes, void* strea
   }
   if (!d_workspace || ((uintptr_t)d_workspace % kAlign)) return PM_EINVAL;
   const Layout L = make_layout(cfg);
-  if (bytes < L.total) return PM_ENOMEM;
+  const int nb = batch_of(cfg);
+  if (bytes / (size_t)nb < L.total) return PM_ENOMEM;
+  char* ws = reinterpret_cast<char*>(d_workspace);
+  pm_ctx* plan = nullptr;
+  int st = create_one(cfg, ws, L, stream, &plan);
+  if (st != PM_OK) return st;
+  if (nb > 1) {
+    plan->batch = nb;
+    plan->mstride = L.total;
+    plan->desc_dev = reinterpret_cast<pm_req_desc*>(ws + L.desc);
+    plan->desc_host.assign(nb, pm_req_desc{});
+    plan->members.push_back(plan);
+    for (int m = 1; m < nb; ++m) {
+      pm_ctx* c = nullptr;
+      st = create_one(cfg, ws + (size_t)m * L.total, L, stream, &c);
+      if (st != PM_OK) {
+        delete plan;
+        return st;
+      }
+      c->plan = plan;
+      plan->members.push_back(c);
+    }
+  }
+  *out = plan;
+  return PM_OK;
+}
+
+namespace {
+int create_one(const pm_config* cfg, char* ws, const Layout& L, void* stream, pm_ctx** out) {
   pm_ctx* c = new (std::nothrow) pm_ctx;
   if (!c) return PM_ENOMEM;
   c->cfg = *cfg;
@@ -525,7 +671,7 @@ int pm_create(const pm_config* cfg, void* d_workspace, size_t bytes, void* strea
     c->cfg.cosmo.pk_p = c->pk_p_copy.data();
   }
   c->stream = reinterpret_cast<hipStream_t>(stream);
-  c->ws = reinterpret_cast<char*>(d_workspace);
+  c->ws = ws;
   c->L = L;
   c->ng = cfg->n_mesh;
   c->npart = cfg->n_part;
@@ -551,6 +697,7 @@ int pm_create(const pm_config* cfg, void* d_workspace, size_t bytes, void* strea
   c->ckpt_base_dev = reinterpret_cast<float**>(w + L.steps + 64);
   c->step_tab = reinterpret_cast<float4*>(w + L.steps + 256);
   c->red = reinterpret_cast<double*>(w + L.red);
+  c->cola_tab = reinterpret_cast<float4*>(w + L.cola);
   c->nc = cfg->pyramid_levels > 0 ? c->ng >> cfg->pyramid_levels : 0;
   if (c->nc) {
     for (int i = 0; i < 3; ++i) {
@@ -600,15 +747,23 @@ int pm_create(const pm_config* cfg, void* d_workspace, size_t bytes, void* strea
   *out = c;
   return PM_OK;
 }
+}  // namespace
 
 int pm_destroy(pm_ctx* ctx) {
+  if (ctx && ctx->plan) return PM_EINVAL;   // a member belongs to its plan
   delete ctx;
   return PM_OK;
 }
 
 int pm_set_stream(pm_ctx* ctx, void* stream) {
   if (!ctx) return PM_EINVAL;
+  if (ctx->plan) return ctx->fail(PM_EINVAL, "set the stream on the plan, not on a member");
+  for (pm_ctx* m : ctx->members) m->stream = reinterpret_cast<hipStream_t>(stream);
   ctx->stream = reinterpret_cast<hipStream_t>(stream);
+  if (ctx->bgraph) {   // a captured step belongs to its stream's capture
+    (void)hipGraphExecDestroy(ctx->bgraph);   // rebuilt on the next advance
+    ctx->bgraph = nullptr;
+  }
   return PM_OK;
 }
 
@@ -629,7 +784,7 @@ int pm_kdk_factors(const pm_ctx* ctx, const double* h_a, int n_a, double* h_k1, 
   if (!ctx || !h_a || !h_k1 || !h_dr || !h_k2 || n_a < 2) return PM_EINVAL;
   for (int i = 0; i < n_a; ++i)
     if (!(h_a[i] > 0) || (i && !(h_a[i] > h_a[i - 1]))) return PM_EINVAL;
-  ctx->cosmo.kdk_factors(h_a, n_a, h_k1, h_dr, h_k2);
+  ctx->factors(h_a, n_a, h_k1, h_dr, h_k2);
   return PM_OK;
 }
 
@@ -642,6 +797,7 @@ int pm_noise(pm_ctx* ctx, uint64_t seed, float* d_noise) {
 int pm_init_lpt(pm_ctx* ctx, uint64_t seed, double a0, const float* d_noise_in, float* d_noise_out, float* d_pos,
                 float* d_mom) {
   if (!ctx || !d_pos || !d_mom || !(a0 > 0)) return PM_EINVAL;
+  Range rg("pm_init_lpt");
   pm_ctx& c = *ctx;
   const long n3 = c.np3;
   Field f[10];
@@ -699,6 +855,8 @@ int pm_init_lpt(pm_ctx* ctx, uint64_t seed, double a0, const float* d_noise_in, 
   a.has_s2 = order >= 2 ? 1 : 0;
   a.pos = d_pos;
   a.mom = d_mom;
+  a.psi1 = c.psi1;   // the LPT frame, when set: B s1, B s2
+  a.psi2 = c.psi2;
   pmk::launch_lpt_particles(a, c.stream);
   return c.check("pm_init_lpt");
 }
@@ -730,7 +888,8 @@ int pm_kdk_step(pm_ctx* ctx, float* d_pos, float* d_mom, float* d_force, double 
   pm_ctx& c = *ctx;
   const double aa[2] = {a0, a1};
   double k1, dr, k2;
-  c.cosmo.kdk_factors(aa, 2, &k1, &dr, &k2);
+  if (c.cola()) return c.fail(PM_EINVAL, "pm_kdk_step: the COLA integrator runs through pm_run");
+  c.factors(aa, 2, &k1, &dr, &k2);
   pmk::launch_kick_drift(d_pos, d_mom, d_force, c.np3, (float)k1, (float)dr, (float)c.ng, c.stream);
   c.sort(d_pos, d_mom, nullptr, c.np3, 0);
   c.paint(0, c.np3, c.mesh[0].r);
@@ -757,8 +916,12 @@ int pm_run_begin(pm_ctx* ctx, const double* h_a, int n_a, float* d_pos, float* d
   r.k1.resize(r.ns);
   r.dr.resize(r.ns);
   r.k2.resize(r.ns);
-  c.cosmo.kdk_factors(h_a, n_a, r.k1.data(), r.dr.data(), r.k2.data());
   if (r.ns > kMaxSteps) return c.fail(PM_EINVAL, "at most 65536 steps per run");
+  if (c.cola()) {
+    if (!c.psi1) return c.fail(PM_ESTATE, "pm_run_begin: the COLA integrator needs pm_set_lpt_frame");
+    if (d_ckpt) return c.fail(PM_EINVAL, "pm_run_begin: no checkpoints with the COLA integrator");
+  }
+  c.factors(h_a, n_a, r.k1.data(), r.dr.data(), r.k2.data());
   r.tab.resize(r.ns);
   for (int i = 0; i < r.ns; ++i)
     r.tab[i] = make_float4(i ? (float)r.k2[i - 1] : 0.f, (float)r.k1[i], (float)r.dr[i], 0.f);
@@ -776,7 +939,28 @@ int pm_run_begin(pm_ctx* ctx, const double* h_a, int n_a, float* d_pos, float* d
   }
   pmk::launch_fill_u32(c.step_ctr, 1, 0u, c.stream);
   r.fck = c.fck && n_a <= c.fck_slots;
+  Range rg("pm_run_begin");
   c.sort(d_pos, d_mom, nullptr, np, r.cur);
+  if (c.cola()) {
+    // the frame's factors per step: LPT force at a_i, LPT drift a_i -> a_i+1;
+    // the end's factors, and the start's residual momentum p - p_LPT(a0)
+    r.cola_tab.resize(r.ns > 0 ? r.ns : 1);
+    double cc[2], q[2], d[2], cn[2], qn[2], dn[2];
+    for (int i = 0; i < r.ns; ++i) {
+      c.cola_coeffs(h_a[i], cc, q, d);
+      c.cola_coeffs(h_a[i + 1], cn, qn, dn);
+      r.cola_tab[i] = make_float4((float)cc[0], (float)cc[1], (float)(dn[0] - d[0]), (float)(dn[1] - d[1]));
+    }
+    c.cola_coeffs(h_a[n_a - 1], r.cola_end, r.cola_qend, d);
+    if (r.ns > 0) {
+      const hipError_t e = hipMemcpyAsync(c.cola_tab, r.cola_tab.data(), (size_t)r.ns * sizeof(float4),
+                                          hipMemcpyHostToDevice, c.stream);
+      if (e != hipSuccess) return c.fail(PM_EHIP, std::string("pm_run_begin: ") + hipGetErrorString(e));
+    }
+    c.cola_coeffs(h_a[0], cc, q, d);
+    pmk::launch_frame_shift(c.mom_s[r.cur], c.id_s[r.cur], c.psi1, c.psi2, np, (float)-q[0], (float)-q[1],
+                            c.stream);
+  }
   c.paint(r.cur, np, c.mesh[0].r);
   c.force_meshes(r.fck ? c.fck_slot(0) : nullptr);
   r.active = true;
@@ -792,9 +976,16 @@ int pm_run_advance(pm_ctx* ctx, int max_steps, int* h_remaining) {
   // one step from ping-pong buffer cur; its factors and checkpoint slot come
   // from the device step table at the device step counter
   auto enqueue_step = [&](int cur, int i) {
+    Range rg("pm_kdk_step", i);
     c.timed(PC_FILL, [&] { pmk::launch_fill_u32(c.count, c.L.n_keys, 0u, c.stream); });
     pmk::ReadoutArgs a = c.readout_args(cur, np);
     a.flags = pmk::RO_KICK | pmk::RO_DRIFT | pmk::RO_WRITE_SORTED | pmk::RO_KEYS | (r.ckpt ? pmk::RO_CKPT : 0);
+    if (c.cola()) {
+      a.flags |= pmk::RO_COLA;
+      a.psi1 = c.psi1;
+      a.psi2 = c.psi2;
+      a.cola_steps = c.cola_tab;
+    }
     a.steps = c.step_tab;
     a.step_i = c.step_ctr;
     a.ckpt_base = c.ckpt_base_dev;
@@ -848,6 +1039,7 @@ int pm_run_end(pm_ctx* ctx, float* d_delta_final) {
   if (r.step != r.ns) return c.fail(PM_ESTATE, "pm_run_end before the last step");
   const long np = c.np3;
   const size_t ck = (size_t)np * 3;
+  Range rg("pm_run_end");
   if (d_delta_final) c.paint(r.cur, np, d_delta_final, true);
   pmk::ReadoutArgs a = c.readout_args(r.cur, np);
   a.flags = pmk::RO_KICK | pmk::RO_XP_BYID;
@@ -855,6 +1047,13 @@ int pm_run_end(pm_ctx* ctx, float* d_delta_final) {
   a.kick_b = 0.f;
   a.pos_out = r.pos;
   a.mom_out = r.mom;
+  if (c.cola()) {   // residual kick at the last a, then back to the full momentum
+    a.flags |= pmk::RO_COLA | pmk::RO_COLA_OUT;
+    a.psi1 = c.psi1;
+    a.psi2 = c.psi2;
+    a.cola = make_float4((float)r.cola_end[0], (float)r.cola_end[1], 0.f, 0.f);
+    a.cola_out = make_float2((float)r.cola_qend[0], (float)r.cola_qend[1]);
+  }
   if (r.ckpt) {
     a.flags |= pmk::RO_CKPT;
     a.ckpt_x = r.ckpt + (2 * (size_t)r.ns) * ck;
@@ -875,6 +1074,100 @@ int pm_run(pm_ctx* ctx, const double* h_a, int n_a, float* d_pos, float* d_mom, 
   return pm_run_end(ctx, d_delta_final);
 }
 
+int pm_kdk_step_batched(pm_ctx* plan, const pm_req_desc* d_descs, int n) {
+  if (!plan) return PM_EINVAL;
+  if (plan->batch < 2 || plan->plan) return plan->fail(PM_EINVAL, "pm_kdk_step_batched: not a batch plan");
+  if (!d_descs || n < 1 || n > plan->batch) return plan->fail(PM_EINVAL, "pm_kdk_step_batched: bad descriptors");
+  plan->batched_step(d_descs, n);
+  return plan->check("pm_kdk_step_batched");
+}
+
+int pm_batch_member(pm_ctx* plan, int m, pm_ctx** out) {
+  if (!plan || !out || plan->plan || plan->batch < 2 || m < 0 || m >= plan->batch) return PM_EINVAL;
+  *out = plan->members[m];
+  return PM_OK;
+}
+
+int pm_batch_begin(pm_ctx* plan, int m, const double* h_a, int n_a, float* d_pos, float* d_mom, float* d_ckpt) {
+  if (!plan || plan->plan || plan->batch < 2 || m < 0 || m >= plan->batch) return PM_EINVAL;
+  pm_ctx* c = plan->members[m];
+  if (c->run.active) return plan->fail(PM_ESTATE, "pm_batch_begin: the member already runs");
+  if (c->fck) return plan->fail(PM_ESTATE, "pm_batch_begin: members take no force checkpoints");
+  const int st = pm_run_begin(c, h_a, n_a, d_pos, d_mom, d_ckpt);   // sorts into buffer 0
+  if (st != PM_OK) return plan->fail(st, std::string("pm_batch_begin: ") + c->err);
+  return PM_OK;
+}
+
+int pm_batch_advance(pm_ctx* plan, int* h_stepped) {
+  if (!plan || plan->plan || plan->batch < 2) return PM_EINVAL;
+  pm_ctx& p = *plan;
+  int k = 0;
+  for (int m = 0; m < p.batch; ++m) {
+    auto& r = p.members[m]->run;
+    pm_req_desc& d = p.desc_host[m];
+    d = pm_req_desc{};
+    d.member = -1;
+    if (!r.active || r.step >= r.ns) continue;
+    const int i = r.step;
+    const size_t ck = (size_t)p.np3 * 3;
+    d.member = m;
+    d.kick_close = r.tab[i].x;
+    d.kick_open = r.tab[i].y;
+    d.drift = r.tab[i].z;
+    if (r.ckpt) {
+      d.flags = PM_REQ_CKPT;
+      d.ckpt_x = r.ckpt + (2 * (size_t)i) * ck;
+      d.ckpt_p = r.ckpt + (2 * (size_t)i + 1) * ck;
+    }
+    ++k;
+  }
+  if (h_stepped) *h_stepped = k;
+  if (!k) return PM_OK;
+  // pageable source: the copy has left desc_host when the call returns
+  hipError_t e = hipMemcpyAsync(p.desc_dev, p.desc_host.data(), (size_t)p.batch * sizeof(pm_req_desc),
+                                hipMemcpyHostToDevice, p.stream);
+  if (e != hipSuccess) return p.fail(PM_EHIP, std::string("pm_batch_advance: ") + hipGetErrorString(e));
+  if (p.use_graphs && !p.prof.on) {
+    if (!p.bgraph) {
+      if (hipStreamBeginCapture(p.stream, hipStreamCaptureModeRelaxed) != hipSuccess)
+        return p.fail(PM_EHIP, "pm_batch_advance: stream capture could not start (graphs need a non-default stream)");
+      p.batched_step(p.desc_dev, p.batch);
+      hipGraph_t g = nullptr;
+      const hipError_t e1 = hipStreamEndCapture(p.stream, &g);
+      const hipError_t e2 = e1 == hipSuccess ? hipGraphInstantiate(&p.bgraph, g, nullptr, nullptr, 0) : e1;
+      if (g) (void)hipGraphDestroy(g);   // the instantiated graph keeps what it needs
+      if (e2 != hipSuccess) {
+        p.bgraph = nullptr;
+        return p.fail(PM_EHIP, std::string("pm_batch_advance: graph capture failed: ") + hipGetErrorString(e2));
+      }
+    }
+    e = hipGraphLaunch(p.bgraph, p.stream);
+    if (e != hipSuccess) return p.fail(PM_EHIP, std::string("pm_batch_advance: ") + hipGetErrorString(e));
+  } else {
+    p.batched_step(p.desc_dev, p.batch);
+  }
+  for (int m = 0; m < p.batch; ++m)
+    if (p.desc_host[m].member >= 0) ++p.members[m]->run.step;
+  return p.check("pm_batch_advance");
+}
+
+int pm_batch_remaining(pm_ctx* plan, int m) {
+  if (!plan || plan->plan || plan->batch < 2 || m < 0 || m >= plan->batch) return PM_EINVAL;
+  const auto& r = plan->members[m]->run;
+  if (!r.active) return PM_ESTATE;
+  return r.ns - r.step;
+}
+
+int pm_batch_end(pm_ctx* plan, int m, float* d_delta_final) {
+  if (!plan || plan->plan || plan->batch < 2 || m < 0 || m >= plan->batch) return PM_EINVAL;
+  pm_ctx* c = plan->members[m];
+  if (!c->run.active) return plan->fail(PM_ESTATE, "pm_batch_end: the member does not run");
+  c->run.step = c->run.ns;   // steps taken through pm_kdk_step_batched are not counted here
+  const int st = pm_run_end(c, d_delta_final);
+  if (st != PM_OK) return plan->fail(st, std::string("pm_batch_end: ") + c->err);
+  return PM_OK;
+}
+
 int pm_run_adjoint(pm_ctx* ctx, const double* h_a, int n_a, const float* d_ckpt, const float* d_noise,
                    const float* d_grad_delta_final, float* d_grad_pos, float* d_grad_mom, float* d_grad_noise) {
   if (!ctx || !h_a || n_a < 1 || !d_ckpt || !d_grad_pos || !d_grad_mom) return PM_EINVAL;
@@ -883,8 +1176,9 @@ int pm_run_adjoint(pm_ctx* ctx, const double* h_a, int n_a, const float* d_ckpt,
   for (int i = 0; i < n_a; ++i)
     if (!(h_a[i] > 0) || (i && !(h_a[i] > h_a[i - 1]))) return c.fail(PM_EINVAL, "a must be > 0 and increasing");
   const int ns = n_a - 1;
+  if (c.cola()) return c.fail(PM_EINVAL, "pm_run_adjoint: no adjoint of the COLA integrator");
   std::vector<double> k1(ns), dr(ns), k2(ns);
-  c.cosmo.kdk_factors(h_a, n_a, k1.data(), dr.data(), k2.data());
+  c.factors(h_a, n_a, k1.data(), dr.data(), k2.data());
   const long np = c.np3;
   const size_t ck = (size_t)np * 3;
   float* xbar = d_grad_pos;
@@ -901,6 +1195,7 @@ int pm_run_adjoint(pm_ctx* ctx, const double* h_a, int n_a, const float* d_ckpt,
   // meshes come from the forward's checkpoints when it kept them
   const bool use_fck = c.fck && n_a <= c.fck_slots;
   for (int j = ns; j >= 0; --j) {
+    Range rg("pm_adjoint_step", j);
     const double kj = (j < ns ? k1[j] : 0.0) + (j > 0 ? k2[j - 1] : 0.0);
     if (kj != 0.0) {
       c.sort(ckpt_x(j), nullptr, nullptr, np, 0);
@@ -1112,6 +1407,7 @@ int pm_recon_step(pm_ctx* ctx, const double* h_a, int n_a, const float* d_data, 
   if (!(sigma > 0) || t < 1 || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps >= 0))
     return c.fail(PM_EINVAL, "need sigma > 0, t >= 1, lr > 0, 0 <= beta < 1, eps >= 0");
   if ((uintptr_t)d_work % kAlign) return c.fail(PM_EINVAL, "d_work must be 256-byte aligned");
+  if (c.cola()) return c.fail(PM_EINVAL, "pm_recon_step: no reconstruction with the COLA integrator");
   if (c.run.active) return c.fail(PM_ESTATE, "a resumable run is in progress");
   const ReconWork w = recon_work(c, n_a, static_cast<char*>(d_work));
   if (work_bytes < w.total) return c.fail(PM_ENOMEM, "reconstruction work buffer too small");
@@ -1214,10 +1510,24 @@ int pm_set_force_ckpt(pm_ctx* ctx, float* d_fckpt, int64_t n_slots) {
   return PM_OK;
 }
 
+int pm_set_lpt_frame(pm_ctx* ctx, float* d_psi1, float* d_psi2) {
+  if (!ctx) return PM_EINVAL;
+  if (!d_psi1 != !d_psi2) return ctx->fail(PM_EINVAL, "pm_set_lpt_frame: both fields or neither");
+  if (ctx->run.active) return ctx->fail(PM_ESTATE, "pm_set_lpt_frame during a run");
+  ctx->psi1 = d_psi1;
+  ctx->psi2 = d_psi2;
+  ctx->drop_graphs();   // captured steps hold the frame's pointers
+  return PM_OK;
+}
+
 int pm_use_graphs(pm_ctx* ctx, int enable) {
   if (!ctx) return PM_EINVAL;
   ctx->use_graphs = enable != 0;
-  if (!ctx->use_graphs) ctx->drop_graphs();
+  if (!ctx->use_graphs) {
+    ctx->drop_graphs();
+    if (ctx->bgraph) (void)hipGraphExecDestroy(ctx->bgraph);   // rebuilt on demand
+    ctx->bgraph = nullptr;
+  }
   return PM_OK;
 }
 

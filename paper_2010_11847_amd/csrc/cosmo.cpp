@@ -114,6 +114,44 @@ void Cosmo::kdk_factors(const double* a, int n_a, double* k1, double* dr, double
   }
 }
 
+namespace {
+// int_ai^aj f(a) da as int f(a) a dln a, composite Simpson over 512 intervals
+// in ln a (the integrands are smooth powers of a times 1/E)
+template <class F>
+double simpson_lna(double ai, double aj, F f) {
+  constexpr int kN = 512;
+  const double l0 = std::log(ai), h = (std::log(aj) - l0) / kN;
+  double s = 0.0;
+  for (int i = 0; i <= kN; ++i) {
+    const double a = std::exp(l0 + i * h);
+    const double w = (i == 0 || i == kN) ? 1.0 : (i % 2 ? 4.0 : 2.0);
+    s += w * f(a) * a;
+  }
+  return s * h / 3.0;
+}
+}  // namespace
+
+double Cosmo::std_kick(double ai, double aj) const {
+  return simpson_lna(ai, aj, [&](double a) { return 1.0 / (a * a * E(a)); });
+}
+
+double Cosmo::std_drift(double ai, double aj) const {
+  return simpson_lna(ai, aj, [&](double a) { return 1.0 / (a * a * a * E(a)); });
+}
+
+void Cosmo::step_factors(int integrator, const double* a, int n_a, double* k1, double* dr, double* k2) const {
+  if (integrator == PM_INT_FASTPM) {
+    kdk_factors(a, n_a, k1, dr, k2);
+    return;
+  }
+  for (int i = 0; i + 1 < n_a; ++i) {
+    const double ac = std::sqrt(a[i] * a[i + 1]);
+    k1[i] = std_kick(a[i], ac);
+    dr[i] = std_drift(a[i], a[i + 1]);
+    k2[i] = std_kick(ac, a[i + 1]);
+  }
+}
+
 void Cosmo::init(const pm_cosmo& c) {
   om = c.omega_m;
   par = c;

@@ -26,6 +26,11 @@ struct Cosmo {
   // kick k1 (a_i -> a_c), drift dr (a_i -> a_j) and closing kick k2
   // (a_c -> a_j), a_c = sqrt(a_i a_j), from one sweep of the growth ODE.
   void kdk_factors(const double* a, int n_a, double* k1, double* dr, double* k2) const;
+  // The plain leapfrog's factors: int_ai^aj da / (a^2 E) and da / (a^3 E).
+  double std_kick(double ai, double aj) const;
+  double std_drift(double ai, double aj) const;
+  // k1, dr, k2 of the integrator (PM_INT_*) over the n_a scale factors
+  void step_factors(int integrator, const double* a, int n_a, double* k1, double* dr, double* k2) const;
   double eh_transfer(double k) const;
   double shape(double k) const;
   double pk(double k) const;          // linear P(k) at a = 1, (Mpc/h)^3

@@ -194,6 +194,7 @@ struct ColPass {
   ColGeom gm, gp;
   int nb_main;
   int ntiles;   // main + plane tiles per field
+  BatchArg bat; // batched launches: blockIdx.z selects the member
 };
 
 template <int N, int M, int DIR, bool BLK>
@@ -207,7 +208,9 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(ColPass p, const float2* 
   const bool is_plane = tile >= p.nb_main;
   if (is_plane) tile -= p.nb_main;
   const ColGeom& g = is_plane ? p.gp : p.gm;
-  float2* data = is_plane ? p.plane[blockIdx.y] : p.main[blockIdx.y];
+  const long bo = batch_bytes(p.bat);
+  if (bo < 0) return;
+  float2* data = byte_adv(is_plane ? p.plane[blockIdx.y] : p.main[blockIdx.y], bo);
   int b, c0;
   tile_bc<BLK>(tile, is_plane ? ((int)gridDim.x - p.nb_main) / g.ntc : p.nb_main / g.ntc, g.ntc, M, b, c0);
   float2* base = data + b * g.sb + (long)c0 * CS;
@@ -291,7 +294,9 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols_force(ColPass p, const fl
   const bool shared = blockIdx.y == 1;   // uniform
   const int b = tile / g.ntc;
   const int c0 = (tile - b * g.ntc) * M;
-  const long off = b * g.sb + c0;
+  const long bo = batch_bytes(p.bat);
+  if (bo < 0) return;
+  const long off = b * g.sb + c0 + bo / (long)sizeof(float2);
   float2* base = (is_plane ? p.plane[blockIdx.y] : p.main[blockIdx.y]) + off;
   const int tid = threadIdx.x;
 
@@ -523,12 +528,14 @@ __global__ __launch_bounds__(kThreads) void k_r2c_z(float* __restrict__ r0, floa
                                                      float* __restrict__ r2, float2* __restrict__ q0,
                                                      float2* __restrict__ q1, float2* __restrict__ q2,
                                                      const float2* __restrict__ twh,
-                                                     const float2* __restrict__ twn) {
+                                                     const float2* __restrict__ twn, BatchArg bat) {
   using G = ZGeom<N>;
   constexpr int H = G::H, L = G::L, ZP = G::ZP;
   __shared__ float2 lds[G::size];
-  float* r = blockIdx.y == 0 ? r0 : (blockIdx.y == 1 ? r1 : r2);
-  float2* q = blockIdx.y == 0 ? q0 : (blockIdx.y == 1 ? q1 : q2);
+  const long bo = batch_bytes(bat);
+  if (bo < 0) return;
+  float* r = byte_adv(blockIdx.y == 0 ? r0 : (blockIdx.y == 1 ? r1 : r2), bo);
+  float2* q = byte_adv(blockIdx.y == 0 ? q0 : (blockIdx.y == 1 ? q1 : q2), bo);
   const long l0 = (long)xcd_tile(blockIdx.x, gridDim.x) * L;
   float2* reg = reinterpret_cast<float2*>(r) + l0 * H;   // region: L*H complex = L*N floats
   copy16<L * H / 2>(reinterpret_cast<float4*>(lds), reinterpret_cast<const float4*>(reg));
@@ -618,10 +625,17 @@ template <int N>
 __global__ __launch_bounds__(kThreads) void k_c2r_z3(const float* __restrict__ r0, long fstride,
                                                       const float2* __restrict__ q0, long qstride,
                                                       float* __restrict__ out, const float2* __restrict__ twh,
-                                                      const float2* __restrict__ twn) {
+                                                      const float2* __restrict__ twn, BatchArg bat) {
   using G = Z3Geom<N>;
   constexpr int H = G::H, L = G::L, ZP = G::ZP;
   __shared__ float2 lds[G::size];
+  {
+    const long bo = batch_bytes(bat);
+    if (bo < 0) return;
+    r0 = byte_adv(r0, bo);
+    q0 = byte_adv(q0, bo);
+    out = byte_adv(out, bo);
+  }
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int row = tile / 3, f = tile - 3 * row;
   const long l0 = (long)row * L;
@@ -673,6 +687,7 @@ struct FusedArgs {
   const float2* in_main;   // input spectrum (forward-y transformed)
   const float2* in_nyq;
   FftTables t;
+  BatchArg bat;            // batched launches (k_fft_x_force): blockIdx.z selects the member
 };
 
 template <int N>
@@ -1094,7 +1109,9 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_force(FusedArgs a) {
   const ColGeom& g = mode ? a.gp : a.gm;
   int b, c0;
   tile_bc<true>(tile, mode ? ((int)gridDim.x - a.nb_main) / g.ntc : a.nb_main / g.ntc, g.ntc, M, b, c0);
-  const long off = b * g.sb + (long)c0 * 8;
+  const long bo = batch_bytes(a.bat);
+  if (bo < 0) return;
+  const long off = b * g.sb + (long)c0 * 8 + bo / (long)sizeof(float2);
   const int tid = threadIdx.x;
   const SpecOp& op = a.op;
   const FftTables& t = a.t;
@@ -1388,7 +1405,7 @@ inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
 template <int N, int DIR, bool BLK>
 void launch_cols(float2* const* dm, float2* const* dq, int nf, ColGeom gm, int nbm, ColGeom gp, int nbp,
-                 const float2* tw, hipStream_t s) {
+                 const float2* tw, hipStream_t s, const BatchArg& bat = BatchArg()) {
   constexpr int M = Cols<N>::M;
   ColPass p;
   for (int i = 0; i < 3; ++i) {
@@ -1401,20 +1418,21 @@ void launch_cols(float2* const* dm, float2* const* dq, int nf, ColGeom gm, int n
   p.gp = gp;
   p.nb_main = nbm * gm.ntc;
   p.ntiles = p.nb_main + nbp * gp.ntc;
-  dim3 grid(p.ntiles, nf);
+  p.bat = bat;
+  dim3 grid(p.ntiles, nf, bat.n);
   hipLaunchKernelGGL((k_fft_cols<N, M, DIR, BLK>), grid, dim3(kThreads), 0, s, p, tw);
 }
 
 // y pass over the main arrays and the Nyquist planes of nf fields
 template <int N, int DIR>
-void ypass(const FftTables& t, Field* f, int nf, hipStream_t s) {
+void ypass(const FftTables& t, Field* f, int nf, hipStream_t s, const BatchArg& bat = BatchArg()) {
   float2* dm[3];
   float2* dq[3];
   for (int i = 0; i < nf; ++i) { dm[i] = f[i].c(); dq[i] = f[i].q; }
   // main c[xb][y][kz][xi]: (b = xb, n = y, c = kz*8 + xi): sb = 4N^2, sn = 4N, ncols = 4N
   // Nyquist plane q[xb][y][xi]: (b = xb, n = y, c = xi): sb = 8N, sn = 8, ncols = 8
   launch_cols<N, DIR, false>(dm, dq, nf, ColGeom{4L * N * N, 4L * N, 4 * N, 0}, N / 8,
-                             ColGeom{8L * N, 8, 8, 0}, N / 8, t.tw_n, s);
+                             ColGeom{8L * N, 8, 8, 0}, N / 8, t.tw_n, s, bat);
 }
 
 template <int N, int DIR>
@@ -1429,19 +1447,19 @@ void xpass(const FftTables& t, Field* f, int nf, hipStream_t s) {
 }
 
 template <int N>
-void zr2c(const FftTables& t, Field* f, int nf, hipStream_t s) {
+void zr2c(const FftTables& t, Field* f, int nf, hipStream_t s, const BatchArg& bat = BatchArg()) {
   using G = ZGeom<N>;
-  dim3 grid((N * N) / G::L, nf);
+  dim3 grid((N * N) / G::L, nf, bat.n);
   hipLaunchKernelGGL((k_r2c_z<N>), grid, dim3(kThreads), 0, s, f[0].r, nf > 1 ? f[1].r : f[0].r,
                      nf > 2 ? f[2].r : f[0].r, f[0].q, nf > 1 ? f[1].q : f[0].q, nf > 2 ? f[2].q : f[0].q,
-                     t.tw_h, t.tw_n);
+                     t.tw_h, t.tw_n, bat);
 }
 
 template <int N>
-void zc2r3(const FftTables& t, const Field* f, float* out, hipStream_t s) {
-  dim3 grid(3 * (N * N) / Z3Geom<N>::L);
+void zc2r3(const FftTables& t, const Field* f, float* out, hipStream_t s, const BatchArg& bat = BatchArg()) {
+  dim3 grid(3 * (N * N) / Z3Geom<N>::L, 1, bat.n);
   hipLaunchKernelGGL((k_c2r_z3<N>), grid, dim3(kThreads), 0, s, f[0].r, (long)(f[1].r - f[0].r), f[0].q,
-                     (long)(f[1].q - f[0].q), out, t.tw_h, t.tw_n);
+                     (long)(f[1].q - f[0].q), out, t.tw_h, t.tw_n, bat);
 }
 
 template <int N>
@@ -1500,7 +1518,7 @@ void xfused(const FftTables& t, const Field& in, const SpecOp& op, hipStream_t s
 // k_fft_x_force, for N <= 32 (OP_FORCE, whole columns in registers) the
 // fused register pass.
 template <int N>
-void xforce(const FftTables& t, const Field& in, const SpecOp& op, hipStream_t s) {
+void xforce(const FftTables& t, const Field& in, const SpecOp& op, hipStream_t s, const BatchArg& bat = BatchArg()) {
   constexpr int M = Cols<N>::M;
   if constexpr (Split<N>::R2 == 1) {
     xfused<N>(t, in, op, s);
@@ -1517,7 +1535,8 @@ void xforce(const FftTables& t, const Field& in, const SpecOp& op, hipStream_t s
     a.park_main = nullptr;
     a.park_nyq = nullptr;
     a.pbasis = 0;
-    const dim3 grid(a.nb_main + a.gp.ntc);
+    a.bat = bat;
+    const dim3 grid(a.nb_main + a.gp.ntc, 1, bat.n);
     hipLaunchKernelGGL((k_fft_x_force<N, M>), grid, dim3(kThreads), 0, s, a);
   }
 }
@@ -1556,7 +1575,7 @@ void xforce_t(const FftTables& t, Field* f, const SpecOp& op, hipStream_t s) {
 }
 
 template <int N>
-void yforce(const FftTables& t, Field* f, hipStream_t s) {
+void yforce(const FftTables& t, Field* f, hipStream_t s, const BatchArg& bat = BatchArg()) {
   if constexpr (Split<N>::R2 > 1) {
     constexpr int M = Cols<N>::M;
     ColPass p;
@@ -1569,7 +1588,8 @@ void yforce(const FftTables& t, Field* f, hipStream_t s) {
     p.gm = ColGeom{4L * N * N, 4L * N, 4 * N, cdiv(4 * N, M)};
     p.gp = ColGeom{8L * N, 8, 8, cdiv(8, M)};
     p.nb_main = (N / 8) * p.gm.ntc;
-    const dim3 grid(p.nb_main + (N / 8) * p.gp.ntc, 2);
+    p.bat = bat;
+    const dim3 grid(p.nb_main + (N / 8) * p.gp.ntc, 2, bat.n);
     hipLaunchKernelGGL((k_fft_cols_force<N, M>), grid, dim3(kThreads), 0, s, p, t.tw_n, t.dxy, t.dz);
   }
 }
@@ -1603,17 +1623,17 @@ void fft_r2c_zy(const FftTables& t, Field* f, int nf, hipStream_t s) {
   });
 }
 
-void fft_z_r2c(const FftTables& t, Field* f, int nf, hipStream_t s) {
+void fft_z_r2c(const FftTables& t, Field* f, int nf, hipStream_t s, const BatchArg& bat) {
   by3(f, nf, [&](Field* g, int k) {
-#define CALL(N) zr2c<N>(t, g, k, s)
+#define CALL(N) zr2c<N>(t, g, k, s, bat)
     PM_FFT_SWITCH(t.n, CALL)
 #undef CALL
   });
 }
 
-void fft_y(const FftTables& t, Field* f, int nf, int dir, hipStream_t s) {
+void fft_y(const FftTables& t, Field* f, int nf, int dir, hipStream_t s, const BatchArg& bat) {
   by3(f, nf, [&](Field* g, int k) {
-#define CALL(N) (dir < 0 ? ypass<N, -1>(t, g, k, s) : ypass<N, 1>(t, g, k, s))
+#define CALL(N) (dir < 0 ? ypass<N, -1>(t, g, k, s, bat) : ypass<N, 1>(t, g, k, s, bat))
     PM_FFT_SWITCH(t.n, CALL)
 #undef CALL
   });
@@ -1649,8 +1669,8 @@ void fft_x_fused(const FftTables& t, const Field& in, const SpecOp& op, hipStrea
 #undef CALL
 }
 
-void fft_x_force(const FftTables& t, const Field& in, const SpecOp& op, hipStream_t s) {
-#define CALL(N) xforce<N>(t, in, op, s)
+void fft_x_force(const FftTables& t, const Field& in, const SpecOp& op, hipStream_t s, const BatchArg& bat) {
+#define CALL(N) xforce<N>(t, in, op, s, bat)
   PM_FFT_SWITCH(t.n, CALL)
 #undef CALL
 }
@@ -1665,14 +1685,14 @@ void fft_x_force_t(const FftTables& t, Field* f, const SpecOp& op, hipStream_t s
 #undef CALL
 }
 
-void fft_y_force(const FftTables& t, Field* f, hipStream_t s) {
-#define CALL(N) yforce<N>(t, f, s)
+void fft_y_force(const FftTables& t, Field* f, hipStream_t s, const BatchArg& bat) {
+#define CALL(N) yforce<N>(t, f, s, bat)
   PM_FFT_SWITCH(t.n, CALL)
 #undef CALL
 }
 
-void fft_z_c2r_interleaved3(const FftTables& t, const Field* f, float* out, hipStream_t s) {
-#define CALL(N) zc2r3<N>(t, f, out, s)
+void fft_z_c2r_interleaved3(const FftTables& t, const Field* f, float* out, hipStream_t s, const BatchArg& bat) {
+#define CALL(N) zc2r3<N>(t, f, out, s, bat)
   PM_FFT_SWITCH(t.n, CALL)
 #undef CALL
 }

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 
+#include "batch.h"
 #include "layout.h"
 
 namespace pmk {
@@ -39,6 +40,8 @@ struct LptParticleArgs {
   int has_s2 = 0;
   float* pos = nullptr;
   float* mom = nullptr;
+  float* psi1 = nullptr;        // optional: B s1 and B s2 by particle, [np][3] (the COLA frame)
+  float* psi2 = nullptr;
 };
 
 struct ScatterArgs {
@@ -52,6 +55,7 @@ struct ScatterArgs {
   float* pos_out = nullptr;
   float* mom_out = nullptr;
   uint32_t* id_out = nullptr;
+  BatchArg bat;                    // batched: every pointer is a workspace pointer of member 0
 };
 
 enum ReadoutFlags : int {
@@ -62,6 +66,9 @@ enum ReadoutFlags : int {
   RO_FORCE_BYID = 16,    // write F to force_out at the particle id
   RO_KEYS = 32,          // tile key and rank of the new position
   RO_CKPT = 64,          // write x and p (after kick_a) to ckpt_x/ckpt_p at the id
+  RO_TO_ALT = 128,       // write x, p and the id to pos_alt/mom_alt/id_alt at the same (sorted) index
+  RO_COLA = 256,         // LPT frame: kick with F - c1 psi1 - c2 psi2, drift adds dD1 psi1 + dD2 psi2
+  RO_COLA_OUT = 512,     // momentum written by id is p + q1 psi1 + q2 psi2 (cola_out)
 };
 
 struct ReadoutArgs {
@@ -89,6 +96,21 @@ struct ReadoutArgs {
   const uint32_t* step_i = nullptr;
   float* const* ckpt_base = nullptr;
   long ckpt_stride = 0;
+  // RO_COLA: the frame's fields by particle id and its factors {c1, c2, dD1,
+  // dD2}, per step from cola_steps[*step_i] when steps is set, else `cola`
+  const float* psi1 = nullptr;
+  const float* psi2 = nullptr;
+  const float4* cola_steps = nullptr;
+  float4 cola = {0.f, 0.f, 0.f, 0.f};
+  float2 cola_out = {0.f, 0.f};
+  // RO_TO_ALT destinations
+  float* pos_alt = nullptr;
+  float* mom_alt = nullptr;
+  uint32_t* id_alt = nullptr;
+  // Batched (bat.d != null): every pointer above is a workspace pointer of
+  // member 0; the factors and checkpoint pointers come from the member's
+  // descriptor (kick_close, kick_open, drift; RO_CKPT if it asks for it).
+  BatchArg bat;
 };
 
 struct PowerArgs {
@@ -109,15 +131,16 @@ void launch_noise(uint64_t seed, int n_side, float* out, bool blocked, hipStream
 void launch_relayout(const float* in, float* out, int n_side, bool to_blocked, hipStream_t s);
 void launch_lpt_delta2(float* const* phi6, long n, float* out, hipStream_t s);
 void launch_lpt_particles(const LptParticleArgs& a, hipStream_t s);
-void launch_fill_u32(uint32_t* p, long n, uint32_t v, hipStream_t s);
+void launch_fill_u32(uint32_t* p, long n, uint32_t v, hipStream_t s, const BatchArg& bat = BatchArg());
 void launch_keys(const float* pos, long np, const TileGeom& g, uint32_t* key, uint32_t* rank, uint32_t* count,
                  hipStream_t s);
 long scan_scratch_words(long n);
-void launch_scan(const uint32_t* count, long n, uint32_t* off, uint32_t* bsum, hipStream_t s);
+void launch_scan(const uint32_t* count, long n, uint32_t* off, uint32_t* bsum, hipStream_t s,
+                 const BatchArg& bat = BatchArg());
 void launch_scatter(const ScatterArgs& a, hipStream_t s);
 // std_layout: write [x][y][z] instead of the x-blocked layout
 void launch_paint(const float* pos_sorted, const uint32_t* off, const TileGeom& g, float* out, float scale,
-                  float offset, bool std_layout, hipStream_t s);
+                  float offset, bool std_layout, hipStream_t s, const BatchArg& bat = BatchArg());
 void launch_readout(const ReadoutArgs& a, hipStream_t s);
 // *ctr += 1 (the step counter of a run's device-side step loop)
 void launch_step_inc(uint32_t* ctr, hipStream_t s);
@@ -129,6 +152,10 @@ void launch_paint_weighted(const float* pos_sorted, const uint32_t* id_sorted, c
                            const float* wts, int comp, float k, const uint32_t* maxbits, float* out, hipStream_t s);
 void launch_kick_drift(float* pos, float* mom, const float* f, long np, float kick, float drift, float nmesh,
                        hipStream_t s);
+// mom[j] += u1 psi1[id[j]] + u2 psi2[id[j]] over np sorted particles (the
+// change between the full and the LPT-frame momentum)
+void launch_frame_shift(float* mom, const uint32_t* id, const float* psi1, const float* psi2, long np, float u1,
+                        float u2, hipStream_t s);
 void launch_spec_to_numpy(const float2* c, const float2* q, float2* out, int n, float scale, hipStream_t s);
 void launch_spec_from_numpy(const float2* in, float2* c, float2* q, int n, float scale, hipStream_t s);
 void launch_scale(float* p, long n, float v, hipStream_t s);

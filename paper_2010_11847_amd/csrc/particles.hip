@@ -77,6 +77,10 @@ __global__ void k_lpt_particles(LptParticleArgs a) {
       const float dx = a.cx1 * s1 + a.cx2 * s2;
       x[d] = wrap_pos((float)(a.ratio * q[d]) + a.shift + dx, a.nmesh);
       p[d] = a.cp1 * s1 + a.cp2 * s2;
+      if (a.psi1) {
+        a.psi1[3 * i + d] = (float)a.ratio * s1;
+        a.psi2[3 * i + d] = (float)a.ratio * s2;
+      }
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) a.pos[3 * i + d] = x[d];
@@ -86,7 +90,10 @@ __global__ void k_lpt_particles(LptParticleArgs a) {
 }
 
 // ---- counting sort -------------------------------------------------------------
-__global__ void k_fill_u32(uint32_t* __restrict__ p, long n, uint32_t v) {
+__global__ void k_fill_u32(uint32_t* __restrict__ p, long n, uint32_t v, BatchArg bat) {
+  const long bo = batch_bytes(bat);
+  if (bo < 0) return;
+  p = byte_adv(p, bo);
   const long stride = (long)gridDim.x * blockDim.x;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
@@ -133,8 +140,14 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
 }
 
 __global__ __launch_bounds__(kThreads) void k_scan_local(const uint32_t* __restrict__ cnt, long n,
-                                                         uint32_t* __restrict__ off, uint32_t* __restrict__ bsum) {
+                                                         uint32_t* __restrict__ off, uint32_t* __restrict__ bsum,
+                                                         BatchArg bat) {
   __shared__ uint32_t sh[kThreads];
+  const long bo = batch_bytes(bat);
+  if (bo < 0) return;
+  cnt = byte_adv(cnt, bo);
+  off = byte_adv(off, bo);
+  bsum = byte_adv(bsum, bo);
   const long base = (long)blockIdx.x * kScanBlock + (long)threadIdx.x * kScanItems;
   uint32_t v[kScanItems];
   uint32_t s = 0;
@@ -153,8 +166,11 @@ __global__ __launch_bounds__(kThreads) void k_scan_local(const uint32_t* __restr
   if (threadIdx.x == 0) bsum[blockIdx.x] = total;
 }
 
-__global__ __launch_bounds__(kThreads) void k_scan_top(uint32_t* __restrict__ bsum, int nb) {
+__global__ __launch_bounds__(kThreads) void k_scan_top(uint32_t* __restrict__ bsum, int nb, BatchArg bat) {
   __shared__ uint32_t sh[kThreads];
+  const long bo = batch_bytes(bat);
+  if (bo < 0) return;
+  bsum = byte_adv(bsum, bo);
   uint32_t carry = 0;
   for (int c0 = 0; c0 < nb; c0 += kThreads) {
     const int i = c0 + threadIdx.x;
@@ -168,7 +184,11 @@ __global__ __launch_bounds__(kThreads) void k_scan_top(uint32_t* __restrict__ bs
 }
 
 __global__ __launch_bounds__(kThreads) void k_scan_add(uint32_t* __restrict__ off, long n,
-                                                       const uint32_t* __restrict__ bsum, int nb) {
+                                                       const uint32_t* __restrict__ bsum, int nb, BatchArg bat) {
+  const long bo = batch_bytes(bat);
+  if (bo < 0) return;
+  off = byte_adv(off, bo);
+  bsum = byte_adv(bsum, bo);
   const long base = (long)blockIdx.x * kScanBlock;
   const uint32_t add = bsum[blockIdx.x];
   for (int j = threadIdx.x; j < kScanBlock; j += kThreads)
@@ -180,6 +200,19 @@ __global__ __launch_bounds__(kThreads) void k_scan_add(uint32_t* __restrict__ of
 // dependent offset lookup, and pinned: left to the compiler, the state
 // loads follow the offset load and add a third round trip to the chain.
 __global__ void k_scatter(ScatterArgs a) {
+  if (a.bat.d) {
+    const long bo = batch_bytes(a.bat);
+    if (bo < 0) return;
+    a.pos = byte_adv(a.pos, bo);
+    a.mom = byte_adv(a.mom, bo);
+    a.id = byte_adv(a.id, bo);
+    a.key = byte_adv(a.key, bo);
+    a.rank = byte_adv(a.rank, bo);
+    a.off = byte_adv(a.off, bo);
+    a.pos_out = byte_adv(a.pos_out, bo);
+    a.mom_out = byte_adv(a.mom_out, bo);
+    a.id_out = byte_adv(a.id_out, bo);
+  }
   const long stride = (long)gridDim.x * blockDim.x;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < a.np; i += stride) {
     const uint32_t key = a.key[i], rank = a.rank[i];
@@ -235,15 +268,25 @@ constexpr int kPaintThreads = 512;
 template <bool STD, bool WT>
 __global__ __launch_bounds__(kPaintThreads) void k_paint(const float* __restrict__ pos, const uint32_t* __restrict__ off,
                                                     TileGeom g, float* __restrict__ out, float scale, float offset,
-                                                    PaintWeights pw) {
-  __shared__ unsigned long long acc[kTileCells];
+                                                    PaintWeights pw, BatchArg bat) {
+  __shared__ __align__(16) unsigned long long acc[kTileCells];
   __shared__ RangeTable rt;
+  {
+    const long bo = batch_bytes(bat);
+    if (bo < 0) return;
+    pos = byte_adv(pos, bo);
+    off = byte_adv(off, bo);
+    out = byte_adv(out, bo);
+  }
   const int TX = g.tx, TY = g.ty, TZ = g.tz, n = g.n;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   int tx, ty, tz;
   tile_coords(tile, g, tx, ty, tz);
   const int ox = tx * TX, oy = ty * TY, oz = tz * TZ;
-  for (int c = threadIdx.x; c < tile_cells(g); c += kPaintThreads) acc[c] = 0ull;
+  {   // zero the accumulator with 16-byte LDS writes
+    uint4* a4 = reinterpret_cast<uint4*>(acc);
+    for (int c = threadIdx.x; c < (tile_cells(g) >> 1); c += kPaintThreads) a4[c] = make_uint4(0u, 0u, 0u, 0u);
+  }
   float S = 1.f;   // WT: fixed-point scale, a power of two
   if (WT) {
     const float mx = __uint_as_float(*pw.maxbits) * fabsf(pw.k);
@@ -328,6 +371,24 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint(const float* __restrict
     }
   }
   __syncthreads();
+  auto cell_value = [&](int cx, int cy, int cz) {
+    const unsigned long long v = acc[tile_li(cx, cy, cz, g)];
+    const double rho = WT ? (double)(long long)v / (double)S : (double)v * 0x1p-31;
+    return (float)(rho * (double)scale + (double)offset);
+  };
+  if (!STD && (TX & 7) == 0) {
+    // whole 8-cell x runs: four consecutive x of one (y, z) per thread, one
+    // 16-byte store each (the walk's x%8 is fastest, so c4 * 4 starts at
+    // x%8 = 0 or 4 and the address is 16-byte aligned)
+    for (int c4 = threadIdx.x; c4 < (store_walk_len(g) >> 2); c4 += kPaintThreads) {
+      int cx, cy, cz;
+      store_walk(c4 << 2, g, cx, cy, cz);
+      const float4 v = make_float4(cell_value(cx, cy, cz), cell_value(cx + 1, cy, cz), cell_value(cx + 2, cy, cz),
+                                   cell_value(cx + 3, cy, cz));
+      *reinterpret_cast<float4*>(out + blk_real(ox + cx, oy + cy, oz + cz, n)) = v;
+    }
+    return;
+  }
   for (int c = threadIdx.x; c < store_walk_len(g); c += kPaintThreads) {
     int cx, cy, cz;
     store_walk(c, g, cx, cy, cz);
@@ -379,6 +440,10 @@ __device__ __forceinline__ uint32_t slot_key(int slot, int rx, int ry, int rz, c
 constexpr int kReadoutPPT = 1;
 constexpr int kSlots = 27 * 8;
 
+// EXT: the batched, LPT-frame (RO_COLA, RO_COLA_OUT) and RO_TO_ALT paths;
+// the plain instantiation compiles without them (fewer registers on the
+// path of every single-simulation step).
+template <bool EXT>
 __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
   constexpr int PPT = kReadoutPPT;
   constexpr int kWaves = kThreads / 64;
@@ -392,12 +457,36 @@ __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
   const int lane = threadIdx.x & 63;
   float kick_a = a.kick_a, kick_b = a.kick_b, drift = a.drift;
   float *ckpt_x = a.ckpt_x, *ckpt_p = a.ckpt_p;
+  if (!EXT) a.flags &= ~(RO_COLA | RO_COLA_OUT | RO_TO_ALT);
+  if (EXT && a.bat.d) {   // uniform: this block's member, its factors and checkpoints
+    const long bo = batch_bytes(a.bat);
+    if (bo < 0) return;
+    const pm_req_desc& dsc = a.bat.d[blockIdx.z];
+    a.pos = byte_adv(a.pos, bo);
+    a.mom = byte_adv(a.mom, bo);
+    a.id = byte_adv(a.id, bo);
+    a.fi = byte_adv(a.fi, bo);
+    a.key_out = byte_adv(a.key_out, bo);
+    a.rank_out = byte_adv(a.rank_out, bo);
+    a.count = byte_adv(a.count, bo);
+    a.pos_alt = byte_adv(a.pos_alt, bo);
+    a.mom_alt = byte_adv(a.mom_alt, bo);
+    a.id_alt = byte_adv(a.id_alt, bo);
+    kick_a = dsc.kick_close;
+    kick_b = dsc.kick_open;
+    drift = dsc.drift;
+    ckpt_x = dsc.ckpt_x;
+    ckpt_p = dsc.ckpt_p;
+    a.flags = (a.flags & ~RO_CKPT) | ((dsc.flags & PM_REQ_CKPT) && ckpt_x && ckpt_p ? RO_CKPT : 0);
+  }
+  float4 cola = a.cola;
   if (a.steps) {   // uniform: the factors of step *step_i
     const uint32_t si = *a.step_i;
     const float4 f = a.steps[si];
     kick_a = f.x;
     kick_b = f.y;
     drift = f.z;
+    if (EXT && a.cola_steps) cola = a.cola_steps[si];
     if (a.flags & RO_CKPT) {
       ckpt_x = *a.ckpt_base + 2 * (long)si * a.ckpt_stride;
       ckpt_p = ckpt_x + a.ckpt_stride;
@@ -426,7 +515,8 @@ __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
       for (int d = 0; d < 3; ++d) p[u][d] = a.mom[3 * jc + d];
     }
     // ids are needed only for writes by id (not on ordinary steps)
-    id[u] = (a.id && (a.flags & (RO_FORCE_BYID | RO_XP_BYID | RO_CKPT))) ? a.id[jc] : (uint32_t)jc;
+    id[u] = (a.id && (a.flags & (RO_FORCE_BYID | RO_XP_BYID | RO_CKPT | RO_TO_ALT | RO_COLA))) ? a.id[jc]
+                                                                                        : (uint32_t)jc;
   }
   // all 8 x PPT corner loads first, pinned, then the weighted sums
   float cv[PPT][8][3], wgt[PPT][8];
@@ -466,12 +556,28 @@ __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
       for (int d = 0; d < 3; ++d) F[u][d] += wgt[u][c8] * cv[u][c8][d];
   }
   const float nf = (float)n;
+  // LPT frame: the fields of the particle (by id; loaded after the corner
+  // gathers so that those go first)
+  float ps1[PPT][3], ps2[PPT][3];
+  if (a.flags & RO_COLA) {
+#pragma unroll
+    for (int u = 0; u < PPT; ++u)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        ps1[u][d] = a.psi1[3 * (long)id[u] + d];
+        ps2[u][d] = a.psi2[3 * (long)id[u] + d];
+      }
+  }
 #pragma unroll
   for (int u = 0; u < PPT; ++u) {
     const long j = jj[u];
     if (valid[u] && (a.flags & RO_FORCE_BYID)) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) a.force_out[3 * (long)id[u] + d] = F[u][d];
+    }
+    if (a.flags & RO_COLA) {   // residual force from the LPT trajectory
+#pragma unroll
+      for (int d = 0; d < 3; ++d) F[u][d] -= cola.x * ps1[u][d] + cola.y * ps2[u][d];
     }
     if (a.flags & RO_KICK) {
 #pragma unroll
@@ -489,8 +595,14 @@ __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
       for (int d = 0; d < 3; ++d) p[u][d] += F[u][d] * kick_b;
     }
     if (a.flags & RO_DRIFT) {
+      if (a.flags & RO_COLA) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) x[u][d] = wrap_pos(x[u][d] + p[u][d] * drift, nf);
+        for (int d = 0; d < 3; ++d)
+          x[u][d] = wrap_pos(x[u][d] + p[u][d] * drift + cola.z * ps1[u][d] + cola.w * ps2[u][d], nf);
+      } else {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) x[u][d] = wrap_pos(x[u][d] + p[u][d] * drift, nf);
+      }
     }
     if (!valid[u]) continue;
     if (a.flags & RO_WRITE_SORTED) {
@@ -501,11 +613,24 @@ __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
         for (int d = 0; d < 3; ++d) a.mom[3 * j + d] = p[u][d];
       }
     }
+    if (a.flags & RO_TO_ALT) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) a.pos_alt[3 * j + d] = x[u][d];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) a.mom_alt[3 * j + d] = p[u][d];
+      a.id_alt[j] = id[u];
+    }
     if (a.flags & RO_XP_BYID) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) a.pos_out[3 * (long)id[u] + d] = x[u][d];
+      if (a.flags & RO_COLA_OUT) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) a.mom_out[3 * (long)id[u] + d] = p[u][d];
+        for (int d = 0; d < 3; ++d)
+          a.mom_out[3 * (long)id[u] + d] = p[u][d] + a.cola_out.x * ps1[u][d] + a.cola_out.y * ps2[u][d];
+      } else {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) a.mom_out[3 * (long)id[u] + d] = p[u][d];
+      }
     }
   }
   if (!keys) return;
@@ -552,6 +677,17 @@ __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
 #pragma unroll
   for (int u = 0; u < PPT; ++u)
     if (valid[u]) a.rank_out[jj[u]] = rank[u] + (slot[u] >= 0 ? sbase[slot[u]] : 0u);
+}
+
+__global__ void k_frame_shift(float* __restrict__ mom, const uint32_t* __restrict__ id,
+                              const float* __restrict__ psi1, const float* __restrict__ psi2, long np, float u1,
+                              float u2) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long j = (long)blockIdx.x * blockDim.x + threadIdx.x; j < np; j += stride) {
+    const long i = id[j];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) mom[3 * j + d] += u1 * psi1[3 * i + d] + u2 * psi2[3 * i + d];
+  }
 }
 
 __global__ void k_step_inc(uint32_t* ctr) {
@@ -738,8 +874,8 @@ void launch_lpt_particles(const LptParticleArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_lpt_particles, dim3(grid_for(n3)), dim3(kThreads), 0, s, a);
 }
 
-void launch_fill_u32(uint32_t* p, long n, uint32_t v, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n)), dim3(kThreads), 0, s, p, n, v);
+void launch_fill_u32(uint32_t* p, long n, uint32_t v, hipStream_t s, const BatchArg& bat) {
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n), 1, bat.n), dim3(kThreads), 0, s, p, n, v, bat);
 }
 
 void launch_keys(const float* pos, long np, const TileGeom& g, uint32_t* key, uint32_t* rank, uint32_t* count,
@@ -750,32 +886,33 @@ void launch_keys(const float* pos, long np, const TileGeom& g, uint32_t* key, ui
 
 long scan_scratch_words(long n) { return (n + kScanBlock - 1) / kScanBlock + 1; }
 
-void launch_scan(const uint32_t* count, long n, uint32_t* off, uint32_t* bsum, hipStream_t s) {
+void launch_scan(const uint32_t* count, long n, uint32_t* off, uint32_t* bsum, hipStream_t s, const BatchArg& bat) {
   const int nb = (int)((n + kScanBlock - 1) / kScanBlock);
-  hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(kThreads), 0, s, count, n, off, bsum);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kThreads), 0, s, bsum, nb);
-  hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kThreads), 0, s, off, n, bsum, nb);
+  hipLaunchKernelGGL(k_scan_local, dim3(nb, 1, bat.n), dim3(kThreads), 0, s, count, n, off, bsum, bat);
+  hipLaunchKernelGGL(k_scan_top, dim3(1, 1, bat.n), dim3(kThreads), 0, s, bsum, nb, bat);
+  hipLaunchKernelGGL(k_scan_add, dim3(nb, 1, bat.n), dim3(kThreads), 0, s, off, n, bsum, nb, bat);
 }
 
 void launch_scatter(const ScatterArgs& a, hipStream_t s) {
   // one particle per thread: the key -> offset -> store chain of each
   // particle is latency bound, so many short waves overlap it best
-  hipLaunchKernelGGL(k_scatter, dim3(grid_for(a.np, kThreads, 1 << 30)), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL(k_scatter, dim3(grid_for(a.np, kThreads, 1 << 30), 1, a.bat.n), dim3(kThreads), 0, s, a);
 }
 
 void launch_paint(const float* pos_sorted, const uint32_t* off, const TileGeom& g, float* out, float scale,
-                  float offset, bool std_layout, hipStream_t s) {
+                  float offset, bool std_layout, hipStream_t s, const BatchArg& bat) {
   const PaintWeights pw;
+  const dim3 grid(g.ntiles, 1, bat.n);
   if (std_layout)
-    hipLaunchKernelGGL((k_paint<true, false>), dim3(g.ntiles), dim3(kPaintThreads), 0, s, pos_sorted, off, g, out, scale,
-                       offset, pw);
+    hipLaunchKernelGGL((k_paint<true, false>), grid, dim3(kPaintThreads), 0, s, pos_sorted, off, g, out, scale,
+                       offset, pw, bat);
   else
-    hipLaunchKernelGGL((k_paint<false, false>), dim3(g.ntiles), dim3(kPaintThreads), 0, s, pos_sorted, off, g, out,
-                       scale, offset, pw);
+    hipLaunchKernelGGL((k_paint<false, false>), grid, dim3(kPaintThreads), 0, s, pos_sorted, off, g, out,
+                       scale, offset, pw, bat);
 }
 
 void launch_absmax(const float* v, long n, uint32_t* bits, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kThreads), 0, s, bits, 1L, 0u);
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kThreads), 0, s, bits, 1L, 0u, BatchArg());
   hipLaunchKernelGGL(k_absmax, dim3(grid_for(n, kThreads, 4096)), dim3(kThreads), 0, s, v, n, bits);
 }
 
@@ -788,13 +925,22 @@ void launch_paint_weighted(const float* pos_sorted, const uint32_t* id_sorted, c
   pw.k = k;
   pw.maxbits = maxbits;
   hipLaunchKernelGGL((k_paint<false, true>), dim3(g.ntiles), dim3(kPaintThreads), 0, s, pos_sorted, off, g, out, 1.f,
-                     0.f, pw);
+                     0.f, pw, BatchArg());
 }
 
 void launch_readout(const ReadoutArgs& a, hipStream_t s) {
   const long per = (long)kThreads * kReadoutPPT;
   const int grid = (int)((a.np + per - 1) / per);
-  hipLaunchKernelGGL(k_readout, dim3(grid), dim3(kThreads), 0, s, a);
+  const bool ext = a.bat.d || (a.flags & (RO_COLA | RO_COLA_OUT | RO_TO_ALT));
+  if (ext)
+    hipLaunchKernelGGL(k_readout<true>, dim3(grid, 1, a.bat.n), dim3(kThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_readout<false>, dim3(grid), dim3(kThreads), 0, s, a);
+}
+
+void launch_frame_shift(float* mom, const uint32_t* id, const float* psi1, const float* psi2, long np, float u1,
+                        float u2, hipStream_t s) {
+  hipLaunchKernelGGL(k_frame_shift, dim3(grid_for(np)), dim3(kThreads), 0, s, mom, id, psi1, psi2, np, u1, u2);
 }
 
 void launch_step_inc(uint32_t* ctr, hipStream_t s) {

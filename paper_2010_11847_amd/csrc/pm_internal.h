@@ -8,6 +8,7 @@
 #include <string>
 #include <vector>
 
+#include "batch.h"
 #include "layout.h"
 #include "pm.h"
 
@@ -93,26 +94,30 @@ void fft_x_fused(const FftTables& t, const Field& in, const SpecOp& op, hipStrea
 // Green's function, inverse x transforms into op.out_* (out[0] may alias
 // `in`).  N >= 64 takes OP_FORCE_XS (out[0] = F_x, out[1] = the factor F_y
 // and F_z share), smaller meshes OP_FORCE (three components).
-void fft_x_force(const FftTables& t, const Field& in, const SpecOp& op, hipStream_t s);
+// Batched launches (bat.d != null) cover every member of a plan; they need
+// N >= 64, as do the batched forms of the passes below.
+void fft_x_force(const FftTables& t, const Field& in, const SpecOp& op, hipStream_t s,
+                 const BatchArg& bat = BatchArg());
 // Inverse y pass of the three force meshes after an OP_FORCE_XS x pass:
 // f[0] holds F_x, f[2] the shared factor i g X.  f[2] becomes F_z times
 // D(w_z) in place and f[1] receives F_y = transform of D(w_y) i g X; one
 // read of the shared factor feeds both.  N >= 64.
-void fft_y_force(const FftTables& t, Field* f, hipStream_t s);
+void fft_y_force(const FftTables& t, Field* f, hipStream_t s, const BatchArg& bat = BatchArg());
 // x pass of the transposed force (OP_FORCE_T: op.scale, deconv, split) over
 // the forward-(z, y) spectra f[0..2] of its x, y, z inputs; the result (the
 // fan-in, inverse-x transformed) replaces f[0]; below 64^3 the other two
 // inputs may be overwritten as well.
 void fft_x_force_t(const FftTables& t, Field* f, const SpecOp& op, hipStream_t s);
 // Single passes (the composites above call these).
-void fft_z_r2c(const FftTables& t, Field* f, int nf, hipStream_t s);
-void fft_y(const FftTables& t, Field* f, int nf, int dir, hipStream_t s);
+void fft_z_r2c(const FftTables& t, Field* f, int nf, hipStream_t s, const BatchArg& bat = BatchArg());
+void fft_y(const FftTables& t, Field* f, int nf, int dir, hipStream_t s, const BatchArg& bat = BatchArg());
 void fft_z_c2r(const FftTables& t, Field* f, int nf, hipStream_t s);
 // z pass of three fields written as one interleaved real mesh
 // out[x/8][y][z][x%8][3] (the force meshes the particle readout gathers from).
 // The three fields must be equally spaced in memory (f[2] - f[1] == f[1] - f[0]
 // for both the arrays and the Nyquist planes), as the workspace meshes are.
-void fft_z_c2r_interleaved3(const FftTables& t, const Field* f, float* out, hipStream_t s);
+void fft_z_c2r_interleaved3(const FftTables& t, const Field* f, float* out, hipStream_t s,
+                            const BatchArg& bat = BatchArg());
 // Inverse: y pass then z pass (complex + Nyquist plane -> real), unnormalised.
 void fft_c2r_yz(const FftTables& t, Field* f, int nf, hipStream_t s);
 // Plain inverse x pass (complex, in place).

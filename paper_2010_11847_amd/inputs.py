@@ -25,6 +25,10 @@ SPLIT_NONE = 0
 SPLIT_LONG = 1
 SPLIT_SHORT = 2
 
+INT_FASTPM = 0      # FastPM kick/drift factors
+INT_LEAPFROG = 1    # plain leapfrog factors
+INT_COLA = 2        # plain leapfrog in the LPT frame
+
 
 @dataclass(frozen=True)
 class Cosmology:
@@ -62,6 +66,7 @@ class Workload:
     split_mode: int = SPLIT_NONE
     lattice_shift: float = 0.0   # particle lattice offset from mesh nodes, in cells
     pyramid_levels: int = 0      # 0: single-grid force; f: two-level pyramid force, grid n_mesh / 2^f
+    integrator: int = INT_FASTPM
 
     @property
     def n_particles(self) -> int:

@@ -4,22 +4,31 @@ Requests (forward, or forward + gradient of a chi^2 loss on the final
 density) of different shapes arrive over time.  The loop
 
 * admits a queued request as soon as a slot of its shape class is free and
-  its HBM footprint fits in the budget (requests of other classes are not
+  the HBM it needs fits in the budget.  Each shape class runs on one batch
+  plan of the library (``pm_batch_*``): its workspace, all slots of the
+  class, is charged to the budget when the plan is created and returned
+  when an idle plan is dropped to make room for another class; each
+  request is charged its own arrays.  Requests of other classes are not
   blocked by one that does not fit yet; a request larger than the whole
-  budget is rejected);
-* keeps every admitted request's particle and mesh state on the device (one
-  library context, i.e. one workspace, per slot, reused across requests);
-* advances every active request by one KDK step per tick, each slot on its
-  own HIP stream, so the kernels of different requests overlap on the GPU
-  and new requests join while others are mid-run;
+  budget is rejected;
+* keeps every admitted request's particle and mesh state on the device, in
+  its slot of the class's plan;
+* advances all running requests of a class with one batched step (every
+  kernel of a KDK step launched once for the whole class, a captured graph),
+  each class on its own HIP stream so that classes overlap on the GPU, and
+  keeps at most ``depth`` batched steps of a class in flight so that a new
+  request joins the next step instead of queueing behind a backlog;
 * retires a request when its completion event has fired and records the
   latency from arrival to result ready.
 
 The scheduling policy is host logic (``Scheduler``) and is unit-tested on
-the CPU with a fake executor; ``GpuExecutor`` drives the HIP library.
+the CPU with a fake executor; ``BatchedExecutor`` drives the HIP library's
+batch plans and ``GpuExecutor`` runs one context per request (the FIFO
+baseline, one request at a time).
 """
 from __future__ import annotations
 
+import collections
 import heapq
 import math
 import time
@@ -48,8 +57,10 @@ class SimRequest:
     sigma: float = 0.1            # chi^2 noise level (with_grad)
 
     @property
-    def shape_class(self) -> Tuple[int, int, float, bool]:
-        return (self.n_part, self.n_mesh, self.box_size, self.with_grad)
+    def shape_class(self) -> Tuple[int, int, float]:
+        """Requests of one shape class share a batch plan (forward and
+        forward + gradient alike: the adjoint runs on the request's slot)."""
+        return (self.n_part, self.n_mesh, self.box_size)
 
     def workload(self, cosmo: Optional[Cosmology] = None) -> Workload:
         return Workload(f"req{self.rid}", self.box_size, self.n_mesh, self.n_part, self.seed,
@@ -91,16 +102,22 @@ def poisson_trace(n: int, rate: float, seed: int, mix=None, max_steps: int = 10,
     return out
 
 
-def footprint_bytes(req: SimRequest, workspace_bytes: int) -> int:
-    """HBM held by one admitted request: the library workspace plus its own
-    device arrays (noise, positions, momenta, final density; with the
-    gradient also the checkpoints, target, cotangents and noise gradient)."""
+def request_bytes(req: SimRequest) -> int:
+    """HBM of a request's own device arrays: noise, positions, momenta, final
+    density; with the gradient also the checkpoints, the target, the density
+    cotangent, the position/momentum cotangents and the noise gradient."""
     np3 = req.n_part ** 3
     ng3 = req.n_mesh ** 3
-    b = workspace_bytes + 4 * np3 + 2 * 12 * np3 + 4 * ng3
+    b = 4 * np3 + 2 * 12 * np3 + 4 * ng3
     if req.with_grad:
-        b += (req.n_steps + 1) * 2 * 12 * np3 + 4 * ng3 + 2 * 12 * np3 + 4 * np3 + 4 * ng3
+        b += (req.n_steps + 1) * 2 * 12 * np3 + 4 * ng3 + 4 * ng3 + 2 * 12 * np3 + 4 * np3
     return b
+
+
+def footprint_bytes(req: SimRequest, workspace_bytes: int) -> int:
+    """HBM held by one request run on a context of its own: the library
+    workspace plus the request's arrays."""
+    return workspace_bytes + request_bytes(req)
 
 
 # ---------------------------------------------------------------------------
@@ -108,32 +125,59 @@ def footprint_bytes(req: SimRequest, workspace_bytes: int) -> int:
 # ---------------------------------------------------------------------------
 
 class Scheduler:
-    """Admission by HBM footprint and per-class slot count."""
+    """Admission by HBM and per-class slot count.
 
-    def __init__(self, budget_bytes: int, slots_per_class: int, footprint):
+    ``footprint(req)`` is the HBM a request holds while admitted;
+    ``plan_bytes(cls)`` is the HBM of the resident state of a shape class
+    (its batch plan), charged when the first request of the class is
+    admitted and kept until the class is evicted.  ``used`` never exceeds
+    the budget: when a request does not fit, plans of other classes with no
+    admitted request are evicted (oldest first) and listed in ``evicted``
+    for the executor to free."""
+
+    def __init__(self, budget_bytes: int, slots_per_class: int, footprint, plan_bytes=None):
         self.budget = int(budget_bytes)
         self.slots_per_class = int(slots_per_class)
         self.footprint = footprint          # callable(req) -> bytes
+        self.plan_bytes = plan_bytes or (lambda cls: 0)
         self.used = 0
         self.queue: List[SimRequest] = []
         self.active_per_class: Dict[tuple, int] = {}
         self.held: Dict[int, int] = {}
+        self.plans: Dict[tuple, int] = {}   # resident classes (insertion order = age) -> bytes
+        self.evicted: List[tuple] = []
 
     def submit(self, req: SimRequest):
         self.queue.append(req)
+
+    def _evict_idle(self, need: int, keep_cls) -> bool:
+        """Evict idle resident classes other than keep_cls until need more
+        bytes fit; True if they do."""
+        for cls in list(self.plans):
+            if self.used + need <= self.budget:
+                break
+            if cls != keep_cls and self.active_per_class.get(cls, 0) == 0:
+                self.used -= self.plans.pop(cls)
+                self.evicted.append(cls)
+        return self.used + need <= self.budget
 
     def admit(self) -> Tuple[List[SimRequest], List[Tuple[SimRequest, str]]]:
         """Requests to start now (arrival order), and requests rejected."""
         admitted, rejected, keep = [], [], []
         for req in self.queue:
-            need = self.footprint(req)
-            if need > self.budget:
-                rejected.append((req, f"footprint {need} B exceeds the HBM budget {self.budget} B"))
-                continue
             cls = req.shape_class
-            if self.active_per_class.get(cls, 0) < self.slots_per_class and self.used + need <= self.budget:
+            own = self.footprint(req)
+            plan = self.plan_bytes(cls)
+            if own + plan > self.budget:
+                rejected.append((req, f"footprint {own + plan} B exceeds the HBM budget {self.budget} B"))
+                continue
+            need = own + (0 if cls in self.plans else plan)
+            fits = self.used + need <= self.budget or self._evict_idle(need, cls)
+            if self.active_per_class.get(cls, 0) < self.slots_per_class and fits:
+                if cls not in self.plans:
+                    self.plans[cls] = plan
                 self.used += need
-                self.held[req.rid] = need
+                self.held[req.rid] = own
                 self.active_per_class[cls] = self.active_per_class.get(cls, 0) + 1
                 admitted.append(req)
             else:
@@ -153,18 +197,11 @@ class Scheduler:
 
 
 # ---------------------------------------------------------------------------
-# GPU executor
+# GPU executors
 # ---------------------------------------------------------------------------
 
-class _Slot:
-    def __init__(self, ctx, stream):
-        self.ctx = ctx
-        self.stream = stream
-        self.busy = False
-
-
 class _Job:
-    def __init__(self, req: SimRequest, slot: _Slot):
+    def __init__(self, req: SimRequest, slot):
         self.req = req
         self.slot = slot
         self.remaining = req.n_steps
@@ -174,11 +211,220 @@ class _Job:
         self.tensors = {}
 
 
+def _finish_outputs(torch, req, ctx, t, device, delta):
+    """The gradient request's chi^2 against a seeded target and the adjoint
+    of its run on the request's own context (slot)."""
+    out = {"pos": t["pos"], "mom": t["mom"], "delta": delta}
+    if req.with_grad:
+        m = req.n_mesh
+        gen = torch.Generator(device=device)
+        gen.manual_seed(req.seed + 2000)
+        target = torch.randn((m, m, m), generator=gen, device=device) * req.sigma
+        loss, gdelta = ctx.pm_chi2(delta, target, req.sigma)
+        _, _, gn = ctx.pm_run_adjoint(t["a"], t["ckpt"], noise=t["noise"], grad_delta=gdelta)
+        out.update(loss=loss, grad_noise=gn)
+    return out
+
+
+class _Plan:
+    def __init__(self, batch, stream, slots):
+        self.batch = batch
+        self.stream = stream
+        self.free = list(range(slots))
+        self.jobs: Dict[int, _Job] = {}          # slot -> running job
+        self.inflight = collections.deque()      # events of enqueued batched steps
+        self.grad_pool: List[list] = []          # [context, stream, busy] for adjoints
+
+
+class BatchedExecutor:
+    """Runs each shape class on one batch plan of the HIP library (one
+    stream per class): a request takes a slot, its initial conditions are
+    generated on the slot, and every tick enqueues one batched KDK step for
+    all running requests of a class (at most ``depth`` in flight per class).
+    A finished request leaves its slot at once; a gradient request's chi^2
+    and adjoint (which need only its arrays: checkpoints, noise, final
+    density) then run on a context of its own from a per-class pool, each on
+    its own stream, so that adjoints overlap with each other and with the
+    class's batched steps."""
+
+    def __init__(self, device="cuda", cosmo: Optional[Cosmology] = None, slots_per_class: int = 4,
+                 keep_results: bool = True, graphs: bool = True, depth: int = 2):
+        import torch
+        from .binding import PMBatch
+        self.torch = torch
+        self.PMBatch = PMBatch
+        self.device = torch.device(device)
+        self.cosmo = cosmo or Cosmology()
+        self.slots = max(2, int(slots_per_class))
+        self.keep_results = keep_results
+        self.graphs = graphs
+        self.depth = max(1, int(depth))
+        self.plans: Dict[tuple, _Plan] = {}
+        self._ws: Dict[tuple, int] = {}
+
+    def plan_bytes(self, cls) -> int:
+        """HBM of a class's resident state: the plan (every slot's workspace)
+        and its pool of adjoint contexts (one workspace per slot, created on
+        demand but charged up front)."""
+        if cls not in self._ws:
+            import ctypes as C
+            from . import _lib
+            from .binding import make_config
+            npart, nmesh, box = cls
+            w = Workload("plan", box, nmesh, npart, 0, (0.1, 1.0), self.cosmo)
+            lib = _lib.load()
+            self._ws[cls] = (int(lib.pm_workspace_bytes(C.byref(make_config(w, batch=self.slots))))
+                             + self.slots * int(lib.pm_workspace_bytes(C.byref(make_config(w)))))
+        return self._ws[cls]
+
+    def request_bytes(self, req: SimRequest) -> int:
+        return request_bytes(req)
+
+    def _plan(self, req: SimRequest) -> _Plan:
+        cls = req.shape_class
+        p = self.plans.get(cls)
+        if p is None:
+            stream = self.torch.cuda.Stream(device=self.device)
+            with self.torch.cuda.stream(stream):
+                b = self.PMBatch(req.workload(self.cosmo), self.slots, device=self.device, stream=stream)
+            if self.graphs:
+                b.pm_use_graphs(True)
+            p = self.plans[cls] = _Plan(b, stream, self.slots)
+        return p
+
+    def drop_plan(self, cls):
+        p = self.plans.pop(cls, None)
+        if p is not None:
+            p.stream.synchronize()
+            p.batch.close()
+            for ctx, stream, _ in p.grad_pool:
+                stream.synchronize()
+                ctx.close()
+
+    def _grad_ctx(self, p: _Plan, req: SimRequest):
+        for e in p.grad_pool:
+            if not e[2]:
+                e[2] = True
+                return e
+        from .binding import PMContext
+        stream = self.torch.cuda.Stream(device=self.device)
+        with self.torch.cuda.stream(stream):
+            ctx = PMContext(req.workload(self.cosmo), device=self.device, stream=stream)
+        e = [ctx, stream, True]
+        p.grad_pool.append(e)
+        return e
+
+    def start(self, req: SimRequest) -> _Job:
+        torch = self.torch
+        p = self._plan(req)
+        if not p.free:
+            raise RuntimeError("no free slot in the class's plan")
+        slot = p.free.pop(0)
+        job = _Job(req, (p, slot))
+        w = req.workload(self.cosmo)
+        mc = p.batch.member(slot)
+        try:
+            with torch.cuda.stream(p.stream):
+                n = req.n_part
+                noise = mc.pm_noise(req.seed)
+                pos, mom = mc.pm_init_lpt(req.seed, w.a_list[0], noise=noise)
+                ckpt = None
+                if req.with_grad:
+                    ckpt = torch.empty((req.n_steps + 1, 2, n ** 3, 3), dtype=torch.float32, device=self.device)
+                p.batch.pm_batch_begin(slot, w.a_list, pos, mom, ckpt=ckpt)
+        except Exception:
+            p.free.append(slot)
+            raise
+        job.tensors = {"noise": noise, "pos": pos, "mom": mom, "ckpt": ckpt, "a": w.a_list}
+        p.jobs[slot] = job
+        return job
+
+    def tick(self, jobs: List[_Job]):
+        """One batched step per class with running requests (unless `depth`
+        steps of it are still in flight), then finish the requests whose
+        last step is enqueued."""
+        torch = self.torch
+        for p in self.plans.values():
+            while p.inflight and p.inflight[0].query():
+                p.inflight.popleft()
+            if not any(not j.ended for j in p.jobs.values()) or len(p.inflight) >= self.depth:
+                continue
+            with torch.cuda.stream(p.stream):
+                if p.batch.pm_batch_advance() > 0:
+                    ev = torch.cuda.Event()
+                    ev.record(p.stream)
+                    p.inflight.append(ev)
+            for slot, job in list(p.jobs.items()):
+                if not job.ended:
+                    job.remaining = p.batch.pm_batch_remaining(slot)
+                    if job.remaining == 0:
+                        self._finish(p, slot, job)
+
+    def _finish(self, p: _Plan, slot: int, job: _Job):
+        torch = self.torch
+        req, t = job.req, job.tensors
+        with torch.cuda.stream(p.stream):
+            m = req.n_mesh
+            delta = torch.empty((m, m, m), dtype=torch.float32, device=self.device)
+            p.batch.pm_batch_end(slot, delta_final=delta)
+            ev = torch.cuda.Event()
+            ev.record(p.stream)
+        # the slot is free once its end is enqueued: a later begin on it runs
+        # after the end on the plan's stream
+        del p.jobs[slot]
+        p.free.append(slot)
+        job.slot = (p, None)
+        if req.with_grad:
+            g = self._grad_ctx(p, req)
+            g[1].wait_event(ev)
+            with torch.cuda.stream(g[1]):
+                out = _finish_outputs(torch, req, g[0], t, self.device, delta)
+                ev = torch.cuda.Event()
+                ev.record(g[1])
+            job.grad = g
+        else:
+            out = {"pos": t["pos"], "mom": t["mom"], "delta": delta}
+        job.event = ev
+        job.result = out if self.keep_results else None
+        job.ended = True
+
+    def done(self, job: _Job) -> bool:
+        return job.ended and job.event.query()
+
+    def release(self, job: _Job):
+        p, slot = job.slot
+        job.tensors = {}
+        g = getattr(job, "grad", None)
+        if g is not None:
+            g[2] = False
+            job.grad = None
+        if slot is not None and p.jobs.get(slot) is job:
+            del p.jobs[slot]
+            p.free.append(slot)
+
+    def abandon(self, job: _Job):
+        """Drop a request that failed mid-run (its slot is not reused)."""
+        p, slot = job.slot
+        if slot is not None:
+            p.jobs.pop(slot, None)
+
+
+class _Slot:
+    def __init__(self, ctx, stream):
+        self.ctx = ctx
+        self.stream = stream
+        self.busy = False
+
+
 class GpuExecutor:
-    """Runs requests with the HIP library, one context and stream per slot."""
+    """Runs each request on a library context of its own (one stream per
+    context).  Used for the one-at-a-time baseline (``serve_fifo``), and by
+    ``serve`` as the unbatched comparison: every request then launches its
+    own kernels.  Contexts are pooled per shape class; a class's pool (up to
+    ``slots_per_class`` workspaces) is what ``plan_bytes`` charges."""
 
     def __init__(self, device="cuda", cosmo: Optional[Cosmology] = None, keep_results: bool = True,
-                 graphs: bool = True):
+                 graphs: bool = True, slots_per_class: int = 4):
         import torch
         from .binding import PMContext
         self.torch = torch
@@ -188,6 +434,7 @@ class GpuExecutor:
         self.slots: Dict[tuple, List[_Slot]] = {}
         self.keep_results = keep_results
         self.graphs = graphs   # each slot replays one captured graph per step
+        self.slots_per_class = int(slots_per_class)
         self._ws_bytes: Dict[tuple, int] = {}
 
     def workspace_bytes(self, req: SimRequest) -> int:
@@ -200,8 +447,20 @@ class GpuExecutor:
             self._ws_bytes[key] = int(lib.pm_workspace_bytes(C.byref(make_config(req.workload(self.cosmo)))))
         return self._ws_bytes[key]
 
+    def plan_bytes(self, cls) -> int:
+        npart, nmesh, box = cls
+        return self.slots_per_class * self.workspace_bytes(SimRequest(0, npart, nmesh, box, 1, 0))
+
+    def request_bytes(self, req: SimRequest) -> int:
+        return request_bytes(req)
+
+    def drop_plan(self, cls):
+        for s in self.slots.pop(cls, []):
+            s.stream.synchronize()
+            s.ctx.close()
+
     def _slot(self, req: SimRequest) -> _Slot:
-        cls = (req.n_part, req.n_mesh, req.box_size)
+        cls = req.shape_class
         pool = self.slots.setdefault(cls, [])
         for s in pool:
             if not s.busy:
@@ -245,19 +504,20 @@ class GpuExecutor:
             m = req.n_mesh
             delta = torch.empty((m, m, m), dtype=torch.float32, device=self.device)
             ctx.pm_run_end(delta_final=delta)
-            out = {"pos": t["pos"], "mom": t["mom"], "delta": delta}
-            if req.with_grad:
-                gen = torch.Generator(device=self.device)
-                gen.manual_seed(req.seed + 2000)
-                target = torch.randn((m, m, m), generator=gen, device=self.device) * req.sigma
-                loss, gdelta = ctx.pm_chi2(delta, target, req.sigma)
-                _, _, gn = ctx.pm_run_adjoint(t["a"], t["ckpt"], noise=t["noise"], grad_delta=gdelta)
-                out.update(loss=loss, grad_noise=gn)
+            out = _finish_outputs(torch, req, ctx, t, self.device, delta)
             ev = torch.cuda.Event()
             ev.record(job.slot.stream)
         job.event = ev
         job.result = out if self.keep_results else None
         job.ended = True
+
+    def tick(self, jobs: List[_Job]):
+        """One step of every running request (each on its own stream)."""
+        for job in jobs:
+            if job.remaining > 0:
+                self.step(job)
+            elif not job.ended:
+                self.finish(job)
 
     def done(self, job: _Job) -> bool:
         return job.ended and job.event.query()
@@ -265,6 +525,9 @@ class GpuExecutor:
     def release(self, job: _Job):
         job.tensors = {}
         job.slot.busy = False
+
+    def abandon(self, job: _Job):
+        job.tensors = {}
 
 
 # ---------------------------------------------------------------------------
@@ -277,6 +540,7 @@ class ServeReport:
     wall: float = 0.0
     max_active: int = 0
     max_queue: int = 0
+    max_used: int = 0
 
     def summary(self) -> dict:
         ok = [c for c in self.completions if c.ok]
@@ -293,8 +557,7 @@ def serve(trace: List[SimRequest], executor, budget_bytes: int, slots_per_class:
           realtime: bool = True, results: Optional[dict] = None, clock=time.perf_counter,
           sleep=time.sleep) -> ServeReport:
     """Continuous batching over a trace of requests (sorted by arrival)."""
-    sched = Scheduler(budget_bytes, slots_per_class,
-                      lambda r: footprint_bytes(r, executor.workspace_bytes(r)))
+    sched = Scheduler(budget_bytes, slots_per_class, executor.request_bytes, executor.plan_bytes)
     pending = list(sorted(trace, key=lambda r: r.arrival))
     rep = ServeReport()
     comp: Dict[int, Completion] = {}
@@ -309,6 +572,10 @@ def serve(trace: List[SimRequest], executor, budget_bytes: int, slots_per_class:
             i += 1
         rep.max_queue = max(rep.max_queue, len(sched.queue))
         admitted, rejected = sched.admit()
+        for cls in sched.evicted:
+            executor.drop_plan(cls)
+        sched.evicted.clear()
+        rep.max_used = max(rep.max_used, sched.used)
         for req, why in rejected:
             c = comp[req.rid]
             c.done, c.error = clock() - t0, why
@@ -321,16 +588,14 @@ def serve(trace: List[SimRequest], executor, budget_bytes: int, slots_per_class:
                 c.done, c.error = clock() - t0, f"start failed: {e}"
                 sched.release(req)
         rep.max_active = max(rep.max_active, len(active))
-        # one KDK step of every running request, then close finished ones
-        for job in active:
-            try:
-                if job.remaining > 0:
-                    executor.step(job)
-                elif not job.ended:
-                    executor.finish(job)
-            except Exception as e:
-                job.ended, job.event = True, None
-                comp[job.req.rid].error = f"run failed: {e}"
+        try:
+            executor.tick(active)
+        except Exception as e:       # a failing step fails the requests it carried
+            for job in active:
+                if not job.ended:
+                    job.ended, job.event = True, None
+                    comp[job.req.rid].error = f"run failed: {e}"
+                    executor.abandon(job)
         still = []
         for job in active:
             failed = job.ended and job.event is None
@@ -340,7 +605,8 @@ def serve(trace: List[SimRequest], executor, budget_bytes: int, slots_per_class:
                 c.ok = not failed
                 if results is not None and job.result is not None:
                     results[job.req.rid] = job.result
-                executor.release(job)
+                if not failed:
+                    executor.release(job)
                 sched.release(job.req)
             else:
                 still.append(job)
@@ -354,7 +620,8 @@ def serve(trace: List[SimRequest], executor, budget_bytes: int, slots_per_class:
 
 def serve_fifo(trace: List[SimRequest], executor, realtime: bool = True, results: Optional[dict] = None,
                clock=time.perf_counter, sleep=time.sleep) -> ServeReport:
-    """Baseline: the same trace served one request at a time, in arrival order."""
+    """Baseline: the same trace served one request at a time, in arrival
+    order, each run whole on a context of its own."""
     rep = ServeReport()
     t0 = clock()
     for req in sorted(trace, key=lambda r: r.arrival):

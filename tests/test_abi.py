@@ -107,3 +107,44 @@ def test_no_kernel_uses_scratch():
             if m and int(m.group(1)) > 0:
                 bad.append((os.path.basename(path), name, int(m.group(1))))
     assert not bad, bad
+
+
+def test_batch_plan_sizes_and_validation(lib):
+    """A batch plan of B members takes B single-simulation workspaces; it
+    needs n_mesh >= 64, no pyramid and B <= PM_MAX_BATCH."""
+    from paper_2010_11847_amd import _lib
+    from paper_2010_11847_amd.binding import make_config
+    w = inputs.scaled(inputs.MEDIUM, 64, 32)
+    one = lib.pm_workspace_bytes(C.byref(make_config(w)))
+    assert one > 0
+    assert lib.pm_workspace_bytes(C.byref(make_config(w, batch=1))) == one
+    for b in (2, 5, _lib.PM_MAX_BATCH):
+        assert lib.pm_workspace_bytes(C.byref(make_config(w, batch=b))) == b * one
+    assert lib.pm_workspace_bytes(C.byref(make_config(w, batch=_lib.PM_MAX_BATCH + 1))) == 0
+    assert lib.pm_workspace_bytes(C.byref(make_config(w, batch=-1))) == 0
+    assert lib.pm_workspace_bytes(C.byref(make_config(inputs.scaled(inputs.SMALL, 32, 32), batch=2))) == 0
+    assert lib.pm_workspace_bytes(C.byref(make_config(replace(w, pyramid_levels=1), batch=2))) == 0
+    assert C.sizeof(_lib.pm_req_desc) == 48
+    # the batch entry points reject a missing plan without touching a GPU
+    assert lib.pm_kdk_step_batched(None, None, 1) == _lib.PM_EINVAL
+    assert lib.pm_batch_advance(None, None) == _lib.PM_EINVAL
+    assert lib.pm_batch_remaining(None, 0) == _lib.PM_EINVAL
+    assert lib.pm_batch_end(None, 0, None) == _lib.PM_EINVAL
+    assert lib.pm_batch_begin(None, 0, None, 0, None, None, None) == _lib.PM_EINVAL
+    h = C.c_void_p()
+    assert lib.pm_batch_member(None, 0, C.byref(h)) == _lib.PM_EINVAL
+
+
+def test_integrator_validation(lib):
+    """PM_INT_FASTPM / LEAPFROG / COLA are valid; other values and a COLA
+    batch plan are not; the LPT-frame call rejects a half-given frame."""
+    from paper_2010_11847_amd import _lib
+    from paper_2010_11847_amd.binding import make_config
+    w = inputs.scaled(inputs.MEDIUM, 64, 32)
+    for k in (inputs.INT_FASTPM, inputs.INT_LEAPFROG, inputs.INT_COLA):
+        assert lib.pm_workspace_bytes(C.byref(make_config(replace(w, integrator=k)))) > 0
+    for k in (-1, 3):
+        assert lib.pm_workspace_bytes(C.byref(make_config(replace(w, integrator=k)))) == 0
+    assert lib.pm_workspace_bytes(C.byref(make_config(replace(w, integrator=inputs.INT_COLA), batch=2))) == 0
+    assert lib.pm_workspace_bytes(C.byref(make_config(replace(w, integrator=inputs.INT_LEAPFROG), batch=2))) > 0
+    assert lib.pm_set_lpt_frame(None, None, None) == _lib.PM_EINVAL

@@ -13,8 +13,9 @@ per-step bar), 1e-4 for adjoint cotangents and noise gradients.
 * One reverse KDK step on a 512^3 mesh: the transposed force at that size.
 * The 5-step reverse sweep at 128^3 particles / 256^3 mesh (the larger
   differentiable configuration), down to the white-noise gradient.
-* The gradient of the 64^3 / 128^3 chi^2 run against central finite
-  differences of the FP64 oracle at 32 seeded cells.
+* The gradient of the 64^3 / 128^3 chi^2 run at 32 seeded cells: along the
+  oracle's trajectory against the oracle, and end to end against central
+  finite differences of the FP64 oracle.
 """
 import json
 import os
@@ -121,32 +122,65 @@ def test_adjoint_sweep_128_on_256_matches_golden(gpu):
 
 
 def test_adjoint_of_64_on_128_run_vs_fd_golden(gpu):
-    """The GPU gradient of the chi^2 loss (its own float32 forward run and
-    adjoint) against Richardson-extrapolated central differences of the FP64
-    oracle's forward run at 32 seeded white-noise cells: |g - g_fd| / rms(g)
-    <= 1e-4 (rms over every cell of the oracle's adjoint gradient)."""
+    """The GPU adjoint of the chi^2 loss of the 64^3 / 128^3 5-step run at 32
+    seeded white-noise cells, scaled by the rms over all cells of the
+    oracle's gradient.
+
+    (1) Along the oracle's trajectory rounded to float32 (only the adjoint
+    runs on the GPU): equal to the oracle's gradient along that same rounded
+    trajectory (stored), max |g - g_o| / rms <= 1e-5.
+    (2) End to end (the GPU's float32 forward run and its adjoint) against
+    Richardson-extrapolated central differences of the FP64 oracle: within
+    2e-3.  The oracle's own adjoint along its FP64 trajectory meets those
+    differences to 3.1e-5 (pinned on the CPU), but a float32 state moves
+    positions by up to 8e-6 cells, enough to put a few particles on the
+    other side of a CIC kink, and the oracle's own gradient along its
+    float32-rounded trajectory is already 4.9e-4 from the differences at
+    one of the cells; the GPU's float32 trajectory carries the same
+    sensitivity."""
+    from oracle import adjoint as A
+    from oracle import lpt as olpt
     from paper_2010_11847_amd.binding import PMContext
     g = load("fd_adj64_mesh128_box200")
+    gt = load("grad_f32traj_adj64_mesh128_box200")
     w = inputs.ADJ_SMALL
     banner(f"adjoint vs FD golden, {w.name}")
     sigma = g["sigma"]
     noise = white_noise(w.seed, w.n_part)
     target = G.chi2_target(w, sigma)
+    cells = np.array(g["cells"])
+    assert cells.tolist() == gt["cells"]
+    fd = np.array(g["fd"])
     c = PMContext(w)
     z = to_dev(noise.astype(np.float32))
+    # (1) the oracle's trajectory rounded to float32, the GPU's adjoint
+    x0, p0 = olpt.generate(w, noise=noise)
+    xs, _, _ = A.run_forward_trajectory(x0, p0, w.a_list, w.n_mesh, w.n_particles, w.cosmo.omega_m)
+    ck = torch.zeros((len(w.a_list), 2, w.n_particles, 3), device="cuda")
+    for i, x in enumerate(xs):
+        ck[i, 0] = to_dev(x)
+    delta = c.pm_paint(ck[-1, 0])
+    _, gdelta = c.pm_chi2(delta, to_dev(target.astype(np.float32)), sigma)
+    _, _, gn = c.pm_run_adjoint(w.a_list, ck, noise=z, grad_delta=gdelta)
+    got = to_np(gn).reshape(-1)[cells].astype(np.float64)
+    err1 = float(np.abs(got - np.array(gt["grad"])).max() / gt["grad_rms"])
+    # (2) end to end on the GPU
     pos, mom = c.pm_init_lpt(0, w.a_list[0], noise=z)
     ckpt = torch.empty((len(w.a_list), 2, w.n_particles, 3), device="cuda")
-    delta = torch.empty((w.n_mesh,) * 3, device="cuda")
-    c.pm_run(w.a_list, pos, mom, ckpt=ckpt, delta_final=delta)
-    _, gdelta = c.pm_chi2(delta, to_dev(target.astype(np.float32)), sigma)
-    _, _, gn = c.pm_run_adjoint(w.a_list, ckpt, noise=z, grad_delta=gdelta)
-    got = to_np(gn).reshape(-1)[np.array(g["cells"])].astype(np.float64)
-    fd = np.array(g["fd"])
-    err = float(np.abs(got - fd).max() / g["grad_rms"])
-    rn = rel(got, fd)
-    banner(f"  max |g - fd| / rms {err:.2e}; rel norm over the cells {rn:.2e}; "
-           f"oracle adjoint vs fd {g['oracle_adjoint_vs_fd_max_rel_to_rms']:.2e}")
-    record("fd_c4a_max_over_rms", err)
-    record("fd_c4a_rel_norm", rn)
+    d_gpu = torch.empty((w.n_mesh,) * 3, device="cuda")
+    c.pm_run(w.a_list, pos, mom, ckpt=ckpt, delta_final=d_gpu)
+    _, gd_gpu = c.pm_chi2(d_gpu, to_dev(target.astype(np.float32)), sigma)
+    _, _, gn2 = c.pm_run_adjoint(w.a_list, ckpt, noise=z, grad_delta=gd_gpu)
+    got2 = to_np(gn2).reshape(-1)[cells].astype(np.float64)
+    err2 = float(np.abs(got2 - fd).max() / g["grad_rms"])
+    err_traj_fd = float(np.abs(got - fd).max() / g["grad_rms"])
+    banner(f"  along the float32-rounded oracle trajectory vs the oracle there: max / rms {err1:.2e}; "
+           f"that gradient vs fd {err_traj_fd:.2e}; end to end vs fd {err2:.2e} (rel norm {rel(got2, fd):.2e}); "
+           f"oracle (FP64 trajectory) vs fd {g['oracle_adjoint_vs_fd_max_rel_to_rms']:.2e}")
+    record("fd_c4a_gpu_vs_oracle_f32_trajectory_max_over_rms", err1)
+    record("fd_c4a_f32_trajectory_vs_fd_max_over_rms", err_traj_fd)
+    record("fd_c4a_end_to_end_max_over_rms", err2)
+    record("fd_c4a_end_to_end_rel_norm", rel(got2, fd))
     c.close()
-    assert err < 1e-4
+    assert err1 < 1e-5
+    assert err2 < 2e-3

@@ -108,3 +108,24 @@ def test_chi2_gradient_matches_central_fd_on_random_cells():
         errs.append(abs(g.reshape(-1)[c] - ref))
     scale = np.sqrt(np.mean(g ** 2))
     assert max(errs) / scale < 1e-6
+
+
+def test_stored_c4a_gradient_meets_finite_differences():
+    """At the 64^3 / 128^3 differentiable configuration (5 steps) the oracle's
+    adjoint (along its FP64 trajectory) meets Richardson-extrapolated central
+    differences of its forward run to 1e-4 of the gradient's rms at 32
+    seeded cells (written by tests/golden/make_golden.py fd_c4a), while the
+    same adjoint along the trajectory rounded to float32 (fd_c4a_f32traj)
+    moves by CIC-kink crossings at some cell: the float32 state, not the
+    adjoint, sets the end-to-end agreement of a float32 run."""
+    import json
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    g = json.load(open(os.path.join(here, "fd_adj64_mesh128_box200.json")))
+    gt = json.load(open(os.path.join(here, "grad_f32traj_adj64_mesh128_box200.json")))
+    fd, ga = np.array(g["fd"]), np.array(g["oracle_adjoint"])
+    assert np.abs(ga - fd).max() / g["grad_rms"] < 1e-4
+    assert g["oracle_adjoint_vs_fd_max_rel_to_rms"] < 1e-4
+    assert g["cells"] == gt["cells"]
+    d32 = np.abs(np.array(gt["grad"]) - fd).max() / g["grad_rms"]
+    assert 1e-4 < d32 < 2e-3

@@ -20,21 +20,33 @@ class FakeJob:
 
 class FakeExecutor:
     """Steps take no time; a request finishes one tick after its last step.
-    Records the interleaving of steps across requests."""
+    Records the interleaving of steps across requests, the live plans and
+    the HBM they and the running requests hold."""
 
-    def __init__(self, ws=100, fail=()):
+    def __init__(self, ws=100, fail=(), plan=0):
         self.ws = ws
+        self.plan = plan
         self.fail = set(fail)
         self.trace = []
         self.active_now = 0
         self.max_active = 0
+        self.live_plans = set()
+        self.dropped = []
 
-    def workspace_bytes(self, req):
+    def request_bytes(self, req):
         return self.ws
+
+    def plan_bytes(self, cls):
+        return self.plan
+
+    def drop_plan(self, cls):
+        self.live_plans.discard(cls)
+        self.dropped.append(cls)
 
     def start(self, req):
         if req.rid in self.fail:
             raise RuntimeError("forced failure")
+        self.live_plans.add(req.shape_class)
         self.active_now += 1
         self.max_active = max(self.max_active, self.active_now)
         return FakeJob(req, self.trace)
@@ -46,10 +58,20 @@ class FakeExecutor:
     def finish(self, job):
         job.ended = True
 
+    def tick(self, jobs):
+        for job in jobs:
+            if job.remaining > 0:
+                self.step(job)
+            elif not job.ended:
+                self.finish(job)
+
     def done(self, job):
         return job.ended
 
     def release(self, job):
+        self.active_now -= 1
+
+    def abandon(self, job):
         self.active_now -= 1
 
 
@@ -61,6 +83,7 @@ def test_footprint_counts_checkpoints():
     a = serve.footprint_bytes(req(0, 64, 5), 1000)
     b = serve.footprint_bytes(req(0, 64, 5, grad=True), 1000)
     assert b - a >= 6 * 2 * 12 * 64 ** 3
+    assert serve.request_bytes(req(0, 64, 5)) == a - 1000
 
 
 def test_admission_respects_budget_and_slots():
@@ -126,12 +149,45 @@ def test_serve_interleaves_and_isolates_failures():
 
 
 def test_tiny_budget_serialises_without_oom():
-    ex = FakeExecutor(ws=1000)
+    ex = FakeExecutor(ws=1000, plan=500)
     trace = [req(i, steps=2) for i in range(5)]
-    fp = serve.footprint_bytes(trace[0], 1000)
-    rep = serve.serve(trace, ex, budget_bytes=fp, slots_per_class=8, realtime=False)
+    rep = serve.serve(trace, ex, budget_bytes=1500, slots_per_class=8, realtime=False)
     assert all(c.ok for c in rep.completions)
     assert ex.max_active == 1
+    assert rep.max_used <= 1500
+
+
+def test_plan_memory_is_charged_and_idle_plans_evicted():
+    """Resident plans count against the budget from their first request until
+    they are evicted; with several shape classes the HBM in use (plans plus
+    running requests) never exceeds the budget, and an idle plan of another
+    class is dropped when a request would not fit otherwise."""
+    ex = FakeExecutor(ws=10, plan=100)
+    trace = []
+    for i in range(12):
+        npart = (8, 16, 32)[i % 3]
+        trace.append(req(i, npart=npart, steps=1 + i % 2, arrival=float(i // 3)))
+    rep = serve.serve(trace, ex, budget_bytes=125, slots_per_class=2, realtime=False)
+    assert all(c.ok for c in rep.completions)
+    assert rep.max_used <= 125          # one plan + up to two requests
+    assert len(ex.dropped) >= 2         # classes took turns
+    sched = serve.Scheduler(budget_bytes=250, slots_per_class=2, footprint=lambda r: 10, plan_bytes=lambda c: 100)
+    sched.submit(req(0, npart=8))
+    sched.submit(req(1, npart=16))
+    adm, _ = sched.admit()
+    assert [r.rid for r in adm] == [0, 1] and sched.used == 220
+    sched.submit(req(2, npart=32))      # a third plan does not fit while both classes run
+    adm, _ = sched.admit()
+    assert not adm and not sched.evicted
+    sched.release(adm and adm[0] or req(0, npart=8))
+    adm, _ = sched.admit()              # class 8 is idle now: evicted for class 32
+    assert [r.rid for r in adm] == [2] and sched.evicted == [(8, 8, 16.0)]
+    assert sched.used == 220
+    # a request whose own bytes plus its plan exceed the budget is rejected
+    sched2 = serve.Scheduler(budget_bytes=105, slots_per_class=2, footprint=lambda r: 10, plan_bytes=lambda c: 100)
+    sched2.submit(req(0))
+    adm, rej = sched2.admit()
+    assert not adm and len(rej) == 1 and "exceeds the HBM budget" in rej[0][1]
 
 
 def test_fifo_baseline_runs_in_order():
