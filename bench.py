@@ -418,6 +418,24 @@ def main():
                     "bytes_per_launch": nbytes[dom], "avg_launch_ms": kernels[dom]["avg_ms"]}
         print(f"[bench] kernels {json.dumps(kernels)}", file=sys.stderr, flush=True)
 
+    # the particle kernels at the start and at the end of the run: one force
+    # evaluation on the 2LPT positions (a = 0.1, nearly uniform) and on the
+    # final ones (a = 1, clustered: heavy tiles)
+    by_epoch = None
+    if not args.no_profile:
+        by_epoch = {}
+        for label, p in (("a0.1", pos0), ("a1.0", pos)):
+            f = ctx.pm_force(p)
+            ctx.pm_profile(True)
+            ctx.pm_force(p, out=f)
+            pr = ctx.pm_profile_read()
+            ctx.pm_profile(False)
+            for k in ("scatter", "paint", "readout_kdk"):
+                if k in pr:
+                    by_epoch[f"{label}_{k}_ms"] = round(pr[k][0] / pr[k][1], 4)
+            del f
+        print(f"[bench] particle kernels by epoch {by_epoch}", file=sys.stderr, flush=True)
+
     del ctx, pos, mom, pos0, mom0
     torch.cuda.empty_cache()
     pyramid = None if args.no_adjoint else optional("pyramid", pyramid_section, w, args.steps)
@@ -456,6 +474,7 @@ def main():
         "reconstruction": reconstruction,
         "serving": serving,
         "kernels": kernels,
+        "particle_kernels_by_epoch": by_epoch,
     }
     print(json.dumps(out))
 

@@ -133,7 +133,7 @@ Layout make_layout(const pm_config* c) {
   const long ng = c->n_mesh, np = c->n_part;
   const long np3 = np * np * np;
   L.cap = c->max_particles > 0 ? c->max_particles : np3;
-  L.n_keys = (long)make_tiles((int)ng).ntiles * 8;
+  L.n_keys = (long)make_tiles((int)ng).ntiles * 64;   // tile x class x half-tile block
   L.n_bins_max = (int)(ng / 2);
   size_t o = 0;
   auto take = [&](size_t bytes) {

@@ -3,10 +3,11 @@
 // fused with the kick and drift updates, and the binned power spectrum.
 //
 // Tiles.  The mesh is cut into T^3-cell tiles.  A particle whose CIC base
-// cell floor(x) lies in tile t gets key 8*t + c, where the class bit c_d is
-// set when floor(x_d) is the last cell of the tile along d, i.e. when the
-// particle also deposits into the next tile along d.  A counting sort by key
-// groups the particles of every tile in 8 contiguous bins.
+// cell floor(x) lies in tile t gets key (8*t + c)*8 + b, where the class bit
+// c_d is set when floor(x_d) is the last cell of the tile along d, i.e. when
+// the particle also deposits into the next tile along d, and b names the
+// half-tile block of floor(x).  A counting sort by key groups the particles
+// of every tile in 8 contiguous (tile, class) bins, each ordered by block.
 //  - Paint: the workgroup of tile t accumulates, in LDS, its own particles
 //    and those particles of the 7 lower neighbour tiles whose class says they
 //    reach into t, keeping only the corners inside t.  Every mesh cell is
@@ -401,44 +402,16 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint(const float* __restrict
 }
 
 // ---- readout + kick + drift ---------------------------------------------------------
-// Slot of a new key among the 27 neighbour tiles x 8 classes of the
-// reference tile (rx, ry, rz), or -1 when it is further away (or the tile
-// grid is too small for the neighbourhood to be unambiguous).
-__device__ __forceinline__ int key_slot(uint32_t key, int rx, int ry, int rz, const TileGeom& g) {
-  if (g.ntx < 3 || g.nty < 3 || g.ntz < 3) return -1;
-  int kx, ky, kz;
-  tile_coords((int)(key >> 3), g, kx, ky, kz);
-  auto d = [](int a, int b, int nt) {
-    int v = a - b;
-    if (v > (nt >> 1)) v -= nt;
-    if (v < -(nt >> 1)) v += nt;
-    return v;
-  };
-  const int dx = d(kx, rx, g.ntx), dy = d(ky, ry, g.nty), dz = d(kz, rz, g.ntz);
-  if (dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1) return -1;
-  return (((dx + 1) * 3 + (dy + 1)) * 3 + (dz + 1)) * 8 + (int)(key & 7u);
-}
-
-__device__ __forceinline__ uint32_t slot_key(int slot, int rx, int ry, int rz, const TileGeom& g) {
-  const int cls = slot & 7, s = slot >> 3;
-  const int dz = s % 3 - 1, dy = (s / 3) % 3 - 1, dx = s / 9 - 1;
-  const int kx = (rx + dx) & (g.ntx - 1), ky = (ry + dy) & (g.nty - 1), kz = (rz + dz) & (g.ntz - 1);
-  return ((((uint32_t)kx << g.lny | (uint32_t)ky) << g.lnz | (uint32_t)kz) << 3) | (uint32_t)cls;
-}
-
 // One tile-sorted particle per thread: CIC gather of the 8 corners from the
 // interleaved force mesh (one 12-byte load per corner; sorted neighbours
-// share cache lines), kicks, drift, wrap, and the tile key + rank of the
+// share cache lines), kicks, drift, wrap, and the sort key + rank of the
 // new position.  All loads are issued before any is used (every lane
 // computes, on a clamped index, and only the stores are predicated).  Ranks
-// are counted per wave in LDS by slot (27 neighbour tiles x 8 classes of
-// the tile of the wave's first particle after the drift), then one global
-// atomic per used slot reserves the range; particles outside the
-// neighbourhood take a global atomic each.  Nothing waits on a workgroup
-// barrier, and each rank is written once.  (Two particles per thread
-// measured slower: the tile span per wave grows in voids.)
+// are reserved per group of equal keys in the wave (agg_rank): one global
+// atomic per group.  Nothing waits on a workgroup barrier, and each rank is
+// written once.  (Two particles per thread measured slower: the tile span
+// per wave grows in voids.)
 constexpr int kReadoutPPT = 1;
-constexpr int kSlots = 27 * 8;
 
 // EXT: the batched, LPT-frame (RO_COLA, RO_COLA_OUT) and RO_TO_ALT paths;
 // the plain instantiation compiles without them (fewer registers on the
@@ -446,15 +419,11 @@ constexpr int kSlots = 27 * 8;
 template <bool EXT>
 __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
   constexpr int PPT = kReadoutPPT;
-  constexpr int kWaves = kThreads / 64;
-  __shared__ uint32_t slot_cnt[kWaves][kSlots];
-  __shared__ uint32_t slot_base[kWaves][kSlots];
   const TileGeom& g = a.g;
   const int n = g.n;
   const long chunk = xcd_tile(blockIdx.x, gridDim.x);
   const long j0 = chunk * (long)(kThreads * PPT);
   const bool keys = (a.flags & RO_KEYS) != 0;
-  const int lane = threadIdx.x & 63;
   float kick_a = a.kick_a, kick_b = a.kick_b, drift = a.drift;
   float *ckpt_x = a.ckpt_x, *ckpt_p = a.ckpt_p;
   if (!EXT) a.flags &= ~(RO_COLA | RO_COLA_OUT | RO_TO_ALT);
@@ -492,10 +461,6 @@ __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
       ckpt_p = ckpt_x + a.ckpt_stride;
     }
   }
-  uint32_t* cnt = slot_cnt[threadIdx.x >> 6];
-  uint32_t* sbase = slot_base[threadIdx.x >> 6];
-  if (keys)
-    for (int i = lane; i < kSlots; i += 64) cnt[i] = 0u;
   long jj[PPT];
   bool valid[PPT];
   float x[PPT][3], p[PPT][3];
@@ -634,49 +599,24 @@ __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
     }
   }
   if (!keys) return;
-  // reference tile: that of lane 0's new position (an invalid lane 0 holds
-  // the clamped last particle, still a valid position)
-  int rx, ry, rz;
-  {
-    int cx, cy, cz;
-    float t;
-    cic_base(__shfl(x[0][0], 0, 64), n, cx, t);
-    cic_base(__shfl(x[0][1], 0, 64), n, cy, t);
-    cic_base(__shfl(x[0][2], 0, 64), n, cz, t);
-    rx = cx >> g.lx;
-    ry = cy >> g.ly;
-    rz = cz >> g.lz;
-  }
-  int slot[PPT];
-  uint32_t rank[PPT];
+  // sort key of the new position and its rank: the wave's lanes with equal
+  // keys are grouped with ballots and each group reserves its ranks with one
+  // global atomic (a sorted wave holds a few keys)
 #pragma unroll
   for (int u = 0; u < PPT; ++u) {
-    slot[u] = -1;
-    rank[u] = 0u;
-    if (!valid[u]) continue;
-    int kx, ky, kz;
-    float t;
-    cic_base(x[u][0], n, kx, t);
-    cic_base(x[u][1], n, ky, t);
-    cic_base(x[u][2], n, kz, t);
-    const uint32_t key = tile_key(kx, ky, kz, g);
-    slot[u] = key_slot(key, rx, ry, rz, g);
-    a.key_out[jj[u]] = key;
-    rank[u] = slot[u] >= 0 ? atomicAdd(&cnt[slot[u]], 1u) : atomicAdd(&a.count[key], 1u);
+    uint32_t key = 0u;
+    if (valid[u]) {
+      int kx, ky, kz;
+      float t;
+      cic_base(x[u][0], n, kx, t);
+      cic_base(x[u][1], n, ky, t);
+      cic_base(x[u][2], n, kz, t);
+      key = tile_key(kx, ky, kz, g);
+      a.key_out[jj[u]] = key;
+    }
+    const uint32_t r = agg_rank(a.count, key, valid[u]);
+    if (valid[u]) a.rank_out[jj[u]] = r;
   }
-  // the wave's own LDS operations complete in order; the fence keeps the
-  // compiler from moving the reads of other lanes' counts above the atomics
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  for (int i = lane; i < kSlots; i += 64) {
-    const uint32_t c = cnt[i];
-    sbase[i] = c ? atomicAdd(&a.count[slot_key(i, rx, ry, rz, g)], c) : 0u;
-  }
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-#pragma unroll
-  for (int u = 0; u < PPT; ++u)
-    if (valid[u]) a.rank_out[jj[u]] = rank[u] + (slot[u] >= 0 ? sbase[slot[u]] : 0u);
 }
 
 __global__ void k_frame_shift(float* __restrict__ mom, const uint32_t* __restrict__ id,

@@ -36,11 +36,20 @@ static __device__ __forceinline__ float wrap_pos(float x, float n) {
   return x;
 }
 
+// Sort key of a particle with CIC base cell (ix, iy, iz):
+//   ((tile * 8 + class) * 8 + sub)
+// class bit d: the base cell is the last of its tile along d (the particle
+// also deposits into the next tile); sub bit d: the base cell lies in the
+// upper half of the tile along d.  Paint gathers whole (tile, class) bins,
+// eight consecutive keys; inside a bin the half-tile blocks keep the
+// particles that one wave reads out close together in the force mesh.
 static __device__ __forceinline__ uint32_t tile_key(int ix, int iy, int iz, const TileGeom& g) {
   const uint32_t tile = ((((uint32_t)ix >> g.lx) << g.lny | ((uint32_t)iy >> g.ly)) << g.lnz) | ((uint32_t)iz >> g.lz);
-  const uint32_t c = (uint32_t)((ix & (g.tx - 1)) == g.tx - 1) | ((uint32_t)((iy & (g.ty - 1)) == g.ty - 1) << 1) |
-                     ((uint32_t)((iz & (g.tz - 1)) == g.tz - 1) << 2);
-  return tile * 8u + c;
+  const uint32_t lx = (uint32_t)ix & (g.tx - 1), ly = (uint32_t)iy & (g.ty - 1), lz = (uint32_t)iz & (g.tz - 1);
+  const uint32_t c = (uint32_t)(lx == (uint32_t)g.tx - 1) | ((uint32_t)(ly == (uint32_t)g.ty - 1) << 1) |
+                     ((uint32_t)(lz == (uint32_t)g.tz - 1) << 2);
+  const uint32_t sub = ((lx >> (g.lx - 1)) << 2) | ((ly >> (g.ly - 1)) << 1) | (lz >> (g.lz - 1));
+  return (tile * 8u + c) * 8u + sub;
 }
 
 // (x, y, z) tile coordinates of a flattened tile index
@@ -139,7 +148,7 @@ static __device__ __forceinline__ void build_ranges(RangeTable& rt, const uint32
       const int sx = (tx - (e_sel & 1)) & (g.ntx - 1), sy = (ty - ((e_sel >> 1) & 1)) & (g.nty - 1),
                 sz = (tz - ((e_sel >> 2) & 1)) & (g.ntz - 1);
       const uint32_t bin = (((uint32_t)sx * g.nty + sy) * g.ntz + sz) * 8 + c_sel;
-      const uint32_t b0 = off[bin], b1 = off[bin + 1];
+      const uint32_t b0 = off[bin * 8], b1 = off[bin * 8 + 8];   // its eight half-tile keys
       rt.start[r] = b0;
       len = b1 - b0;
     }
