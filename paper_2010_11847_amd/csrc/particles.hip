@@ -214,8 +214,11 @@ __global__ void k_scatter(ScatterArgs a) {
     a.mom_out = byte_adv(a.mom_out, bo);
     a.id_out = byte_adv(a.id_out, bo);
   }
+  // consecutive blocks of particles on one XCD: their destinations form
+  // runs that continue from block to block, and the partial cache lines at
+  // the ends of the runs then merge in one L2
   const long stride = (long)gridDim.x * blockDim.x;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < a.np; i += stride) {
+  for (long i = (long)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; i < a.np; i += stride) {
     const uint32_t key = a.key[i], rank = a.rank[i];
     float x[3], p[3] = {0.f, 0.f, 0.f};
 #pragma unroll
