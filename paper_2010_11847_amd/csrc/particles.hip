@@ -268,6 +268,8 @@ struct PaintWeights {
 // allows four workgroups per CU, and 512 threads each make that the full
 // eight waves per SIMD to hide the latency of the range and particle loads.
 constexpr int kPaintThreads = 512;
+// workgroups of the persistent paint (a multiple of 8)
+constexpr int kPaintPersistentGroups = 1024;
 
 template <bool STD, bool WT>
 __global__ __launch_bounds__(kPaintThreads) void k_paint(const float* __restrict__ pos, const uint32_t* __restrict__ off,
@@ -401,6 +403,155 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint(const float* __restrict
     const unsigned long long v = acc[tile_li(cx, cy, cz, g)];
     const double rho = WT ? (double)(long long)v / (double)S : (double)v * 0x1p-31;
     out[STD ? ((long)x * n + y) * n + z : blk_real(x, y, z, n)] = (float)(rho * (double)scale + (double)offset);
+  }
+}
+
+// Persistent form of the plain paint (unit masses, x-blocked mesh, tiles at
+// least 8 cells wide along x): each workgroup walks its own run of tiles and
+// overlaps the global loads of the next tile with the work on the current
+// one.  While it deposits tile k, wave 0 has the bin offsets of tile k+1 in
+// flight; while it stores tile k (and clears the accumulator cell by cell as
+// it reads it), every thread has its first particles of tile k+1 in flight.
+// A one-tile-per-workgroup launch waits for both round trips on every tile.
+// The cells, sums and stores are those of k_paint<false, false>; the tiles
+// are 16^3 cells.
+__global__ __launch_bounds__(kPaintThreads) void k_paint_p(const float* __restrict__ pos,
+                                                           const uint32_t* __restrict__ off, TileGeom g,
+                                                           float* __restrict__ out, float scale, float offset,
+                                                           BatchArg bat) {
+  __shared__ __align__(16) unsigned long long acc[kTileCells];
+  __shared__ RangeTable rt[2];
+  {
+    const long bo = batch_bytes(bat);
+    if (bo < 0) return;
+    pos = byte_adv(pos, bo);
+    off = byte_adv(off, bo);
+    out = byte_adv(out, bo);
+  }
+  const int n = g.n;
+  // tiles: XCD x (= blockIdx.x % 8) takes the contiguous eighth of the
+  // tiles [x cnt, (x + 1) cnt) and its nslot workgroups take every nslot-th
+  // of them (gridDim.x is a multiple of 8, at most ntiles)
+  const int cnt = g.ntiles >> 3, nslot = (int)gridDim.x >> 3;
+  const int c0 = ((int)blockIdx.x & 7) * cnt;
+  int k = (int)blockIdx.x >> 3;
+  if (k >= cnt) return;   // uniform over the workgroup
+  {
+    uint4* a4 = reinterpret_cast<uint4*>(acc);
+    for (int c = threadIdx.x; c < (tile_cells(g) >> 1); c += kPaintThreads) a4[c] = make_uint4(0u, 0u, 0u, 0u);
+  }
+  constexpr int kBatch = 2;
+  constexpr int kRound = kPaintThreads * kBatch;
+  auto coords = [&](int tile, int& tx, int& ty, int& tz) { tile_coords(tile, g, tx, ty, tz); };
+  // particles of a tile: indices past the end are clamped onto its last
+  // particle (particle 0 for an empty tile) and skipped at deposit time.
+  // The loads are unconditional, so that every path leaves the same loads
+  // in flight and the waits before the deposits count only these.
+  auto issue = [&](const RangeTable& t, uint32_t total, uint32_t base, float (&px)[kBatch][3]) {
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const uint32_t idx = base + threadIdx.x + u * kPaintThreads;
+      const uint32_t j = total ? range_particle(t, idx < total ? idx : total - 1) : 0u;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) px[u][d] = pos[3 * (long)j + d];
+    }
+  };
+  auto deposit = [&](const float (&px)[kBatch][3], uint32_t total, uint32_t base, int ox, int oy, int oz) {
+    const int TX = g.tx, TY = g.ty, TZ = g.tz;
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      if (base + threadIdx.x + u * kPaintThreads >= total) continue;
+      int ix, iy, iz;
+      float fx, fy, fz;
+      cic_base(px[u][0], n, ix, fx);
+      cic_base(px[u][1], n, iy, fy);
+      cic_base(px[u][2], n, iz, fz);
+      int lx = (ix - ox) & (n - 1), ly = (iy - oy) & (n - 1), lz = (iz - oz) & (n - 1);
+      if (lx > TX) lx -= n;
+      if (ly > TY) ly -= n;
+      if (lz > TZ) lz -= n;
+      const float wx[2] = {1.f - fx, fx}, wy[2] = {1.f - fy, fy}, wz[2] = {1.f - fz, fz};
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int cx = lx + a;
+        if (cx < 0 || cx >= TX) continue;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const int cy = ly + b;
+          if (cy < 0 || cy >= TY) continue;
+          const float wxy = wx[a] * wy[b];
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const int cz = lz + c;
+            if (cz < 0 || cz >= TZ) continue;
+            atomicAdd(&acc[tile_li(cx, cy, cz, g)], (unsigned long long)(uint32_t)(wxy * wz[c] * 2147483648.0f));
+          }
+        }
+      }
+    }
+  };
+
+  int cur = 0;
+  int tx, ty, tz;
+  coords(c0 + k, tx, ty, tz);
+  build_ranges(rt[0], off, tx, ty, tz, g);
+  uint32_t total = rt[0].pre[27];
+  float px[kBatch][3];
+  issue(rt[0], total, 0, px);
+  for (;;) {
+    const int kn = k + nslot;
+    const bool more = kn < cnt;   // uniform
+    // the next tile's bin offsets, loaded by every lane (lane r of each wave
+    // reads range min(r, 26); the last tile reloads its own), used by wave 0
+    int nx, ny, nz;
+    coords(c0 + (more ? kn : k), nx, ny, nz);
+    uint32_t b0, b1;
+    {
+      const int r = (int)(threadIdx.x & 63);
+      range_loads(off, nx, ny, nz, g, r < 27 ? r : 26, b0, b1);
+    }
+    // deposits of tile k: the first round from the particles already loaded
+    const int ox = tx * g.tx, oy = ty * g.ty, oz = tz * g.tz;
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) asm volatile("" : "+v"(px[u][0]), "+v"(px[u][1]), "+v"(px[u][2]));
+    deposit(px, total, 0, ox, oy, oz);
+    for (uint32_t base = kRound; base < total; base += kRound) {   // heavy tiles
+      issue(rt[cur], total, base, px);
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) asm volatile("" : "+v"(px[u][0]), "+v"(px[u][1]), "+v"(px[u][2]));
+      deposit(px, total, base, ox, oy, oz);
+    }
+    if (more && threadIdx.x < 64) range_publish(rt[cur ^ 1], threadIdx.x, b0, b1);
+    __syncthreads();   // deposits done, the next table published
+    // (after the last tile: particle 0, unused)
+    const uint32_t ntotal = more ? rt[cur ^ 1].pre[27] : 0u;
+    issue(rt[cur ^ 1], ntotal, 0, px);
+    // store tile k four cells at a time (16-byte stores, x%8 fastest) and
+    // clear each cell as it is read: a fixed count per thread, so that the
+    // wait for the next particles need not wait for these stores
+    static_assert((kTileCells / 4) % kPaintThreads == 0, "whole store rounds");
+#pragma unroll
+    for (int r4 = 0; r4 < kTileCells / 4 / kPaintThreads; ++r4) {
+      const int c4 = threadIdx.x + r4 * kPaintThreads;
+      int cx, cy, cz;
+      store_walk(c4 << 2, g, cx, cy, cz);
+      float v[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        unsigned long long& cell = acc[tile_li(cx + i, cy, cz, g)];
+        v[i] = (float)((double)cell * 0x1p-31 * (double)scale + (double)offset);
+        cell = 0ull;
+      }
+      *reinterpret_cast<float4*>(out + blk_real(ox + cx, oy + cy, oz + cz, n)) = make_float4(v[0], v[1], v[2], v[3]);
+    }
+    if (!more) break;
+    __syncthreads();   // the accumulator is clear and the old table free
+    k = kn;
+    cur ^= 1;
+    total = ntotal;
+    tx = nx;
+    ty = ny;
+    tz = nz;
   }
 }
 
@@ -845,6 +996,13 @@ void launch_scatter(const ScatterArgs& a, hipStream_t s) {
 void launch_paint(const float* pos_sorted, const uint32_t* off, const TileGeom& g, float* out, float scale,
                   float offset, bool std_layout, hipStream_t s, const BatchArg& bat) {
   const PaintWeights pw;
+  if (!std_layout && g.tx * g.ty * g.tz == kTileCells && g.ntiles >= 8) {
+    // persistent: up to four workgroups per CU of 256 CUs, a multiple of 8
+    const int nwg = g.ntiles < kPaintPersistentGroups ? g.ntiles : kPaintPersistentGroups;
+    hipLaunchKernelGGL(k_paint_p, dim3(nwg, 1, bat.n), dim3(kPaintThreads), 0, s, pos_sorted, off, g, out, scale,
+                       offset, bat);
+    return;
+  }
   const dim3 grid(g.ntiles, 1, bat.n);
   if (std_layout)
     hipLaunchKernelGGL((k_paint<true, false>), grid, dim3(kPaintThreads), 0, s, pos_sorted, off, g, out, scale,

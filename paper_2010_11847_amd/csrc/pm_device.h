@@ -129,38 +129,47 @@ struct RangeTable {
 };
 
 // Ranges of the 27 (neighbour tile, class) bins whose particles deposit
-// into tile (tx, ty, tz).  Wave 0 loads the bin offsets and scans the
-// lengths with lane shuffles; one barrier publishes the table.
+// into tile (tx, ty, tz), in two halves so that the loads can be issued
+// early: range_loads (lanes r < 27 of wave 0) reads the offsets of range r,
+// range_publish (the whole of wave 0) scans the lengths with lane shuffles
+// and writes the table; a barrier must follow before other waves read it.
+static __device__ __forceinline__ void range_loads(const uint32_t* __restrict__ off, int tx, int ty, int tz,
+                                                   const TileGeom& g, int r, uint32_t& b0, uint32_t& b1) {
+  // enumerate (e, cls) pairs with (cls & e) == e in a fixed order
+  int k = 0, e_sel = 0, c_sel = 0;
+  for (int e = 0; e < 8; ++e)
+    for (int c = 0; c < 8; ++c)
+      if ((c & e) == e) {
+        if (k == r) { e_sel = e; c_sel = c; }
+        ++k;
+      }
+  const int sx = (tx - (e_sel & 1)) & (g.ntx - 1), sy = (ty - ((e_sel >> 1) & 1)) & (g.nty - 1),
+            sz = (tz - ((e_sel >> 2) & 1)) & (g.ntz - 1);
+  const uint32_t bin = (((uint32_t)sx * g.nty + sy) * g.ntz + sz) * 8 + c_sel;
+  b0 = off[bin * 8];       // its eight half-tile keys
+  b1 = off[bin * 8 + 8];
+}
+static __device__ __forceinline__ void range_publish(RangeTable& rt, int r, uint32_t b0, uint32_t b1) {
+  const uint32_t len = r < 27 ? b1 - b0 : 0u;
+  if (r < 27) rt.start[r] = b0;
+  uint32_t v = len;   // inclusive scan over lanes 0..31
+#pragma unroll
+  for (int d = 1; d < 32; d <<= 1) {
+    const uint32_t t = __shfl_up(v, d, 64);
+    if (r >= d) v += t;
+  }
+  if (r < 27) rt.pre[r + 1] = v;
+  if (r == 0) rt.pre[0] = 0;
+  if (r >= 28 && r < 32) rt.pre[r] = 0xFFFFFFFFu;
+}
+// Both halves by wave 0, then one barrier that publishes the table.
 static __device__ __forceinline__ void build_ranges(RangeTable& rt, const uint32_t* __restrict__ off, int tx, int ty,
                                                     int tz, const TileGeom& g) {
   const int r = threadIdx.x;
   if (r < 64) {
-    uint32_t len = 0;
-    if (r < 27) {
-      // enumerate (e, cls) pairs with (cls & e) == e in a fixed order
-      int k = 0, e_sel = 0, c_sel = 0;
-      for (int e = 0; e < 8; ++e)
-        for (int c = 0; c < 8; ++c)
-          if ((c & e) == e) {
-            if (k == r) { e_sel = e; c_sel = c; }
-            ++k;
-          }
-      const int sx = (tx - (e_sel & 1)) & (g.ntx - 1), sy = (ty - ((e_sel >> 1) & 1)) & (g.nty - 1),
-                sz = (tz - ((e_sel >> 2) & 1)) & (g.ntz - 1);
-      const uint32_t bin = (((uint32_t)sx * g.nty + sy) * g.ntz + sz) * 8 + c_sel;
-      const uint32_t b0 = off[bin * 8], b1 = off[bin * 8 + 8];   // its eight half-tile keys
-      rt.start[r] = b0;
-      len = b1 - b0;
-    }
-    uint32_t v = len;   // inclusive scan over lanes 0..31
-#pragma unroll
-    for (int d = 1; d < 32; d <<= 1) {
-      const uint32_t t = __shfl_up(v, d, 64);
-      if (r >= d) v += t;
-    }
-    if (r < 27) rt.pre[r + 1] = v;
-    if (r == 0) rt.pre[0] = 0;
-    if (r >= 28 && r < 32) rt.pre[r] = 0xFFFFFFFFu;
+    uint32_t b0 = 0, b1 = 0;
+    if (r < 27) range_loads(off, tx, ty, tz, g, r, b0, b1);
+    range_publish(rt, r, b0, b1);
   }
   __syncthreads();
 }
