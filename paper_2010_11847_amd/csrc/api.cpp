@@ -64,7 +64,7 @@ struct Layout {
   size_t mesh[3] = {0, 0, 0};
   size_t force_i = 0;
   size_t pos_s[2] = {0, 0}, mom_s[2] = {0, 0}, id_s[2] = {0, 0};
-  size_t key = 0, rank = 0;
+  size_t key = 0;
   size_t count = 0, off = 0, bsum = 0;
   size_t pw_partial = 0, pw_out = 0;
   size_t misc = 0;   // small device words (the adjoint paint's max |weight|)
@@ -163,7 +163,6 @@ Layout make_layout(const pm_config* c) {
   for (int i = 0; i < 2; ++i) L.mom_s[i] = take((size_t)L.cap * 12);
   for (int i = 0; i < 2; ++i) L.id_s[i] = take((size_t)L.cap * 4);
   L.key = take((size_t)L.cap * 4);
-  L.rank = take((size_t)L.cap * 4);
   if (nc) {
     for (int i = 0; i < 3; ++i) L.coarse[i] = take(field_bytes(nc));
     L.force_c = take((size_t)nc * nc * nc * 12);
@@ -344,7 +343,7 @@ struct pm_ctx {
   float* pos_s[2] = {};
   float* mom_s[2] = {};
   uint32_t* id_s[2] = {};
-  uint32_t *key = nullptr, *rank = nullptr, *count = nullptr, *off = nullptr, *bsum = nullptr;
+  uint32_t *key = nullptr, *count = nullptr, *off = nullptr, *bsum = nullptr;
   double *pw_partial = nullptr, *pw_out = nullptr;
   float* pk_lat = nullptr;
   Profiler prof;
@@ -400,10 +399,10 @@ struct pm_ctx {
   // counting sort of np particles (caller order) into sorted buffer dst
   void sort(const float* pos, const float* mom, const uint32_t* id, long np, int dst) {
     timed(PC_FILL, [&] { pmk::launch_fill_u32(count, L.n_keys, 0u, stream); });
-    timed(PC_KEYS, [&] { pmk::launch_keys(pos, np, tg, key, rank, count, stream); });
+    timed(PC_KEYS, [&] { pmk::launch_keys(pos, np, tg, key, count, stream); });
     finish_sort(pos, mom, id, np, dst);
   }
-  // scan + scatter once key/rank/count are known
+  // scan + scatter once the keys and their counts are known
   void finish_sort(const float* pos, const float* mom, const uint32_t* id, long np, int dst) {
     timed(PC_SCAN, [&] { pmk::launch_scan(count, L.n_keys, off, bsum, stream); });
     pmk::ScatterArgs a;
@@ -412,8 +411,7 @@ struct pm_ctx {
     a.mom = mom;
     a.id = id;
     a.key = key;
-    a.rank = rank;
-    a.off = off;
+    a.cursor = count;   // the scan left a copy of the offsets there
     a.pos_out = pos_s[dst];
     a.mom_out = mom ? mom_s[dst] : nullptr;
     a.id_out = id_s[dst];
@@ -565,8 +563,7 @@ struct pm_ctx {
     sa.mom = mom_s[1];
     sa.id = id_s[1];
     sa.key = key;
-    sa.rank = rank;
-    sa.off = off;
+    sa.cursor = count;
     sa.pos_out = pos_s[0];
     sa.mom_out = mom_s[0];
     sa.id_out = id_s[0];
@@ -588,7 +585,6 @@ struct pm_ctx {
     a.id = id_s[cur];
     a.fi = cur_force ? cur_force : force_i;
     a.key_out = key;
-    a.rank_out = rank;
     a.count = count;
     return a;
   }
@@ -712,7 +708,6 @@ int create_one(const pm_config* cfg, char* ws, const Layout& L, void* stream, pm
     c->id_s[i] = reinterpret_cast<uint32_t*>(w + L.id_s[i]);
   }
   c->key = reinterpret_cast<uint32_t*>(w + L.key);
-  c->rank = reinterpret_cast<uint32_t*>(w + L.rank);
   c->count = reinterpret_cast<uint32_t*>(w + L.count);
   c->off = reinterpret_cast<uint32_t*>(w + L.off);
   c->bsum = reinterpret_cast<uint32_t*>(w + L.bsum);

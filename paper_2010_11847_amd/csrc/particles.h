@@ -50,8 +50,7 @@ struct ScatterArgs {
   const float* mom = nullptr;      // may be null
   const uint32_t* id = nullptr;    // null: identity
   const uint32_t* key = nullptr;
-  const uint32_t* rank = nullptr;
-  const uint32_t* off = nullptr;
+  uint32_t* cursor = nullptr;      // per key: the next free slot (the scan's copy of the offsets)
   float* pos_out = nullptr;
   float* mom_out = nullptr;
   uint32_t* id_out = nullptr;
@@ -64,7 +63,7 @@ enum ReadoutFlags : int {
   RO_WRITE_SORTED = 4,   // write x, p back in sorted order
   RO_XP_BYID = 8,        // write x, p to pos_out/mom_out at the particle id
   RO_FORCE_BYID = 16,    // write F to force_out at the particle id
-  RO_KEYS = 32,          // tile key and rank of the new position
+  RO_KEYS = 32,          // tile key of the new position, counted per key
   RO_CKPT = 64,          // write x and p (after kick_a) to ckpt_x/ckpt_p at the id
   RO_TO_ALT = 128,       // write x, p and the id to pos_alt/mom_alt/id_alt at the same (sorted) index
   RO_COLA = 256,         // LPT frame: kick with F - c1 psi1 - c2 psi2, drift adds dD1 psi1 + dD2 psi2
@@ -86,7 +85,6 @@ struct ReadoutArgs {
   float* ckpt_x = nullptr;
   float* ckpt_p = nullptr;
   uint32_t* key_out = nullptr;
-  uint32_t* rank_out = nullptr;
   uint32_t* count = nullptr;
   // A run's step loop reads its factors from device memory, so that one
   // captured graph serves every step: at i = *step_i, steps[i] = {kick_a,
@@ -132,10 +130,12 @@ void launch_relayout(const float* in, float* out, int n_side, bool to_blocked, h
 void launch_lpt_delta2(float* const* phi6, long n, float* out, hipStream_t s);
 void launch_lpt_particles(const LptParticleArgs& a, hipStream_t s);
 void launch_fill_u32(uint32_t* p, long n, uint32_t v, hipStream_t s, const BatchArg& bat = BatchArg());
-void launch_keys(const float* pos, long np, const TileGeom& g, uint32_t* key, uint32_t* rank, uint32_t* count,
-                 hipStream_t s);
+// tile keys of np particles, counted per key into count (zeroed first)
+void launch_keys(const float* pos, long np, const TileGeom& g, uint32_t* key, uint32_t* count, hipStream_t s);
 long scan_scratch_words(long n);
-void launch_scan(const uint32_t* count, long n, uint32_t* off, uint32_t* bsum, hipStream_t s,
+// off = exclusive scan of count[0..n), off[n] = total; count[0..n) is then
+// overwritten with a copy of off[0..n) (the scatter's cursors)
+void launch_scan(uint32_t* count, long n, uint32_t* off, uint32_t* bsum, hipStream_t s,
                  const BatchArg& bat = BatchArg());
 void launch_scatter(const ScatterArgs& a, hipStream_t s);
 // std_layout: write [x][y][z] instead of the x-blocked layout

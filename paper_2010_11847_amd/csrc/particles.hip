@@ -100,8 +100,7 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, long n, uint32_t v, BatchAr
 }
 
 __global__ __launch_bounds__(kThreads) void k_keys(const float* __restrict__ pos, long np, TileGeom g,
-                                                   uint32_t* __restrict__ key, uint32_t* __restrict__ rank,
-                                                   uint32_t* __restrict__ count) {
+                                                   uint32_t* __restrict__ key, uint32_t* __restrict__ count) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = i < np;
   uint32_t k = 0;
@@ -113,11 +112,8 @@ __global__ __launch_bounds__(kThreads) void k_keys(const float* __restrict__ pos
     cic_base(pos[3 * i + 2], g.n, iz, t);
     k = tile_key(ix, iy, iz, g);
   }
-  const uint32_t r = agg_rank(count, k, valid);
-  if (valid) {
-    key[i] = k;
-    rank[i] = r;
-  }
+  agg_count(count, k, valid);
+  if (valid) key[i] = k;
 }
 
 // Exclusive scan of count[0..n) into off[0..n], off[n] = total.
@@ -184,22 +180,34 @@ __global__ __launch_bounds__(kThreads) void k_scan_top(uint32_t* __restrict__ bs
   if (threadIdx.x == 0) bsum[nb] = carry;
 }
 
-__global__ __launch_bounds__(kThreads) void k_scan_add(uint32_t* __restrict__ off, long n,
-                                                       const uint32_t* __restrict__ bsum, int nb, BatchArg bat) {
+// adds the block carries and copies the offsets into the (consumed) counts:
+// the scatter's per-key cursors
+__global__ __launch_bounds__(kThreads) void k_scan_add(uint32_t* __restrict__ off, uint32_t* __restrict__ cursor,
+                                                       long n, const uint32_t* __restrict__ bsum, int nb,
+                                                       BatchArg bat) {
   const long bo = batch_bytes(bat);
   if (bo < 0) return;
   off = byte_adv(off, bo);
+  cursor = byte_adv(cursor, bo);
   bsum = byte_adv(bsum, bo);
   const long base = (long)blockIdx.x * kScanBlock;
   const uint32_t add = bsum[blockIdx.x];
   for (int j = threadIdx.x; j < kScanBlock; j += kThreads)
-    if (base + j < n) off[base + j] += add;
+    if (base + j < n) {
+      const uint32_t v = off[base + j] + add;
+      off[base + j] = v;
+      cursor[base + j] = v;
+    }
   if (blockIdx.x == 0 && threadIdx.x == 0) off[n] = bsum[nb];
 }
 
-// Every load of a particle (key, rank, state, id) is issued before the
-// dependent offset lookup, and pinned: left to the compiler, the state
-// loads follow the offset load and add a third round trip to the chain.
+// Each particle's destination is reserved at its key's cursor (one atomic
+// per group of equal keys in the wave; the order inside a key is the order
+// in which the groups arrive, which no result depends on: paint sums in
+// integers and the readout is per particle).  Every load of a particle
+// (key, state, id) is issued before the atomic, and pinned: left to the
+// compiler, the state loads follow it and add a third round trip to the
+// chain.
 __global__ void k_scatter(ScatterArgs a) {
   if (a.bat.d) {
     const long bo = batch_bytes(a.bat);
@@ -208,28 +216,32 @@ __global__ void k_scatter(ScatterArgs a) {
     a.mom = byte_adv(a.mom, bo);
     a.id = byte_adv(a.id, bo);
     a.key = byte_adv(a.key, bo);
-    a.rank = byte_adv(a.rank, bo);
-    a.off = byte_adv(a.off, bo);
+    a.cursor = byte_adv(a.cursor, bo);
     a.pos_out = byte_adv(a.pos_out, bo);
     a.mom_out = byte_adv(a.mom_out, bo);
     a.id_out = byte_adv(a.id_out, bo);
   }
   // consecutive blocks of particles on one XCD: their destinations form
   // runs that continue from block to block, and the partial cache lines at
-  // the ends of the runs then merge in one L2
+  // the ends of the runs then merge in one L2.  The loop bound is uniform
+  // over the block: the whole wave takes part in the key grouping.
   const long stride = (long)gridDim.x * blockDim.x;
-  for (long i = (long)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; i < a.np; i += stride) {
-    const uint32_t key = a.key[i], rank = a.rank[i];
+  for (long i0 = (long)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x; i0 < a.np; i0 += stride) {
+    const long i = i0 + threadIdx.x;
+    const bool valid = i < a.np;
+    const long ic = valid ? i : a.np - 1;
+    const uint32_t key = a.key[ic];
     float x[3], p[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-    for (int d = 0; d < 3; ++d) x[d] = a.pos[3 * i + d];
+    for (int d = 0; d < 3; ++d) x[d] = a.pos[3 * ic + d];
     if (a.mom) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) p[d] = a.mom[3 * i + d];
+      for (int d = 0; d < 3; ++d) p[d] = a.mom[3 * ic + d];
     }
-    const uint32_t id = (a.id_out && a.id) ? a.id[i] : (uint32_t)i;
+    const uint32_t id = (a.id_out && a.id) ? a.id[ic] : (uint32_t)ic;
     asm volatile("" : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(p[0]), "+v"(p[1]), "+v"(p[2]));
-    const uint32_t d = a.off[key] + rank;
+    const uint32_t d = agg_rank(a.cursor, key, valid);
+    if (!valid) continue;
 #pragma unroll
     for (int c = 0; c < 3; ++c) a.pos_out[3 * (long)d + c] = x[c];
     if (a.mom) {
@@ -558,13 +570,14 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint_p(const float* __restri
 // ---- readout + kick + drift ---------------------------------------------------------
 // One tile-sorted particle per thread: CIC gather of the 8 corners from the
 // interleaved force mesh (one 12-byte load per corner; sorted neighbours
-// share cache lines), kicks, drift, wrap, and the sort key + rank of the
-// new position.  All loads are issued before any is used (every lane
-// computes, on a clamped index, and only the stores are predicated).  Ranks
-// are reserved per group of equal keys in the wave (agg_rank): one global
-// atomic per group.  Nothing waits on a workgroup barrier, and each rank is
-// written once.  (Two particles per thread measured slower: the tile span
-// per wave grows in voids.)
+// share cache lines), kicks, drift, wrap, and the sort key of the new
+// position, counted per key.  All loads are issued before any is used
+// (every lane computes, on a clamped index, and only the stores are
+// predicated).  The counts are added per group of equal keys in the wave
+// (agg_count: one global atomic per group, not waited for); the scatter
+// reserves the destinations.  Nothing waits on a workgroup barrier.  (Two
+// particles per thread measured slower: the tile span per wave grows in
+// voids.)
 constexpr int kReadoutPPT = 1;
 
 // EXT: the batched, LPT-frame (RO_COLA, RO_COLA_OUT) and RO_TO_ALT paths;
@@ -590,7 +603,6 @@ __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
     a.id = byte_adv(a.id, bo);
     a.fi = byte_adv(a.fi, bo);
     a.key_out = byte_adv(a.key_out, bo);
-    a.rank_out = byte_adv(a.rank_out, bo);
     a.count = byte_adv(a.count, bo);
     a.pos_alt = byte_adv(a.pos_alt, bo);
     a.mom_alt = byte_adv(a.mom_alt, bo);
@@ -753,9 +765,9 @@ __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
     }
   }
   if (!keys) return;
-  // sort key of the new position and its rank: the wave's lanes with equal
-  // keys are grouped with ballots and each group reserves its ranks with one
-  // global atomic (a sorted wave holds a few keys)
+  // sort key of the new position, counted: the wave's lanes with equal keys
+  // are grouped with ballots and each group adds its size with one global
+  // atomic (a sorted wave holds a few keys)
 #pragma unroll
   for (int u = 0; u < PPT; ++u) {
     uint32_t key = 0u;
@@ -768,8 +780,7 @@ __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
       key = tile_key(kx, ky, kz, g);
       a.key_out[jj[u]] = key;
     }
-    const uint32_t r = agg_rank(a.count, key, valid[u]);
-    if (valid[u]) a.rank_out[jj[u]] = r;
+    agg_count(a.count, key, valid[u]);
   }
 }
 
@@ -972,23 +983,23 @@ void launch_fill_u32(uint32_t* p, long n, uint32_t v, hipStream_t s, const Batch
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n), 1, bat.n), dim3(kThreads), 0, s, p, n, v, bat);
 }
 
-void launch_keys(const float* pos, long np, const TileGeom& g, uint32_t* key, uint32_t* rank, uint32_t* count,
+void launch_keys(const float* pos, long np, const TileGeom& g, uint32_t* key, uint32_t* count,
                  hipStream_t s) {
   const int grid = (int)((np + kThreads - 1) / kThreads);
-  hipLaunchKernelGGL(k_keys, dim3(grid), dim3(kThreads), 0, s, pos, np, g, key, rank, count);
+  hipLaunchKernelGGL(k_keys, dim3(grid), dim3(kThreads), 0, s, pos, np, g, key, count);
 }
 
 long scan_scratch_words(long n) { return (n + kScanBlock - 1) / kScanBlock + 1; }
 
-void launch_scan(const uint32_t* count, long n, uint32_t* off, uint32_t* bsum, hipStream_t s, const BatchArg& bat) {
+void launch_scan(uint32_t* count, long n, uint32_t* off, uint32_t* bsum, hipStream_t s, const BatchArg& bat) {
   const int nb = (int)((n + kScanBlock - 1) / kScanBlock);
   hipLaunchKernelGGL(k_scan_local, dim3(nb, 1, bat.n), dim3(kThreads), 0, s, count, n, off, bsum, bat);
   hipLaunchKernelGGL(k_scan_top, dim3(1, 1, bat.n), dim3(kThreads), 0, s, bsum, nb, bat);
-  hipLaunchKernelGGL(k_scan_add, dim3(nb, 1, bat.n), dim3(kThreads), 0, s, off, n, bsum, nb, bat);
+  hipLaunchKernelGGL(k_scan_add, dim3(nb, 1, bat.n), dim3(kThreads), 0, s, off, count, n, bsum, nb, bat);
 }
 
 void launch_scatter(const ScatterArgs& a, hipStream_t s) {
-  // one particle per thread: the key -> offset -> store chain of each
+  // one particle per thread: the key -> cursor -> store chain of each
   // particle is latency bound, so many short waves overlap it best
   hipLaunchKernelGGL(k_scatter, dim3(grid_for(a.np, kThreads, 1 << 30), 1, a.bat.n), dim3(kThreads), 0, s, a);
 }

@@ -89,8 +89,9 @@ static __device__ __forceinline__ void cell_coords(int c, const TileGeom& g, int
   cx = c >> (g.lz + g.ly);
 }
 
-// Rank of this lane's key among all keys counted so far.  Lanes of a wave
-// with equal keys share one atomic: the groups are found with ballots
+// Rank of this lane's key among all keys counted so far (count[key] is
+// advanced by the group and its old value returned).  Lanes of a wave with
+// equal keys share one atomic: the groups are found with ballots
 // first, then every group leader issues its atomic in the same instruction,
 // so the wave waits for one atomic round trip however many distinct keys it
 // holds (particles in lattice order span several tiles per wave).  Must be
@@ -116,6 +117,23 @@ static __device__ __forceinline__ uint32_t agg_rank(uint32_t* count, uint32_t ke
   if (group) base = atomicAdd(&count[key], group);
   base = __shfl(base, my_leader);
   return valid ? base + my_prefix : 0u;
+}
+
+// count[key] += 1 for this lane's key, one atomic per group of equal keys in
+// the wave, none of them waited for (the counts are read by a later
+// kernel).  Must be called by the whole wave.
+static __device__ __forceinline__ void agg_count(uint32_t* count, uint32_t key, bool valid) {
+  uint64_t active = __ballot(valid);
+  const int lane = __lane_id();
+  uint32_t group = 0;
+  while (active) {
+    const int leader = __ffsll((unsigned long long)active) - 1;
+    const uint32_t lk = __shfl(key, leader);
+    const uint64_t mask = __ballot(valid && key == lk) & active;
+    if (lane == leader) group = (uint32_t)__popcll(mask);
+    active &= ~mask;
+  }
+  if (group) (void)atomicAdd(&count[key], group);
 }
 
 // The 27 particle ranges a paint workgroup gathers: for every lower
