@@ -31,7 +31,7 @@ def kernel_bytes(w, np3):
     """Algorithmic HBM bytes per launch of each timed kernel class (float32).
 
     Mesh field F = N^3 reals = N^2 (N/2) complex, plus the Nyquist plane of
-    N^2 complex values.  Particle state 24 B (x, p), id 4 B, key+rank 8 B.
+    N^2 complex values.  Particle state 24 B (x, p), id 4 B, sort key 4 B.
     The x_force and y_inv figures are those of meshes from 64^3 up, where F_y
     and F_z share one inverse x transform.
     """
@@ -45,8 +45,8 @@ def kernel_bytes(w, np3):
         "fft_y_inv": 2 * spec + 3 * spec,               # F_x and the shared factor in; F_x, F_y, F_z out
         "fft_z_c2r": 3 * (spec + real),                 # 3 fields
         "paint": 12.0 * np3 + real,                     # positions in, mesh out
-        "readout_kdk": 3 * real + np3 * (24 + 24 + 8),  # 3 meshes + x,p in; x,p,key,rank out
-        "scatter": np3 * (8 + 28 + 28),                 # key+rank, state in, state out
+        "readout_kdk": 3 * real + np3 * (24 + 24 + 4),  # 3 meshes + x,p in; x,p,key out
+        "scatter": np3 * (4 + 28 + 28),                 # key, state in, state out
     }
 
 
