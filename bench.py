@@ -409,6 +409,7 @@ def main():
             ent = {"total_ms": round(ms, 3), "launches": cnt, "avg_ms": round(avg, 4)}
             if name in nbytes:
                 ent["GBps"] = round(nbytes[name] / (avg / 1e3) / 1e9, 1)
+                ent["frac"] = round(ent["GBps"] / HBM_PEAK_GBS, 4)
             kernels[name] = ent
         dom = max((k for k in kernels if k in nbytes), key=lambda k: kernels[k]["total_ms"])
         ach = kernels[dom]["GBps"]

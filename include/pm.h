@@ -382,8 +382,10 @@ int pm_batch_member(pm_ctx* plan, int m, pm_ctx** out);
 int pm_batch_begin(pm_ctx* plan, int m, const double* h_a, int n_a, float* d_pos, float* d_mom, float* d_ckpt);
 
 /* One batched step of every running member with steps left: fills the
- * plan's device descriptor table from the members' scale factors and calls
- * pm_kdk_step_batched (a captured graph once pm_use_graphs(plan, 1)).
+ * plan's device descriptor table from the members' scale factors (the
+ * running members' descriptors packed at its front, so that no workgroup is
+ * launched for an idle slot) and calls pm_kdk_step_batched (a captured
+ * graph once pm_use_graphs(plan, 1), one per number of running members).
  * *h_stepped (may be NULL) receives the number of members advanced. */
 int pm_batch_advance(pm_ctx* plan, int* h_stepped);
 

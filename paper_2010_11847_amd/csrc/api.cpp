@@ -334,10 +334,20 @@ struct pm_ctx {
   std::vector<pm_ctx*> members;       // plan: members[0] == this
   pm_req_desc* desc_dev = nullptr;    // plan: device descriptor table (PM_MAX_BATCH entries)
   std::vector<pm_req_desc> desc_host;
-  hipGraphExec_t bgraph = nullptr;    // plan: one captured batched step over all slots
+  // plan: captured batched steps, one per number of running members (the
+  // descriptors of the running members are packed at the front of the
+  // table, so that a step launches no workgroups for idle slots)
+  std::vector<hipGraphExec_t> bgraphs;
+  void drop_bgraphs() {
+    for (auto& g : bgraphs)
+      if (g) {
+        (void)hipGraphExecDestroy(g);   // rebuilt on demand
+        g = nullptr;
+      }
+  }
   ~pm_ctx() {
     drop_graphs();
-    if (bgraph) (void)hipGraphExecDestroy(bgraph);   // teardown: nothing to report to
+    drop_bgraphs();   // teardown: nothing to report to
     for (size_t m = 1; m < members.size(); ++m) delete members[m];
   }
   float* pos_s[2] = {};
@@ -755,10 +765,7 @@ int pm_set_stream(pm_ctx* ctx, void* stream) {
   if (ctx->plan) return ctx->fail(PM_EINVAL, "set the stream on the plan, not on a member");
   for (pm_ctx* m : ctx->members) m->stream = reinterpret_cast<hipStream_t>(stream);
   ctx->stream = reinterpret_cast<hipStream_t>(stream);
-  if (ctx->bgraph) {   // a captured step belongs to its stream's capture
-    (void)hipGraphExecDestroy(ctx->bgraph);   // rebuilt on the next advance
-    ctx->bgraph = nullptr;
-  }
+  ctx->drop_bgraphs();   // a captured step belongs to its stream's capture: rebuilt on the next advance
   return PM_OK;
 }
 
@@ -1096,13 +1103,12 @@ int pm_batch_begin(pm_ctx* plan, int m, const double* h_a, int n_a, float* d_pos
 int pm_batch_advance(pm_ctx* plan, int* h_stepped) {
   if (!plan || plan->plan || plan->batch < 2) return PM_EINVAL;
   pm_ctx& p = *plan;
-  int k = 0;
+  int k = 0;   // running members, their descriptors packed at the front
   for (int m = 0; m < p.batch; ++m) {
     auto& r = p.members[m]->run;
-    pm_req_desc& d = p.desc_host[m];
-    d = pm_req_desc{};
-    d.member = -1;
     if (!r.active || r.step >= r.ns) continue;
+    pm_req_desc& d = p.desc_host[k];
+    d = pm_req_desc{};
     const int i = r.step;
     const size_t ck = (size_t)p.np3 * 3;
     d.member = m;
@@ -1119,30 +1125,31 @@ int pm_batch_advance(pm_ctx* plan, int* h_stepped) {
   if (h_stepped) *h_stepped = k;
   if (!k) return PM_OK;
   // pageable source: the copy has left desc_host when the call returns
-  hipError_t e = hipMemcpyAsync(p.desc_dev, p.desc_host.data(), (size_t)p.batch * sizeof(pm_req_desc),
+  hipError_t e = hipMemcpyAsync(p.desc_dev, p.desc_host.data(), (size_t)k * sizeof(pm_req_desc),
                                 hipMemcpyHostToDevice, p.stream);
   if (e != hipSuccess) return p.fail(PM_EHIP, std::string("pm_batch_advance: ") + hipGetErrorString(e));
   if (p.use_graphs && !p.prof.on) {
-    if (!p.bgraph) {
+    if (p.bgraphs.size() < (size_t)p.batch + 1) p.bgraphs.resize((size_t)p.batch + 1, nullptr);
+    hipGraphExec_t& ge = p.bgraphs[k];
+    if (!ge) {
       if (hipStreamBeginCapture(p.stream, hipStreamCaptureModeRelaxed) != hipSuccess)
         return p.fail(PM_EHIP, "pm_batch_advance: stream capture could not start (graphs need a non-default stream)");
-      p.batched_step(p.desc_dev, p.batch);
+      p.batched_step(p.desc_dev, k);
       hipGraph_t g = nullptr;
       const hipError_t e1 = hipStreamEndCapture(p.stream, &g);
-      const hipError_t e2 = e1 == hipSuccess ? hipGraphInstantiate(&p.bgraph, g, nullptr, nullptr, 0) : e1;
+      const hipError_t e2 = e1 == hipSuccess ? hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) : e1;
       if (g) (void)hipGraphDestroy(g);   // the instantiated graph keeps what it needs
       if (e2 != hipSuccess) {
-        p.bgraph = nullptr;
+        ge = nullptr;
         return p.fail(PM_EHIP, std::string("pm_batch_advance: graph capture failed: ") + hipGetErrorString(e2));
       }
     }
-    e = hipGraphLaunch(p.bgraph, p.stream);
+    e = hipGraphLaunch(ge, p.stream);
     if (e != hipSuccess) return p.fail(PM_EHIP, std::string("pm_batch_advance: ") + hipGetErrorString(e));
   } else {
-    p.batched_step(p.desc_dev, p.batch);
+    p.batched_step(p.desc_dev, k);
   }
-  for (int m = 0; m < p.batch; ++m)
-    if (p.desc_host[m].member >= 0) ++p.members[m]->run.step;
+  for (int i = 0; i < k; ++i) ++p.members[p.desc_host[i].member]->run.step;
   return p.check("pm_batch_advance");
 }
 
@@ -1520,8 +1527,7 @@ int pm_use_graphs(pm_ctx* ctx, int enable) {
   ctx->use_graphs = enable != 0;
   if (!ctx->use_graphs) {
     ctx->drop_graphs();
-    if (ctx->bgraph) (void)hipGraphExecDestroy(ctx->bgraph);   // rebuilt on demand
-    ctx->bgraph = nullptr;
+    ctx->drop_bgraphs();
   }
   return PM_OK;
 }

@@ -580,11 +580,16 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint_p(const float* __restri
 // voids.)
 constexpr int kReadoutPPT = 1;
 
-// EXT: the batched, LPT-frame (RO_COLA, RO_COLA_OUT) and RO_TO_ALT paths;
-// the plain instantiation compiles without them (fewer registers on the
-// path of every single-simulation step).
-template <bool EXT>
+// Instantiations by the flags they keep (the others compile away, fewer
+// registers and branches): VAR 0, a single simulation's steps and force
+// evaluations (no batch descriptors, no LPT frame, no RO_TO_ALT); VAR 1, the
+// batched step (descriptors, RO_KICK, RO_DRIFT, RO_KEYS, RO_TO_ALT and the
+// descriptors' checkpoints only); VAR 2, everything (the LPT frame).
+template <int VAR>
 __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
+  constexpr bool EXT = VAR != 0;
+  constexpr int kKeep = VAR == 0 ? ~(RO_COLA | RO_COLA_OUT | RO_TO_ALT)
+                                 : (VAR == 1 ? (RO_KICK | RO_DRIFT | RO_KEYS | RO_TO_ALT | RO_CKPT) : ~0);
   constexpr int PPT = kReadoutPPT;
   const TileGeom& g = a.g;
   const int n = g.n;
@@ -593,7 +598,7 @@ __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
   const bool keys = (a.flags & RO_KEYS) != 0;
   float kick_a = a.kick_a, kick_b = a.kick_b, drift = a.drift;
   float *ckpt_x = a.ckpt_x, *ckpt_p = a.ckpt_p;
-  if (!EXT) a.flags &= ~(RO_COLA | RO_COLA_OUT | RO_TO_ALT);
+  a.flags &= kKeep;
   if (EXT && a.bat.d) {   // uniform: this block's member, its factors and checkpoints
     const long bo = batch_bytes(a.bat);
     if (bo < 0) return;
@@ -612,7 +617,7 @@ __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
     drift = dsc.drift;
     ckpt_x = dsc.ckpt_x;
     ckpt_p = dsc.ckpt_p;
-    a.flags = (a.flags & ~RO_CKPT) | ((dsc.flags & PM_REQ_CKPT) && ckpt_x && ckpt_p ? RO_CKPT : 0);
+    a.flags = ((a.flags & ~RO_CKPT) | ((dsc.flags & PM_REQ_CKPT) && ckpt_x && ckpt_p ? RO_CKPT : 0)) & kKeep;
   }
   float4 cola = a.cola;
   if (a.steps) {   // uniform: the factors of step *step_i
@@ -621,7 +626,7 @@ __global__ __launch_bounds__(kThreads) void k_readout(ReadoutArgs a) {
     kick_a = f.x;
     kick_b = f.y;
     drift = f.z;
-    if (EXT && a.cola_steps) cola = a.cola_steps[si];
+    if (VAR == 2 && a.cola_steps) cola = a.cola_steps[si];
     if (a.flags & RO_CKPT) {
       ckpt_x = *a.ckpt_base + 2 * (long)si * a.ckpt_stride;
       ckpt_p = ckpt_x + a.ckpt_stride;
@@ -1043,11 +1048,13 @@ void launch_paint_weighted(const float* pos_sorted, const uint32_t* id_sorted, c
 void launch_readout(const ReadoutArgs& a, hipStream_t s) {
   const long per = (long)kThreads * kReadoutPPT;
   const int grid = (int)((a.np + per - 1) / per);
-  const bool ext = a.bat.d || (a.flags & (RO_COLA | RO_COLA_OUT | RO_TO_ALT));
-  if (ext)
-    hipLaunchKernelGGL(k_readout<true>, dim3(grid, 1, a.bat.n), dim3(kThreads), 0, s, a);
+  const int batched = RO_KICK | RO_DRIFT | RO_KEYS | RO_TO_ALT | RO_CKPT;
+  if (a.bat.d && !(a.flags & ~batched))
+    hipLaunchKernelGGL(k_readout<1>, dim3(grid, 1, a.bat.n), dim3(kThreads), 0, s, a);
+  else if (a.bat.d || (a.flags & (RO_COLA | RO_COLA_OUT | RO_TO_ALT)))
+    hipLaunchKernelGGL(k_readout<2>, dim3(grid, 1, a.bat.n), dim3(kThreads), 0, s, a);
   else
-    hipLaunchKernelGGL(k_readout<false>, dim3(grid), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(k_readout<0>, dim3(grid), dim3(kThreads), 0, s, a);
 }
 
 void launch_frame_shift(float* mom, const uint32_t* id, const float* psi1, const float* psi2, long np, float u1,

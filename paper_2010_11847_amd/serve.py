@@ -340,14 +340,19 @@ class BatchedExecutor:
         return job
 
     def tick(self, jobs: List[_Job]):
-        """One batched step per class with running requests (unless `depth`
-        steps of it are still in flight), then finish the requests whose
-        last step is enqueued."""
+        """One batched step per class with running requests (unless its
+        in-flight limit of steps is reached), then finish the requests whose
+        last step is enqueued.  The class with the most mesh cells among
+        those running keeps 2 `depth` steps in flight (its queue then
+        outlasts a longer pause of this loop), the lighter ones `depth`."""
         torch = self.torch
-        for p in self.plans.values():
+        active = [cls for cls, p in self.plans.items() if any(not j.ended for j in p.jobs.values())]
+        heavy = max((cls[1] for cls in active), default=0)
+        for cls, p in self.plans.items():
             while p.inflight and p.inflight[0].query():
                 p.inflight.popleft()
-            if not any(not j.ended for j in p.jobs.values()) or len(p.inflight) >= self.depth:
+            limit = 2 * self.depth if cls[1] >= heavy else self.depth
+            if cls not in active or len(p.inflight) >= limit:
                 continue
             with torch.cuda.stream(p.stream):
                 if p.batch.pm_batch_advance() > 0:

@@ -137,6 +137,28 @@ def test_init_lpt_with_tabulated_pk_matches_oracle(gpu):
     assert rel(gp, ap) < 5e-3
 
 
+def test_init_lpt_with_short_table_extrapolates_like_the_oracle(gpu):
+    # a table that ends at k = 0.4 h/Mpc, below the largest lattice mode of
+    # 32^3 particles in 200 Mpc/h (0.87 h/Mpc): the modes above it take the
+    # end segment's power law on both sides (and a table starting above the
+    # smallest nonzero mode, 0.031 h/Mpc, the first segment's)
+    banner("lpt with a tabulated P(k) extrapolated at both ends")
+    base = wl(64, 32)
+    ks = np.logspace(np.log10(0.05), np.log10(0.4), 24)
+    pk = cosmology.linear_power(ks, base.cosmo)
+    cos = replace(base.cosmo, pk_kind=inputs.PK_TABLE, pk_table=(tuple(ks), tuple(pk)))
+    w = replace(base, cosmo=cos)
+    c = ctx_for(w)
+    pos, mom = c.pm_init_lpt(w.seed, w.a_list[0])
+    gx, gp = to_np(pos), to_np(mom)
+    ox, op = lpt.generate(w)
+    d = float(np.abs(pm.min_image(gx - ox, 64)).max())
+    record("lpt_short_table_pos_max", d)
+    record("lpt_short_table_mom_rel", rel(gp, op))
+    assert d < 1e-4
+    assert rel(gp, op) < 1e-5
+
+
 def oracle_start(w):
     """The 2LPT start of the oracle, rounded to float32: the state both sides
     are fed (so that no oracle input comes from the GPU)."""
