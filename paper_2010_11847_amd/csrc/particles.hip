@@ -253,10 +253,11 @@ __global__ void k_scatter(ScatterArgs a) {
 }
 
 // ---- paint ---------------------------------------------------------------------
-// LDS accumulator order of a tile: x-blocked like the mesh,
-// li = ((cx/8 * TY + cy) * TZ + cz) * 8 + cx%8, so that the store walks
-// contiguous runs of the x-blocked mesh.  STD writes the plain [x][y][z]
-// layout instead (caller-visible meshes).
+// LDS accumulator order of a tile: tile_li (z fastest, z swizzled so that
+// the deposits of a wave spread over the banks); the store walks the cells
+// in the order of the x-blocked mesh (x%8 fastest), so that its global
+// stores are contiguous.  STD writes the plain [x][y][z] layout instead
+// (caller-visible meshes).
 //
 // The tile accumulates in 64-bit fixed point (ds_add_u64): LDS float atomics
 // run about 25x slower than integer ones on gfx950 (measured), and integer
