@@ -1216,9 +1216,9 @@ int pm_run_adjoint(pm_ctx* ctx, const double* h_a, int n_a, const float* d_ckpt,
         pmk::launch_readout_grad3(c.pos_s[0], c.id_s[0], np, c.ng, fmesh, pbar, (float)kj, xbar, c.stream);
       // term B: positions that paint the density, through G^T
       pmk::launch_absmax(pbar, 3 * np, c.misc, c.stream);
-      for (int d = 0; d < 3; ++d)
-        pmk::launch_paint_weighted(c.pos_s[0], c.id_s[0], c.off, c.tg, pbar, d, (float)kj, c.misc, c.mesh[d].r,
-                                   c.stream);
+      // the three channels in one launch (the meshes are equally spaced)
+      pmk::launch_paint_weighted(c.pos_s[0], c.id_s[0], c.off, c.tg, pbar, -1, (float)kj, c.misc, c.mesh[0].r,
+                                 c.stream, (long)(c.mesh[1].r - c.mesh[0].r));
       // pyramid force: F_d^T m = G_d^T (m - E R m) + 2^f E G_c,d^T R m
       // (R = REDUCE, E = EXPAND); the interleaved force mesh, read by term A
       // above, is free scratch here

@@ -147,9 +147,12 @@ void launch_step_inc(uint32_t* ctr, hipStream_t s);
 // *bits = bit pattern of max_i |v_i| over n floats
 void launch_absmax(const float* v, long n, uint32_t* bits, hipStream_t s);
 // x-blocked paint of signed masses wts[3 id + comp] * k (the adjoint's
-// cotangent channels); *maxbits must hold max |wts| (launch_absmax)
+// cotangent channels); *maxbits must hold max |wts| (launch_absmax).
+// comp < 0: the three components in one launch, component d into
+// out + d * out_stride.
 void launch_paint_weighted(const float* pos_sorted, const uint32_t* id_sorted, const uint32_t* off, const TileGeom& g,
-                           const float* wts, int comp, float k, const uint32_t* maxbits, float* out, hipStream_t s);
+                           const float* wts, int comp, float k, const uint32_t* maxbits, float* out, hipStream_t s,
+                           long out_stride = 0);
 void launch_kick_drift(float* pos, float* mom, const float* f, long np, float kick, float drift, float nmesh,
                        hipStream_t s);
 // mom[j] += u1 psi1[id[j]] + u2 psi2[id[j]] over np sorted particles (the

@@ -272,7 +272,8 @@ __global__ void k_scatter(ScatterArgs a) {
 struct PaintWeights {
   const uint32_t* id = nullptr;     // sorted particle ids
   const float* wts = nullptr;       // [np][3] in particle-id order
-  int comp = 0;
+  int comp = 0;                     // < 0: component blockIdx.y, into out + blockIdx.y * out_stride
+  long out_stride = 0;
   float k = 1.f;
   const uint32_t* maxbits = nullptr;   // bits of max |wts| (non-negative float)
 };
@@ -296,6 +297,10 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint(const float* __restrict
     pos = byte_adv(pos, bo);
     off = byte_adv(off, bo);
     out = byte_adv(out, bo);
+  }
+  if (WT && pw.comp < 0) {   // uniform: one component per blockIdx.y
+    pw.comp = (int)blockIdx.y;
+    out += blockIdx.y * pw.out_stride;
   }
   const int TX = g.tx, TY = g.ty, TZ = g.tz, n = g.n;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -906,12 +911,28 @@ __global__ void k_spec_pack(const float2* __restrict__ c, const float2* __restri
 
 // bits of max_i |v_i| (non-negative floats order like their bit patterns);
 // NaNs are ignored by fmaxf
+// (16-byte loads; one atomic per workgroup: the atomics on the one word
+// are serialized, so their number, not the loads, set the time of a small
+// launch)
 __global__ __launch_bounds__(kThreads) void k_absmax(const float* __restrict__ v, long n, uint32_t* __restrict__ bits) {
+  __shared__ float wm[kThreads / 64];
   float m = 0.f;
   const long stride = (long)gridDim.x * blockDim.x;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) m = fmaxf(m, fabsf(v[i]));
+  const long first = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long n4 = (reinterpret_cast<uintptr_t>(v) & 15) ? 0 : n >> 2;
+  const float4* v4 = reinterpret_cast<const float4*>(v);
+  for (long i = first; i < n4; i += stride) {
+    const float4 t = v4[i];
+    m = fmaxf(m, fmaxf(fmaxf(fabsf(t.x), fabsf(t.y)), fmaxf(fabsf(t.z), fabsf(t.w))));
+  }
+  for (long i = 4 * n4 + first; i < n; i += stride) m = fmaxf(m, fabsf(v[i]));
   for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
-  if ((threadIdx.x & 63) == 0) atomicMax(bits, __float_as_uint(m));
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kThreads / 64; ++w) m = fmaxf(m, wm[w]);
+    atomicMax(bits, __float_as_uint(m));
+  }
 }
 
 // plain [x][y][z] <-> x-blocked real mesh (caller-visible buffers); the
@@ -1031,19 +1052,21 @@ void launch_paint(const float* pos_sorted, const uint32_t* off, const TileGeom& 
 
 void launch_absmax(const float* v, long n, uint32_t* bits, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kThreads), 0, s, bits, 1L, 0u, BatchArg());
-  hipLaunchKernelGGL(k_absmax, dim3(grid_for(n, kThreads, 4096)), dim3(kThreads), 0, s, v, n, bits);
+  hipLaunchKernelGGL(k_absmax, dim3(grid_for(n, kThreads * 16, 2048)), dim3(kThreads), 0, s, v, n, bits);
 }
 
 void launch_paint_weighted(const float* pos_sorted, const uint32_t* id_sorted, const uint32_t* off, const TileGeom& g,
-                           const float* wts, int comp, float k, const uint32_t* maxbits, float* out, hipStream_t s) {
+                           const float* wts, int comp, float k, const uint32_t* maxbits, float* out, hipStream_t s,
+                           long out_stride) {
   PaintWeights pw;
   pw.id = id_sorted;
   pw.wts = wts;
   pw.comp = comp;
+  pw.out_stride = out_stride;
   pw.k = k;
   pw.maxbits = maxbits;
-  hipLaunchKernelGGL((k_paint<false, true>), dim3(g.ntiles), dim3(kPaintThreads), 0, s, pos_sorted, off, g, out, 1.f,
-                     0.f, pw, BatchArg());
+  hipLaunchKernelGGL((k_paint<false, true>), dim3(g.ntiles, comp < 0 ? 3 : 1), dim3(kPaintThreads), 0, s, pos_sorted,
+                     off, g, out, 1.f, 0.f, pw, BatchArg());
 }
 
 void launch_readout(const ReadoutArgs& a, hipStream_t s) {
