@@ -431,8 +431,10 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint(const float* __restrict
 // flight; while it stores tile k (and clears the accumulator cell by cell as
 // it reads it), every thread has its first particles of tile k+1 in flight.
 // A one-tile-per-workgroup launch waits for both round trips on every tile.
-// The cells, sums and stores are those of k_paint<false, false>; the tiles
-// are 16^3 cells.
+// The cells and sums are those of k_paint; the tiles are 16^3 cells.  STD
+// stores the plain [x][y][z] layout (caller-visible meshes), four
+// consecutive z per 16-byte store.
+template <bool STD>
 __global__ __launch_bounds__(kPaintThreads) void k_paint_p(const float* __restrict__ pos,
                                                            const uint32_t* __restrict__ off, TileGeom g,
                                                            float* __restrict__ out, float scale, float offset,
@@ -551,16 +553,25 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint_p(const float* __restri
 #pragma unroll
     for (int r4 = 0; r4 < kTileCells / 4 / kPaintThreads; ++r4) {
       const int c4 = threadIdx.x + r4 * kPaintThreads;
+      // x-blocked: four consecutive x of one (y, z) in the walk's order;
+      // STD ([x][y][z], caller-visible): four consecutive z of one (x, y)
       int cx, cy, cz;
-      store_walk(c4 << 2, g, cx, cy, cz);
+      if (STD) {
+        cz = (c4 & 3) << 2;
+        cy = (c4 >> 2) & 15;
+        cx = c4 >> 6;
+      } else {
+        store_walk(c4 << 2, g, cx, cy, cz);
+      }
       float v[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        unsigned long long& cell = acc[tile_li(cx + i, cy, cz, g)];
+        unsigned long long& cell = acc[STD ? tile_li(cx, cy, cz + i, g) : tile_li(cx + i, cy, cz, g)];
         v[i] = (float)((double)cell * 0x1p-31 * (double)scale + (double)offset);
         cell = 0ull;
       }
-      *reinterpret_cast<float4*>(out + blk_real(ox + cx, oy + cy, oz + cz, n)) = make_float4(v[0], v[1], v[2], v[3]);
+      const long o = STD ? ((long)(ox + cx) * n + (oy + cy)) * n + (oz + cz) : blk_real(ox + cx, oy + cy, oz + cz, n);
+      *reinterpret_cast<float4*>(out + o) = make_float4(v[0], v[1], v[2], v[3]);
     }
     if (!more) break;
     __syncthreads();   // the accumulator is clear and the old table free
@@ -1034,11 +1045,15 @@ void launch_scatter(const ScatterArgs& a, hipStream_t s) {
 void launch_paint(const float* pos_sorted, const uint32_t* off, const TileGeom& g, float* out, float scale,
                   float offset, bool std_layout, hipStream_t s, const BatchArg& bat) {
   const PaintWeights pw;
-  if (!std_layout && g.tx * g.ty * g.tz == kTileCells && g.ntiles >= 8) {
+  if (g.tx * g.ty * g.tz == kTileCells && g.ntiles >= 8) {
     // persistent: up to four workgroups per CU of 256 CUs, a multiple of 8
     const int nwg = g.ntiles < kPaintPersistentGroups ? g.ntiles : kPaintPersistentGroups;
-    hipLaunchKernelGGL(k_paint_p, dim3(nwg, 1, bat.n), dim3(kPaintThreads), 0, s, pos_sorted, off, g, out, scale,
-                       offset, bat);
+    if (std_layout)
+      hipLaunchKernelGGL(k_paint_p<true>, dim3(nwg, 1, bat.n), dim3(kPaintThreads), 0, s, pos_sorted, off, g, out,
+                         scale, offset, bat);
+    else
+      hipLaunchKernelGGL(k_paint_p<false>, dim3(nwg, 1, bat.n), dim3(kPaintThreads), 0, s, pos_sorted, off, g, out,
+                         scale, offset, bat);
     return;
   }
   const dim3 grid(g.ntiles, 1, bat.n);
