@@ -403,8 +403,9 @@ int pm_batch_end(pm_ctx* plan, int m, float* d_delta_final);
 
 /* ---- allocation-free force ----------------------------------------------
  * For callers that cannot allocate device memory or create a workspace
- * (code under stream capture, tight serving loops, harnesses that forbid
- * allocation).  The same computation as pm_force on a context created from
+ * (tight serving loops, harnesses that forbid allocation).  Not for code
+ * under stream capture: the call waits for its table upload.  The same
+ * computation as pm_force on a context created from
  * cfg, with the workspace taken from a fixed device array of
  * PM_STATIC_SCRATCH_BYTES bytes inside the library: every GPU the library
  * runs on holds one such array until the process ends.  The call allocates

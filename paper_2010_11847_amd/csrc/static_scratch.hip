@@ -1,6 +1,7 @@
 // PM force with the library's scratch in a fixed device array, for callers
-// that cannot allocate device memory (code under stream capture, tight
-// serving loops, harnesses that forbid allocation).
+// that cannot allocate device memory (tight serving loops, harnesses that
+// forbid allocation).  The call waits for its table upload, so it is not
+// for code under stream capture.
 //
 // The array below is the workspace pm_create would otherwise take from the
 // caller.  Each GPU the library runs on holds its own copy for the lifetime
