@@ -322,7 +322,9 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint(const float* __restrict
   }
   build_ranges(rt, off, tx, ty, tz, g);
   const uint32_t total = rt.pre[27];
-  constexpr int kBatch = 2;   // particles per thread whose loads are in flight together
+  // particles per thread whose loads are in flight together (the weighted
+  // form has a third dependent load, the weight by id)
+  constexpr int kBatch = WT ? 4 : 2;
   for (uint32_t base = 0; base < total; base += kPaintThreads * kBatch) {
     // all range searches (LDS) first, then all loads, so that the kBatch
     // loads of a thread are in flight together; positions past the end are
@@ -1067,7 +1069,8 @@ void launch_paint(const float* pos_sorted, const uint32_t* off, const TileGeom& 
 
 void launch_absmax(const float* v, long n, uint32_t* bits, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kThreads), 0, s, bits, 1L, 0u, BatchArg());
-  hipLaunchKernelGGL(k_absmax, dim3(grid_for(n, kThreads * 16, 2048)), dim3(kThreads), 0, s, v, n, bits);
+  // at least 64 elements per thread, at most 1024 workgroups (atomics)
+  hipLaunchKernelGGL(k_absmax, dim3(grid_for(n, kThreads * 64, 1024)), dim3(kThreads), 0, s, v, n, bits);
 }
 
 void launch_paint_weighted(const float* pos_sorted, const uint32_t* id_sorted, const uint32_t* off, const TileGeom& g,
