@@ -127,6 +127,16 @@ template <> struct Split<1024> { static constexpr int R1 = 32, R2 = 32; };
 // Columns per workgroup tile of the strided passes.
 template <int N> struct Cols { static constexpr int M = N >= 1024 ? 8 : 16; };
 
+// Tile of a y pass (columns of 8-byte values, rows 4N values apart): 16
+// columns fill each row's 128-byte line, so that no line is written half by
+// one workgroup and half by another.  At N = 1024 such a tile's exchange
+// takes 135 KB of LDS, one workgroup per CU, and runs on 512 threads so that
+// each thread keeps the work of the 8-column tile on 256 threads.
+template <int N> struct YTile {
+  static constexpr int M = 16;
+  static constexpr int TH = (N >= 1024) ? 512 : kThreads;
+};
+
 // twiddle exp(DIR 2 pi i e / N) from the table of exp(-2 pi i k / N)
 template <int DIR>
 __device__ __forceinline__ float2 tw_get(const float2* __restrict__ tw, int e) {
@@ -197,12 +207,12 @@ struct ColPass {
   BatchArg bat; // batched launches: blockIdx.z selects the member
 };
 
-template <int N, int M, int DIR, bool BLK>
-__global__ __launch_bounds__(kThreads) void k_fft_cols(ColPass p, const float2* __restrict__ tw) {
+template <int N, int M, int DIR, bool BLK, int TH = kThreads>
+__global__ __launch_bounds__(TH) void k_fft_cols(ColPass p, const float2* __restrict__ tw) {
   constexpr int R1 = Split<N>::R1, R2 = Split<N>::R2;
   constexpr int CS = BLK ? 8 : 1;
-  constexpr int IA = (M * R2 + kThreads - 1) / kThreads;
-  constexpr int IB = (M * R1 + kThreads - 1) / kThreads;
+  constexpr int IA = (M * R2 + TH - 1) / TH;
+  constexpr int IB = (M * R1 + TH - 1) / TH;
   __shared__ float2 lds[ColLds<N, M>::size];
   int tile = xcd_tile(blockIdx.x, gridDim.x);
   const bool is_plane = tile >= p.nb_main;
@@ -219,7 +229,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(ColPass p, const float2* 
   if constexpr (R2 == 1) {
 #pragma unroll
     for (int i = 0; i < IA; ++i) {
-      const int it = tid + i * kThreads;
+      const int it = tid + i * TH;
       const int m = it % M;
       if (it < M && c0 + m < g.ncols) {
         float2 v[R1];
@@ -234,7 +244,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(ColPass p, const float2* 
     constexpr int SA = ColLds<N, M>::SA;
 #pragma unroll
     for (int i = 0; i < IA; ++i) {
-      const int it = tid + i * kThreads;
+      const int it = tid + i * TH;
       if (it < M * R2) {
         const int m = it % M, j2 = it / M;
         const bool ok = c0 + m < g.ncols;
@@ -250,7 +260,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(ColPass p, const float2* 
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < IB; ++i) {
-      const int it = tid + i * kThreads;
+      const int it = tid + i * TH;
       if (it < M * R1) {
         const int m = it % M, l1 = it / M;
         float2 v[R2];
@@ -275,16 +285,16 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(ColPass p, const float2* 
 // R1 x R2 table in LDS, filled with the first loads, so that the second
 // transform's stage A issues no global load behind the first one's stores.
 // p.main/p.plane hold F_x, the shared factor (F_z) and F_y, in that order.
-template <int N, int M>
-__global__ __launch_bounds__(kThreads) void k_fft_cols_force(ColPass p, const float2* __restrict__ tw,
+template <int N, int M, int TH>
+__global__ __launch_bounds__(TH) void k_fft_cols_force(ColPass p, const float2* __restrict__ tw,
                                                              const float* __restrict__ dy_tab,
                                                              const float* __restrict__ dz_tab) {
   constexpr int R1 = Split<N>::R1, R2 = Split<N>::R2;
   static_assert(R2 > 1, "columns split over two stages");
-  constexpr int IA = (M * R2 + kThreads - 1) / kThreads;
-  constexpr int IB = (M * R1 + kThreads - 1) / kThreads;
+  constexpr int IA = (M * R2 + TH - 1) / TH;
+  constexpr int IB = (M * R1 + TH - 1) / TH;
   constexpr int SA = ColLds<N, M>::SA;
-  constexpr int IT = (R1 * R2 + kThreads - 1) / kThreads;
+  constexpr int IT = (R1 * R2 + TH - 1) / TH;
   __shared__ float2 lds[ColLds<N, M>::size];
   __shared__ float2 tws[R1 * R2];   // exp(+2 pi i j l / N), j < R2, l < R1
   int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -305,14 +315,14 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols_force(ColPass p, const fl
   float2 twv[IT];
 #pragma unroll
   for (int k = 0; k < IT; ++k) {
-    const int e = tid + k * kThreads;
+    const int e = tid + k * TH;
     if (e < R1 * R2) twv[k] = tw_get<1>(tw, (e / R1) * (e % R1));
   }
   float2 v0[IA][R1];
   float d[IA][R1];
 #pragma unroll
   for (int i = 0; i < IA; ++i) {
-    const int it = tid + i * kThreads;
+    const int it = tid + i * TH;
     const int m = it % M, j2 = it / M;
     const bool ok = it < M * R2 && c0 + m < g.ncols;
     if (shared) {
@@ -324,7 +334,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols_force(ColPass p, const fl
   }
 #pragma unroll
   for (int k = 0; k < IT; ++k) {
-    const int e = tid + k * kThreads;
+    const int e = tid + k * TH;
     if (e < R1 * R2) tws[e] = twv[k];
   }
   __syncthreads();
@@ -334,7 +344,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols_force(ColPass p, const fl
   auto stage_a = [&](bool row_factor) {
 #pragma unroll
     for (int i = 0; i < IA; ++i) {
-      const int it = tid + i * kThreads;
+      const int it = tid + i * TH;
       if (it < M * R2) {
         const int m = it % M, j2 = it / M;
         float2 v[R1];
@@ -351,7 +361,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols_force(ColPass p, const fl
   auto stage_b = [&](float2* dst, bool col_factor) {
 #pragma unroll
     for (int i = 0; i < IB; ++i) {
-      const int it = tid + i * kThreads;
+      const int it = tid + i * TH;
       if (it < M * R1) {
         const int m = it % M, l1 = it / M;
         const bool ok = c0 + m < g.ncols;
@@ -1406,7 +1416,8 @@ inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 template <int N, int DIR, bool BLK>
 void launch_cols(float2* const* dm, float2* const* dq, int nf, ColGeom gm, int nbm, ColGeom gp, int nbp,
                  const float2* tw, hipStream_t s, const BatchArg& bat = BatchArg()) {
-  constexpr int M = Cols<N>::M;
+  constexpr int M = BLK ? Cols<N>::M : YTile<N>::M;
+  constexpr int TH = BLK ? kThreads : YTile<N>::TH;
   ColPass p;
   for (int i = 0; i < 3; ++i) {
     p.main[i] = dm[i < nf ? i : 0];
@@ -1420,7 +1431,7 @@ void launch_cols(float2* const* dm, float2* const* dq, int nf, ColGeom gm, int n
   p.ntiles = p.nb_main + nbp * gp.ntc;
   p.bat = bat;
   dim3 grid(p.ntiles, nf, bat.n);
-  hipLaunchKernelGGL((k_fft_cols<N, M, DIR, BLK>), grid, dim3(kThreads), 0, s, p, tw);
+  hipLaunchKernelGGL((k_fft_cols<N, M, DIR, BLK, TH>), grid, dim3(TH), 0, s, p, tw);
 }
 
 // y pass over the main arrays and the Nyquist planes of nf fields
@@ -1577,7 +1588,7 @@ void xforce_t(const FftTables& t, Field* f, const SpecOp& op, hipStream_t s) {
 template <int N>
 void yforce(const FftTables& t, Field* f, hipStream_t s, const BatchArg& bat = BatchArg()) {
   if constexpr (Split<N>::R2 > 1) {
-    constexpr int M = Cols<N>::M;
+    constexpr int M = YTile<N>::M, TH = YTile<N>::TH;
     ColPass p;
     const int order[3] = {0, 2, 1};   // F_x, shared factor (F_z), F_y
     for (int i = 0; i < 3; ++i) {
@@ -1590,7 +1601,7 @@ void yforce(const FftTables& t, Field* f, hipStream_t s, const BatchArg& bat = B
     p.nb_main = (N / 8) * p.gm.ntc;
     p.bat = bat;
     const dim3 grid(p.nb_main + (N / 8) * p.gp.ntc, 2, bat.n);
-    hipLaunchKernelGGL((k_fft_cols_force<N, M>), grid, dim3(kThreads), 0, s, p, t.tw_n, t.dxy, t.dz);
+    hipLaunchKernelGGL((k_fft_cols_force<N, M, TH>), grid, dim3(TH), 0, s, p, t.tw_n, t.dxy, t.dz);
   }
 }
 
