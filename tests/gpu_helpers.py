@@ -37,10 +37,11 @@ def banner(msg):
     print(f"[gpu] {msg}", flush=True)
 
 
-def record(name, value):
-    """Keep a measured error; written to $PM_METRICS_DIR/parity_margins.json
-    when that variable is set (the committed margins come from such a run)."""
-    _METRICS[name] = float(value)
+def record(name, value, bar=None):
+    """Keep a measured error and the bar its test asserts (None: reported,
+    not asserted); written to $PM_METRICS_DIR/parity_margins.json when that
+    variable is set."""
+    _METRICS[name] = {"value": float(value), "bar": None if bar is None else float(bar)}
     out = os.environ.get("PM_METRICS_DIR")
     if out:
         os.makedirs(out, exist_ok=True)

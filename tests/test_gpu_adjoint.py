@@ -83,7 +83,7 @@ def test_adjoint_matches_oracle_on_same_trajectory(gpu, n_mesh, n_part, steps):
     g_o = A.grad_along_trajectory(xs, noise, w, target, SIGMA)
     r = rel(g_g, g_o)
     banner(f"  rel {r:.2e}")
-    record(f"adjoint_same_traj_{n_mesh}_{n_part}_{steps}", r)
+    record(f"adjoint_same_traj_{n_mesh}_{n_part}_{steps}", r, 1e-4)
     assert r < 1e-4
 
 
@@ -99,7 +99,7 @@ def test_adjoint_with_force_filters_on_same_trajectory(gpu, opts):
     g_g = gpu_grad_along(w, xs, noise, target)
     g_o = A.grad_along_trajectory(xs, noise, w, target, SIGMA, **opts)
     r = rel(g_g, g_o)
-    record("adjoint_same_traj_filters_" + "_".join(f"{k}{v}" for k, v in opts.items()), r)
+    record("adjoint_same_traj_filters_" + "_".join(f"{k}{v}" for k, v in opts.items()), r, 1e-4)
     assert r < 1e-4
 
 
@@ -126,7 +126,7 @@ def test_adjoint_vs_independent_fp64_run(gpu, n_mesh, n_part, steps):
     _, g_o = A.loss_and_grad(noise, w, target, SIGMA)
     g_g = gpu_run_and_grad(w, noise, target)
     r = rel(g_g, g_o)
-    record(f"independent_{n_mesh}_{n_part}_{steps}", r)
+    record(f"independent_{n_mesh}_{n_part}_{steps}", r, 1e-2)
     assert r < 1e-2
 
 
@@ -153,8 +153,8 @@ def test_adjoint_vs_central_fd(gpu):
     got = g_g.reshape(-1)[cells]
     scale = np.sqrt(np.mean(g_g ** 2))
     err = float(np.abs(got - refs).max() / scale)
-    record("fd_16_32_max_over_rms", err)
-    record("fd_16_32_rel_norm", rel(got, refs))
+    record("fd_16_32_max_over_rms", err, 1e-4)
+    record("fd_16_32_rel_norm", rel(got, refs), 1e-4)
     assert err < 1e-4
     assert rel(got, refs) < 1e-4
 

@@ -67,8 +67,8 @@ def test_force_and_paint_at_1024_match_golden(large_ctx, name):
     r_f = rel(f_s, ref)
     r_max = float(np.abs(f_s - ref).max() / np.sqrt(np.mean(ref ** 2)))
     banner(f"  delta rel {r_d:.2e}, force rel {r_f:.2e} (max element / rms {r_max:.2e})")
-    record(f"fullsize_{name}_delta_rel", r_d)
-    record(f"fullsize_{name}_force_rel", r_f)
+    record(f"fullsize_{name}_delta_rel", r_d, 1e-5)
+    record(f"fullsize_{name}_force_rel", r_f, 1e-5)
     record(f"fullsize_{name}_force_max_over_rms", r_max)
     assert r_d < 1e-5
     assert r_f < 1e-5
@@ -91,8 +91,8 @@ def test_adjoint_step_on_512_mesh_matches_golden(gpu):
     rx = rel(to_np(gx[parts]), np.array(g["x0_bar"]))
     rp = rel(to_np(gp[parts]), np.array(g["p0_bar"]))
     banner(f"  x0_bar rel {rx:.2e}, p0_bar rel {rp:.2e}")
-    record("adjoint_step_mesh512_x0bar_rel", rx)
-    record("adjoint_step_mesh512_p0bar_rel", rp)
+    record("adjoint_step_mesh512_x0bar_rel", rx, 1e-4)
+    record("adjoint_step_mesh512_p0bar_rel", rp, 1e-4)
     ctx.close()
     assert rx < 1e-4 and rp < 1e-4
 
@@ -114,9 +114,9 @@ def test_adjoint_sweep_128_on_256_matches_golden(gpu):
     rp = rel(to_np(gp[parts]), np.array(g["p0_bar"]))
     rn = rel(to_np(gn.reshape(-1)[cells]), np.array(g["grad_noise"]))
     banner(f"  x0_bar rel {rx:.2e}, p0_bar rel {rp:.2e}, noise gradient rel {rn:.2e}")
-    record("adjoint_c4b_x0bar_rel", rx)
-    record("adjoint_c4b_p0bar_rel", rp)
-    record("adjoint_c4b_grad_noise_rel", rn)
+    record("adjoint_c4b_x0bar_rel", rx, 1e-4)
+    record("adjoint_c4b_p0bar_rel", rp, 1e-4)
+    record("adjoint_c4b_grad_noise_rel", rn, 1e-4)
     ctx.close()
     assert rx < 1e-4 and rp < 1e-4 and rn < 1e-4
 
@@ -177,9 +177,9 @@ def test_adjoint_of_64_on_128_run_vs_fd_golden(gpu):
     banner(f"  along the float32-rounded oracle trajectory vs the oracle there: max / rms {err1:.2e}; "
            f"that gradient vs fd {err_traj_fd:.2e}; end to end vs fd {err2:.2e} (rel norm {rel(got2, fd):.2e}); "
            f"oracle (FP64 trajectory) vs fd {g['oracle_adjoint_vs_fd_max_rel_to_rms']:.2e}")
-    record("fd_c4a_gpu_vs_oracle_f32_trajectory_max_over_rms", err1)
+    record("fd_c4a_gpu_vs_oracle_f32_trajectory_max_over_rms", err1, 1e-5)
     record("fd_c4a_f32_trajectory_vs_fd_max_over_rms", err_traj_fd)
-    record("fd_c4a_end_to_end_max_over_rms", err2)
+    record("fd_c4a_end_to_end_max_over_rms", err2, 2e-3)
     record("fd_c4a_end_to_end_rel_norm", rel(got2, fd))
     c.close()
     assert err1 < 1e-5

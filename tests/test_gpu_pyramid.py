@@ -29,7 +29,7 @@ def test_pyramid_force_matches_oracle(gpu, n_mesh, levels, n_p):
     x = inputs.clustered_positions(n_p, n_mesh, seed=21 + n_mesh + levels)
     g = to_np(c.pm_force(to_dev(x)))
     o = P.force(x.astype(np.float64), n_mesh, n_p, OM, levels=levels)
-    record(f"pyramid_force_{n_mesh}_f{levels}_rel", rel(g, o))
+    record(f"pyramid_force_{n_mesh}_f{levels}_rel", rel(g, o), 1e-5)
     assert rel(g, o) < 1e-5
 
 
@@ -83,5 +83,5 @@ def test_pyramid_adjoint_matches_oracle_on_same_trajectory(gpu, n_mesh, n_part, 
     g_g = gpu_grad_along(w, xs, noise, target)
     g_o = A.grad_along_trajectory(xs, noise, w, target, SIGMA, pyramid_levels=levels)
     r = rel(g_g, g_o)
-    record(f"pyramid_adjoint_same_traj_{n_mesh}_{n_part}_f{levels}", r)
+    record(f"pyramid_adjoint_same_traj_{n_mesh}_{n_part}_f{levels}", r, 1e-4)
     assert r < 1e-4

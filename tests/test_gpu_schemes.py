@@ -21,8 +21,8 @@ def compare(name, gx, gp, ox, op_, n_mesh):
     rms = float(np.sqrt((d ** 2).sum(1).mean()))
     rp = rel(gp, op_)
     banner(f"  {name}: position rms {rms:.2e} cells, momentum rel {rp:.2e}")
-    record(f"{name}_pos_rms", rms)
-    record(f"{name}_mom_rel", rp)
+    record(f"{name}_pos_rms", rms, 1e-3)
+    record(f"{name}_mom_rel", rp, 1e-4)
     assert rms < 1e-3
     assert rp < 1e-4
 

@@ -83,8 +83,8 @@ def test_served_requests_match_the_oracle(gpu):
         rp = rel(p, np.array(r["p"]))
         banner(f"  request {r['rid']} ({r['n_part']}^3 / {r['n_mesh']}^3): positions rms {rms:.2e} cells, "
                f"momenta rel {rp:.2e}")
-        record(f"serve_class_{r['n_part']}_{r['n_mesh']}_pos_rms_cells", rms)
-        record(f"serve_class_{r['n_part']}_{r['n_mesh']}_mom_rel", rp)
+        record(f"serve_class_{r['n_part']}_{r['n_mesh']}_pos_rms_cells", rms, 1e-3)
+        record(f"serve_class_{r['n_part']}_{r['n_mesh']}_mom_rel", rp, 1e-2)
         assert rms < 1e-3
         assert rp < 1e-2
 
