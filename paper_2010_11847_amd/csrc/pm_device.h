@@ -44,7 +44,7 @@ static __device__ __forceinline__ float wrap_pos(float x, float n) {
 // eight consecutive keys; inside a bin the half-tile blocks keep the
 // particles that one wave reads out close together in the force mesh.
 static __device__ __forceinline__ uint32_t tile_key(int ix, int iy, int iz, const TileGeom& g) {
-  const uint32_t tile = ((((uint32_t)ix >> g.lx) << g.lny | ((uint32_t)iy >> g.ly)) << g.lnz) | ((uint32_t)iz >> g.lz);
+  const uint32_t tile = ((((uint32_t)iz >> g.lz) << g.lny | ((uint32_t)iy >> g.ly)) << g.lnx) | ((uint32_t)ix >> g.lx);
   const uint32_t lx = (uint32_t)ix & (g.tx - 1), ly = (uint32_t)iy & (g.ty - 1), lz = (uint32_t)iz & (g.tz - 1);
   const uint32_t c = (uint32_t)(lx == (uint32_t)g.tx - 1) | ((uint32_t)(ly == (uint32_t)g.ty - 1) << 1) |
                      ((uint32_t)(lz == (uint32_t)g.tz - 1) << 2);
@@ -54,9 +54,9 @@ static __device__ __forceinline__ uint32_t tile_key(int ix, int iy, int iz, cons
 
 // (x, y, z) tile coordinates of a flattened tile index
 static __device__ __forceinline__ void tile_coords(int tile, const TileGeom& g, int& tx, int& ty, int& tz) {
-  tz = tile & (g.ntz - 1);
-  ty = (tile >> g.lnz) & (g.nty - 1);
-  tx = tile >> (g.lnz + g.lny);
+  tx = tile & (g.ntx - 1);
+  ty = (tile >> g.lnx) & (g.nty - 1);
+  tz = tile >> (g.lnx + g.lny);
 }
 
 // LDS slot of tile cell (cx, cy, cz): z fastest, rows of tz cells, with the
@@ -163,7 +163,7 @@ static __device__ __forceinline__ void range_loads(const uint32_t* __restrict__ 
       }
   const int sx = (tx - (e_sel & 1)) & (g.ntx - 1), sy = (ty - ((e_sel >> 1) & 1)) & (g.nty - 1),
             sz = (tz - ((e_sel >> 2) & 1)) & (g.ntz - 1);
-  const uint32_t bin = (((uint32_t)sx * g.nty + sy) * g.ntz + sz) * 8 + c_sel;
+  const uint32_t bin = (((uint32_t)sz * g.nty + sy) * g.ntx + sx) * 8 + c_sel;
   b0 = off[bin * 8];       // its eight half-tile keys
   b1 = off[bin * 8 + 8];
 }
