@@ -11,7 +11,7 @@
 namespace pmk {
 
 // Tiles of tx * ty * tz cells (tz is the contiguous axis): ntx * nty * ntz
-// tiles, tile index (ix * nty + iy) * ntz + iz.
+// tiles, numbered x fastest: (t_z * nty + t_y) * ntx + t_x.
 // Every size here is a power of two; the log2 fields let kernels split
 // indices with shifts and masks instead of integer division.
 struct TileGeom {
