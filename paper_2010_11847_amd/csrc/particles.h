@@ -11,7 +11,8 @@
 namespace pmk {
 
 // Tiles of tx * ty * tz cells (tz is the contiguous axis): ntx * nty * ntz
-// tiles, numbered x fastest: (t_z * nty + t_y) * ntx + t_x.
+// tiles (ntx = nty = ntz), numbered along a Morton curve (tile_index in
+// pm_device.h).
 // Every size here is a power of two; the log2 fields let kernels split
 // indices with shifts and masks instead of integer division.
 struct TileGeom {

@@ -43,8 +43,32 @@ static __device__ __forceinline__ float wrap_pos(float x, float n) {
 // upper half of the tile along d.  Paint gathers whole (tile, class) bins,
 // eight consecutive keys; inside a bin the half-tile blocks keep the
 // particles that one wave reads out close together in the force mesh.
+// Tiles are numbered along a Morton (Z-order) curve: the bits of (t_x,
+// t_y, t_z) interleaved, t_x lowest (the tiling is cubic, ntx = nty = ntz,
+// a power of two up to 2^10).  Tiles close in the sort are then close in
+// all three directions, so that the neighbours whose lines a tile shares
+// (force-mesh faces, count lines, bins) were walked recently.
+static __device__ __forceinline__ uint32_t morton_spread(uint32_t v) {   // bit i -> bit 3i, v < 2^10
+  v = (v | (v << 16)) & 0x030000FFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+static __device__ __forceinline__ uint32_t morton_compact(uint32_t v) {   // bit 3i -> bit i
+  v &= 0x09249249u;
+  v = (v ^ (v >> 2)) & 0x030C30C3u;
+  v = (v ^ (v >> 4)) & 0x0300F00Fu;
+  v = (v ^ (v >> 8)) & 0xFF0000FFu;
+  v = (v ^ (v >> 16)) & 0x000003FFu;
+  return v;
+}
+static __device__ __forceinline__ uint32_t tile_index(uint32_t tx, uint32_t ty, uint32_t tz) {
+  return morton_spread(tx) | (morton_spread(ty) << 1) | (morton_spread(tz) << 2);
+}
+
 static __device__ __forceinline__ uint32_t tile_key(int ix, int iy, int iz, const TileGeom& g) {
-  const uint32_t tile = ((((uint32_t)iz >> g.lz) << g.lny | ((uint32_t)iy >> g.ly)) << g.lnx) | ((uint32_t)ix >> g.lx);
+  const uint32_t tile = tile_index((uint32_t)ix >> g.lx, (uint32_t)iy >> g.ly, (uint32_t)iz >> g.lz);
   const uint32_t lx = (uint32_t)ix & (g.tx - 1), ly = (uint32_t)iy & (g.ty - 1), lz = (uint32_t)iz & (g.tz - 1);
   const uint32_t c = (uint32_t)(lx == (uint32_t)g.tx - 1) | ((uint32_t)(ly == (uint32_t)g.ty - 1) << 1) |
                      ((uint32_t)(lz == (uint32_t)g.tz - 1) << 2);
@@ -54,9 +78,10 @@ static __device__ __forceinline__ uint32_t tile_key(int ix, int iy, int iz, cons
 
 // (x, y, z) tile coordinates of a flattened tile index
 static __device__ __forceinline__ void tile_coords(int tile, const TileGeom& g, int& tx, int& ty, int& tz) {
-  tx = tile & (g.ntx - 1);
-  ty = (tile >> g.lnx) & (g.nty - 1);
-  tz = tile >> (g.lnx + g.lny);
+  (void)g;
+  tx = (int)morton_compact((uint32_t)tile);
+  ty = (int)morton_compact((uint32_t)tile >> 1);
+  tz = (int)morton_compact((uint32_t)tile >> 2);
 }
 
 // LDS slot of tile cell (cx, cy, cz): z fastest, rows of tz cells, with the
@@ -163,7 +188,7 @@ static __device__ __forceinline__ void range_loads(const uint32_t* __restrict__ 
       }
   const int sx = (tx - (e_sel & 1)) & (g.ntx - 1), sy = (ty - ((e_sel >> 1) & 1)) & (g.nty - 1),
             sz = (tz - ((e_sel >> 2) & 1)) & (g.ntz - 1);
-  const uint32_t bin = (((uint32_t)sz * g.nty + sy) * g.ntx + sx) * 8 + c_sel;
+  const uint32_t bin = tile_index((uint32_t)sx, (uint32_t)sy, (uint32_t)sz) * 8 + c_sel;
   b0 = off[bin * 8];       // its eight half-tile keys
   b1 = off[bin * 8 + 8];
 }
