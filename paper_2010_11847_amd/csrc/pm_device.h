@@ -39,8 +39,9 @@ static __device__ __forceinline__ float wrap_pos(float x, float n) {
 // Sort key of a particle with CIC base cell (ix, iy, iz):
 //   ((tile * 8 + class) * 8 + sub)
 // class bit d: the base cell is the last of its tile along d (the particle
-// also deposits into the next tile); sub bit d: the base cell lies in the
-// upper half of the tile along d.  Paint gathers whole (tile, class) bins,
+// also deposits into the next tile); sub bit d (x lowest, as in the tile
+// numbering): the base cell lies in the upper half of the tile along d.
+// Paint gathers whole (tile, class) bins,
 // eight consecutive keys; inside a bin the half-tile blocks keep the
 // particles that one wave reads out close together in the force mesh.
 // Tiles are numbered along a Morton (Z-order) curve: the bits of (t_x,
@@ -72,7 +73,7 @@ static __device__ __forceinline__ uint32_t tile_key(int ix, int iy, int iz, cons
   const uint32_t lx = (uint32_t)ix & (g.tx - 1), ly = (uint32_t)iy & (g.ty - 1), lz = (uint32_t)iz & (g.tz - 1);
   const uint32_t c = (uint32_t)(lx == (uint32_t)g.tx - 1) | ((uint32_t)(ly == (uint32_t)g.ty - 1) << 1) |
                      ((uint32_t)(lz == (uint32_t)g.tz - 1) << 2);
-  const uint32_t sub = ((lx >> (g.lx - 1)) << 2) | ((ly >> (g.ly - 1)) << 1) | (lz >> (g.lz - 1));
+  const uint32_t sub = ((lz >> (g.lz - 1)) << 2) | ((ly >> (g.ly - 1)) << 1) | (lx >> (g.lx - 1));
   return (tile * 8u + c) * 8u + sub;
 }
 
