@@ -407,13 +407,17 @@ struct pm_ctx {
   }
 
   // counting sort of np particles (caller order) into sorted buffer dst
+  // (a first sort: its input is in the caller's order, lattice order when
+  // it holds n_part^3 particles, which the key and scatter passes walk brick
+  // by brick)
   void sort(const float* pos, const float* mom, const uint32_t* id, long np, int dst) {
+    const int lat_ln = np == np3 ? __builtin_ctz((unsigned)npart) : -1;
     timed(PC_FILL, [&] { pmk::launch_fill_u32(count, L.n_keys, 0u, stream); });
-    timed(PC_KEYS, [&] { pmk::launch_keys(pos, np, tg, key, count, stream); });
-    finish_sort(pos, mom, id, np, dst);
+    timed(PC_KEYS, [&] { pmk::launch_keys(pos, np, tg, key, count, stream, lat_ln); });
+    finish_sort(pos, mom, id, np, dst, lat_ln);
   }
   // scan + scatter once the keys and their counts are known
-  void finish_sort(const float* pos, const float* mom, const uint32_t* id, long np, int dst) {
+  void finish_sort(const float* pos, const float* mom, const uint32_t* id, long np, int dst, int lat_ln = -1) {
     timed(PC_SCAN, [&] { pmk::launch_scan(count, L.n_keys, off, bsum, stream); });
     pmk::ScatterArgs a;
     a.np = np;
@@ -425,6 +429,7 @@ struct pm_ctx {
     a.pos_out = pos_s[dst];
     a.mom_out = mom ? mom_s[dst] : nullptr;
     a.id_out = id_s[dst];
+    a.lat_ln = lat_ln;
     timed(PC_SCATTER, [&] { pmk::launch_scatter(a, stream); });
   }
   // overdensity of the sorted particles; std_layout: caller-visible [x][y][z]

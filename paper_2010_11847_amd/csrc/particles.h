@@ -55,6 +55,7 @@ struct ScatterArgs {
   float* pos_out = nullptr;
   float* mom_out = nullptr;
   uint32_t* id_out = nullptr;
+  int lat_ln = -1;                 // >= 0: the source is in lattice order over 2^(3 lat_ln) particles
   BatchArg bat;                    // batched: every pointer is a workspace pointer of member 0
 };
 
@@ -132,7 +133,10 @@ void launch_lpt_delta2(float* const* phi6, long n, float* out, hipStream_t s);
 void launch_lpt_particles(const LptParticleArgs& a, hipStream_t s);
 void launch_fill_u32(uint32_t* p, long n, uint32_t v, hipStream_t s, const BatchArg& bat = BatchArg());
 // tile keys of np particles, counted per key into count (zeroed first)
-void launch_keys(const float* pos, long np, const TileGeom& g, uint32_t* key, uint32_t* count, hipStream_t s);
+// lat_ln >= 0: the np = 2^(3 lat_ln) particles are in lattice order, and the
+// pass walks them brick by brick (lattice_order in pm_device.h)
+void launch_keys(const float* pos, long np, const TileGeom& g, uint32_t* key, uint32_t* count, hipStream_t s,
+                 int lat_ln = -1);
 long scan_scratch_words(long n);
 // off = exclusive scan of count[0..n), off[n] = total; count[0..n) is then
 // overwritten with a copy of off[0..n) (the scatter's cursors)

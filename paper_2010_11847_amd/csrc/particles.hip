@@ -100,9 +100,11 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, long n, uint32_t v, BatchAr
 }
 
 __global__ __launch_bounds__(kThreads) void k_keys(const float* __restrict__ pos, long np, TileGeom g,
-                                                   uint32_t* __restrict__ key, uint32_t* __restrict__ count) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = i < np;
+                                                   uint32_t* __restrict__ key, uint32_t* __restrict__ count,
+                                                   int lat_ln) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = t < np;
+  const long i = valid && lat_ln >= 0 ? lattice_order(t, lat_ln) : t;
   uint32_t k = 0;
   if (valid) {
     int ix, iy, iz;
@@ -227,9 +229,10 @@ __global__ void k_scatter(ScatterArgs a) {
   // over the block: the whole wave takes part in the key grouping.
   const long stride = (long)gridDim.x * blockDim.x;
   for (long i0 = (long)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x; i0 < a.np; i0 += stride) {
-    const long i = i0 + threadIdx.x;
-    const bool valid = i < a.np;
-    const long ic = valid ? i : a.np - 1;
+    const long t = i0 + threadIdx.x;
+    const bool valid = t < a.np;
+    const long tc = valid ? t : a.np - 1;
+    const long ic = a.lat_ln >= 0 ? lattice_order(tc, a.lat_ln) : tc;
     const uint32_t key = a.key[ic];
     float x[3], p[3] = {0.f, 0.f, 0.f};
 #pragma unroll
@@ -1024,9 +1027,9 @@ void launch_fill_u32(uint32_t* p, long n, uint32_t v, hipStream_t s, const Batch
 }
 
 void launch_keys(const float* pos, long np, const TileGeom& g, uint32_t* key, uint32_t* count,
-                 hipStream_t s) {
+                 hipStream_t s, int lat_ln) {
   const int grid = (int)((np + kThreads - 1) / kThreads);
-  hipLaunchKernelGGL(k_keys, dim3(grid), dim3(kThreads), 0, s, pos, np, g, key, count);
+  hipLaunchKernelGGL(k_keys, dim3(grid), dim3(kThreads), 0, s, pos, np, g, key, count, lat_ln);
 }
 
 long scan_scratch_words(long n) { return (n + kScanBlock - 1) / kScanBlock + 1; }

@@ -68,6 +68,20 @@ static __device__ __forceinline__ uint32_t tile_index(uint32_t tx, uint32_t ty, 
   return morton_spread(tx) | (morton_spread(ty) << 1) | (morton_spread(tz) << 2);
 }
 
+// Particle visited by thread t of a pass over n^3 particles in lattice order
+// (index (q_x n + q_y) n + q_z, n = 2^ln >= 4): each wave takes one 4^3
+// brick of lattice sites, and the bricks follow the Morton curve of the
+// tiles, so that a wave's particles (still near their sites) share a sort
+// key and consecutive waves fill consecutive destinations.  A bijection on
+// [0, n^3) whatever the positions.
+static __device__ __forceinline__ long lattice_order(long t, int ln) {
+  const uint32_t lane = (uint32_t)t & 63u, brick = (uint32_t)(t >> 6);
+  const uint32_t qx = (morton_compact(brick) << 2) | (lane >> 4);
+  const uint32_t qy = (morton_compact(brick >> 1) << 2) | ((lane >> 2) & 3u);
+  const uint32_t qz = (morton_compact(brick >> 2) << 2) | (lane & 3u);
+  return ((long)qx << (2 * ln)) | ((long)qy << ln) | (long)qz;
+}
+
 static __device__ __forceinline__ uint32_t tile_key(int ix, int iy, int iz, const TileGeom& g) {
   const uint32_t tile = tile_index((uint32_t)ix >> g.lx, (uint32_t)iy >> g.ly, (uint32_t)iz >> g.lz);
   const uint32_t lx = (uint32_t)ix & (g.tx - 1), ly = (uint32_t)iy & (g.ty - 1), lz = (uint32_t)iz & (g.tz - 1);
