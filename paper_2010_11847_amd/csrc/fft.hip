@@ -157,7 +157,9 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 // ntc column tiles.  The y pass walks columns fastest: neighbouring tiles
 // share 128-byte lines.  The x passes walk batches (ky rows) fastest: the
 // workgroups in flight then spread over many rows of every x block instead
-// of a few (measured 10% faster at 1024^3).
+// of a few (measured 10% faster at 1024^3); the force x pass takes its main
+// array in blocks of 8 ky rows instead, eight column tiles of each in flight
+// together (1.5% faster again).
 template <bool BATCH_FAST>
 __device__ __forceinline__ void tile_bc(int tile, int nbat, int ntc, int M, int& b, int& c0) {
   if (BATCH_FAST) {
@@ -1118,7 +1120,13 @@ __global__ __launch_bounds__(kThreads) void k_fft_x_force(FusedArgs a) {
   if (mode) tile -= a.nb_main;
   const ColGeom& g = mode ? a.gp : a.gm;
   int b, c0;
-  tile_bc<true>(tile, mode ? ((int)gridDim.x - a.nb_main) / g.ntc : a.nb_main / g.ntc, g.ntc, M, b, c0);
+  if (mode == 0) {   // blocks of 8 ky rows, walked column chunk by column chunk
+    const int blk = tile / (8 * g.ntc), r = tile - blk * (8 * g.ntc);
+    b = blk * 8 + (r & 7);
+    c0 = (r >> 3) * M;
+  } else {
+    tile_bc<true>(tile, ((int)gridDim.x - a.nb_main) / g.ntc, g.ntc, M, b, c0);
+  }
   const long bo = batch_bytes(a.bat);
   if (bo < 0) return;
   const long off = b * g.sb + (long)c0 * 8 + bo / (long)sizeof(float2);
