@@ -99,6 +99,9 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, long n, uint32_t v, BatchAr
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
+// Sort key of each particle, counted per key (one atomic per group of equal
+// keys in the wave); particles in lattice order (lat_ln >= 0) are visited
+// brick by brick, so that a wave holds a few keys instead of eight tiles'.
 __global__ __launch_bounds__(kThreads) void k_keys(const float* __restrict__ pos, long np, TileGeom g,
                                                    uint32_t* __restrict__ key, uint32_t* __restrict__ count,
                                                    int lat_ln) {
@@ -209,7 +212,8 @@ __global__ __launch_bounds__(kThreads) void k_scan_add(uint32_t* __restrict__ of
 // integers and the readout is per particle).  Every load of a particle
 // (key, state, id) is issued before the atomic, and pinned: left to the
 // compiler, the state loads follow it and add a third round trip to the
-// chain.
+// chain.  A source in lattice order (a first sort, lat_ln >= 0) is walked
+// brick by brick (lattice_order), so that a wave's particles share keys.
 __global__ void k_scatter(ScatterArgs a) {
   if (a.bat.d) {
     const long bo = batch_bytes(a.bat);
