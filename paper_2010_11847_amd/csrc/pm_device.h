@@ -20,7 +20,7 @@ static __device__ __forceinline__ int xcd_tile(int b, int nb) {
 }
 
 // Base cell (periodic) and fractional offset of one coordinate.
-static __device__ __forceinline__ void cic_base(float x, int n, int& i, float& t) {
+static __host__ __device__ __forceinline__ void cic_base(float x, int n, int& i, float& t) {
   const float f = floorf(x);
   t = x - f;
   i = ((int)f) & (n - 1);
@@ -30,7 +30,7 @@ static __device__ __forceinline__ void cic_base(float x, int n, int& i, float& t
 // power of two, so x / n is exact); a result that rounds onto n becomes 0.
 // Non-finite positions (invalid input) become 0 so that every later index
 // stays inside the mesh.
-static __device__ __forceinline__ float wrap_pos(float x, float n) {
+static __host__ __device__ __forceinline__ float wrap_pos(float x, float n) {
   if (x < 0.f || x >= n) x -= n * floorf(x * (1.f / n));
   if (!(x >= 0.f && x < n)) x = 0.f;
   return x;
@@ -49,14 +49,14 @@ static __device__ __forceinline__ float wrap_pos(float x, float n) {
 // a power of two up to 2^10).  Tiles close in the sort are then close in
 // all three directions, so that the neighbours whose lines a tile shares
 // (force-mesh faces, count lines, bins) were walked recently.
-static __device__ __forceinline__ uint32_t morton_spread(uint32_t v) {   // bit i -> bit 3i, v < 2^10
+static __host__ __device__ __forceinline__ uint32_t morton_spread(uint32_t v) {   // bit i -> bit 3i, v < 2^10
   v = (v | (v << 16)) & 0x030000FFu;
   v = (v | (v << 8)) & 0x0300F00Fu;
   v = (v | (v << 4)) & 0x030C30C3u;
   v = (v | (v << 2)) & 0x09249249u;
   return v;
 }
-static __device__ __forceinline__ uint32_t morton_compact(uint32_t v) {   // bit 3i -> bit i
+static __host__ __device__ __forceinline__ uint32_t morton_compact(uint32_t v) {   // bit 3i -> bit i
   v &= 0x09249249u;
   v = (v ^ (v >> 2)) & 0x030C30C3u;
   v = (v ^ (v >> 4)) & 0x0300F00Fu;
@@ -64,7 +64,7 @@ static __device__ __forceinline__ uint32_t morton_compact(uint32_t v) {   // bit
   v = (v ^ (v >> 16)) & 0x000003FFu;
   return v;
 }
-static __device__ __forceinline__ uint32_t tile_index(uint32_t tx, uint32_t ty, uint32_t tz) {
+static __host__ __device__ __forceinline__ uint32_t tile_index(uint32_t tx, uint32_t ty, uint32_t tz) {
   return morton_spread(tx) | (morton_spread(ty) << 1) | (morton_spread(tz) << 2);
 }
 
@@ -74,7 +74,7 @@ static __device__ __forceinline__ uint32_t tile_index(uint32_t tx, uint32_t ty, 
 // tiles, so that a wave's particles (still near their sites) share a sort
 // key and consecutive waves fill consecutive destinations.  A bijection on
 // [0, n^3) whatever the positions.
-static __device__ __forceinline__ long lattice_order(long t, int ln) {
+static __host__ __device__ __forceinline__ long lattice_order(long t, int ln) {
   const uint32_t lane = (uint32_t)t & 63u, brick = (uint32_t)(t >> 6);
   const uint32_t qx = (morton_compact(brick) << 2) | (lane >> 4);
   const uint32_t qy = (morton_compact(brick >> 1) << 2) | ((lane >> 2) & 3u);
@@ -82,7 +82,7 @@ static __device__ __forceinline__ long lattice_order(long t, int ln) {
   return ((long)qx << (2 * ln)) | ((long)qy << ln) | (long)qz;
 }
 
-static __device__ __forceinline__ uint32_t tile_key(int ix, int iy, int iz, const TileGeom& g) {
+static __host__ __device__ __forceinline__ uint32_t tile_key(int ix, int iy, int iz, const TileGeom& g) {
   const uint32_t tile = tile_index((uint32_t)ix >> g.lx, (uint32_t)iy >> g.ly, (uint32_t)iz >> g.lz);
   const uint32_t lx = (uint32_t)ix & (g.tx - 1), ly = (uint32_t)iy & (g.ty - 1), lz = (uint32_t)iz & (g.tz - 1);
   const uint32_t c = (uint32_t)(lx == (uint32_t)g.tx - 1) | ((uint32_t)(ly == (uint32_t)g.ty - 1) << 1) |
@@ -92,7 +92,7 @@ static __device__ __forceinline__ uint32_t tile_key(int ix, int iy, int iz, cons
 }
 
 // (x, y, z) tile coordinates of a flattened tile index
-static __device__ __forceinline__ void tile_coords(int tile, const TileGeom& g, int& tx, int& ty, int& tz) {
+static __host__ __device__ __forceinline__ void tile_coords(int tile, const TileGeom& g, int& tx, int& ty, int& tz) {
   (void)g;
   tx = (int)morton_compact((uint32_t)tile);
   ty = (int)morton_compact((uint32_t)tile >> 1);
@@ -191,7 +191,7 @@ struct RangeTable {
 // early: range_loads (lanes r < 27 of wave 0) reads the offsets of range r,
 // range_publish (the whole of wave 0) scans the lengths with lane shuffles
 // and writes the table; a barrier must follow before other waves read it.
-static __device__ __forceinline__ void range_loads(const uint32_t* __restrict__ off, int tx, int ty, int tz,
+static __host__ __device__ __forceinline__ void range_loads(const uint32_t* __restrict__ off, int tx, int ty, int tz,
                                                    const TileGeom& g, int r, uint32_t& b0, uint32_t& b1) {
   // enumerate (e, cls) pairs with (cls & e) == e in a fixed order
   int k = 0, e_sel = 0, c_sel = 0;

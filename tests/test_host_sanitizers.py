@@ -7,7 +7,10 @@ UndefinedBehaviorSanitizer, on the CPU:
   it with the sanitizer runtime preloaded into a fresh interpreter;
 * the float64 cosmology (cosmo.cpp) driven by a host-only program built
   with both sanitizers (every P(k) kind, growth, step factors of every
-  integrator).
+  integrator);
+* the sort's index algebra (tile numbering, keys, paint bins, the first
+  sort's lattice walk, the periodic wrap of pm_device.h) run on the host,
+  its host code built with both sanitizers.
 """
 import os
 import shutil
@@ -48,3 +51,19 @@ def test_host_cosmology_under_sanitizers(tmp_path):
                        env=dict(os.environ, ASAN_OPTIONS="detect_leaks=1", UBSAN_OPTIONS="halt_on_error=1"))
     assert r.returncode == 0, r.stdout + r.stderr
     assert "host cosmology check ok" in r.stdout
+
+
+@pytest.mark.skipif(not os.path.exists("/opt/rocm/bin/hipcc"), reason="no hipcc")
+def test_sort_index_algebra_on_host(tmp_path):
+    exe = tmp_path / "host_order_check"
+    cmd = ["/opt/rocm/bin/hipcc", "-x", "hip", "-std=c++17", "-O1", "-g", "--offload-arch=gfx950",
+           "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-sanitize-recover=undefined",
+           f"-I{CSRC}", f"-I{os.path.join(ROOT, 'include')}",
+           os.path.join(ROOT, "tests", "host_order_check.cpp"), "-o", str(exe)]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stderr[-3000:]
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300,
+                       env=dict(os.environ, ASAN_OPTIONS="detect_leaks=0", UBSAN_OPTIONS="halt_on_error=1"))
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "sort index algebra ok" in r.stdout
